@@ -1,0 +1,153 @@
+/*
+ * hp.h -- C ABI of the MI355X library for one step of the one-way
+ * (vector) Helmholtz propagator in its exponential-operator form.
+ *
+ * Method (Keefe, McDaniel, Cubillos, Zilberter, Madden, "A vector Helmholtz
+ * electromagnetic wave propagator for inhomogeneous media"):
+ *   Sec. 2, eq. expop_prop:   w(z+dz) = exp(iK(-I + sqrt(I + Zbar))) w(z),
+ *                             K = k0 n0 dz, Zbar the operator of eq. Z_bar_eq;
+ *   Sec. 2, eqs. rational approximation / pf_expan_eq:
+ *                             exp(iK sqrt(1+z)) ~ r_inf + sum_k a_k/(z - b_k);
+ *   Sec. 2, eqs. Wk_define / approx_prop / W_k_def:
+ *                             w(z+dz) = e^{-iK} (r_inf w + sum_k a_k x_k),
+ *                             (Zbar - b_k I) x_k = w, one sparse solve per pole;
+ *   Sec. 4.2:                 each solve by right-preconditioned GMRES whose
+ *                             preconditioner is the free-space operator
+ *                             Zbar_fs - b_k I (eq. Z_bar_fs_def), solved as the
+ *                             Sylvester equation of eq. fs_sylvester;
+ *   Sec. 4.1:                 13-point fourth-order differences.
+ *
+ * Grid: an nx-by-ny array per field component, row-major [ny][nx] (x fastest).
+ * Node 0 and the virtual node n of each axis are homogeneous-Dirichlet nodes
+ * (odd reflection closes the stencils there, so the free-space preconditioner
+ * is diagonalised exactly by DST-I); unknowns are nodes 1..n-1.  Row 0 and
+ * column 0 of every input field are ignored; they are written as 0 on output.
+ * Fields are complex128, interleaved (re, im), component-major
+ * [ncomp][ny][nx]; ncomp = 1 (scalar) or 2 (E_x, E_y coupled by the
+ * cross-polarisation terms of eq. Z_bar_eq).
+ *
+ * Edge layer: for distance d = min(i, n-i, j, n-j) <= edge_width the medium
+ * terms of Zbar are zero (Sec. 4.1 zeroes them in its boundary layers).  In
+ * place of the paper's PML the layer is a lossy medium n^2 = n0^2 + i eta(d),
+ * eta(d) = edge_eta ((W+1-d)/W)^2, whose loss over a step multiplies the
+ * stepped field by exp(-k0 dz eta(d) / (2 n0)).
+ *
+ * Memory: every field pointer is a DEVICE pointer (hipMalloc'd or a torch
+ * tensor's storage).  The caller owns inputs, outputs and (when given) the
+ * workspace; the plan copies the pole/residue table and stencils at create.
+ * All calls are asynchronous on the plan's stream except where stated; the
+ * GMRES driver synchronises the stream once per Arnoldi step to read the
+ * convergence flags.  A plan is not re-entrant; different plans may run on
+ * different streams.  No call falls back to the CPU.
+ *
+ * Errors: a negative return means nothing valid was written; a positive
+ * return is a warning with the output written.  hp_last_error() gives a
+ * message for the last failing call on the plan (or the thread, for NULL).
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_plan_s* hp_plan;
+typedef struct { double re, im; } hp_c128;
+
+enum {
+  HP_OK = 0,
+  HP_WARN_NOCONV = 1,      /* some solve missed tol after max_cycles restarts */
+  HP_WARN_UNSTABLE = 2,    /* max |e^{-iK} r(mu_p + mu_q)| > 1 + 1e-6 on the free-space spectrum */
+  HP_EINVAL = -1,
+  HP_ENOMEM = -2,
+  HP_EHIP = -3,
+  HP_ESTATE = -4
+};
+
+enum { HP_FP64 = 0, HP_MIXED = 1 };
+
+typedef struct {
+  int nx, ny;                 /* cells per axis = array dims; 64 <= n <= 2048, power of two */
+  double dx, dy;              /* grid spacing */
+  double k0, n0, dz;          /* vacuum wavenumber, reference index, step; K = k0 n0 dz */
+  int ncomp;                  /* 1 scalar, 2 vector */
+  int npoles;                 /* N of the (N,N) rational approximation, 1..60 */
+  const hp_c128* poles;       /* host [npoles]: b_k */
+  const hp_c128* residues;    /* host [npoles]: a_k */
+  hp_c128 r_inf;              /* alpha_NN / beta_NN */
+  const double* d2;           /* host [7]: c0..c6 of the 13-point second derivative */
+  const double* d1;           /* host [6]: d1..d6 of the 13-point first derivative */
+  int edge_width;             /* W >= 6 cells; n >= 2W + 14 */
+  double edge_eta;            /* peak Im(n^2) of the edge layer (>= 0) */
+  double tol;                 /* relative residual ||w - A x|| / ||w|| per solve */
+  int restart;                /* GMRES(m) restart length, 1..64 */
+  int max_cycles;             /* restarts before HP_WARN_NOCONV, >= 1 */
+  int precision;              /* HP_FP64 (complex128 everywhere) or HP_MIXED */
+} hp_plan_desc;
+
+/* Device bytes a plan needs; 0 if desc is invalid. */
+size_t hp_workspace_bytes(const hp_plan_desc* desc);
+
+/* Create a plan.  stream: a hipStream_t (NULL = default stream).  workspace:
+ * NULL (the plan allocates hp_workspace_bytes with hipMalloc and frees it at
+ * destroy) or a caller-owned device buffer of at least that size, 256-byte
+ * aligned.  Validates the descriptor (HP_EINVAL: sizes, W, a pole within
+ * 1e-14 of a free-space eigenvalue mu_p + mu_q), uploads tables, and returns
+ * HP_WARN_UNSTABLE (plan still valid) when the rational function exceeds 1 in
+ * modulus on the free-space spectrum. */
+int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_plan* out);
+
+/* Coefficient preparation (Sec. 2 eq. Z_bar_eq, Sec. 4.1): from the real
+ * refractive-index field n2 (device, [ny][nx] doubles) compute the medium
+ * terms of Zbar: V = (n^2 - n0^2)/n0^2 and, for ncomp = 2, the derivatives of
+ * psi = ln n^2.  Kept in the plan until the next call. */
+int hp_set_medium(hp_plan plan, const double* n2);
+
+/* One step (Sec. 2 eq. approx_prop).  E_in, E_out: device [ncomp][ny][nx]
+ * complex128; E_out may equal E_in.  n2: device [ny][nx] or NULL to keep the
+ * medium of the last call. */
+int hp_step(hp_plan plan, const void* E_in, const double* n2, void* E_out);
+
+/* nsteps steps.  n2 may be NULL (keep), or n2 + s * n2_step_stride is the
+ * medium of step s (stride 0: one z-independent medium). */
+int hp_propagate(hp_plan plan, const void* E_in, const double* n2, long n2_step_stride,
+                 int nsteps, void* E_out);
+
+/* Statistics of the last step (synchronous): GMRES iterations and final
+ * relative residual estimate per pole (either pointer may be NULL). */
+int hp_get_stats(hp_plan plan, int* iters_per_pole, double* final_relres);
+
+/* Fixed-iteration mode (reproducibility / replay): iters[k] > 0 forces a
+ * single GMRES cycle of exactly iters[k] Arnoldi steps for pole k in every
+ * later step; NULL restores tolerance-driven iterations. */
+int hp_set_fixed_iters(hp_plan plan, const int* iters);
+
+/* Operator-level entry points on device fields [ncomp][ny][nx] complex128,
+ * FP64 (used for checking; they share the step's kernels):
+ *   y = (Zbar - b_k I) x         (Sec. 2 eq. W_k_def; the explicit stencils)
+ *   y = (Zbar_fs - b_k I)^{-1} x (Sec. 4.2.2 eq. fs_sylvester by DST-I)
+ * pole < 0 means the shift b = 0. */
+int hp_apply_operator(hp_plan plan, int pole, const void* x, void* y);
+int hp_apply_preconditioner(hp_plan plan, int pole, const void* x, void* y);
+
+/* Kernel timing (diagnostics).  While enabled, each launch of the step's
+ * kernels is bracketed by HIP events on the plan's stream and its algorithmic
+ * HBM bytes (the bytes the operation must move: fields read and written once)
+ * are counted.  hp_profile_read synchronises and returns, per kernel class
+ * (HP_K_*), launches, summed event milliseconds and summed algorithmic bytes
+ * since the last enable; arrays have HP_K_COUNT entries (NULL to skip). */
+enum { HP_K_ROW_FWD = 0, HP_K_COL = 1, HP_K_ROW_APPLY = 2, HP_K_UPDATE = 3, HP_K_SMALL = 4,
+       HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_COUNT = 7 };
+int hp_profile(hp_plan plan, int enable);
+int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
+
+const char* hp_last_error(hp_plan plan);
+void hp_plan_destroy(hp_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HP_H */

@@ -1,0 +1,121 @@
+// In-LDS Stockham FFT and the DST-I built on it.
+//
+// The free-space preconditioner (Sec. 4.2.2, eq. fs_sylvester) is
+// diagonalised by the orthonormal DST-I of length n-1 on each axis:
+//   X_p = sqrt(2/n) sum_{j=1}^{n-1} x_j sin(pi p j / n).
+// With the odd extension y (y_j = x_j, y_{2n-j} = -x_j, y_0 = y_n = 0) of
+// period L = 2n, the forward DFT gives Y_p = -2i sum x_j sin(pi p j/n), so
+//   X_p = i Y_p / sqrt(2n).
+// S is symmetric and S S = I, so the same routine is its own inverse.
+//
+// FFT: self-sorting Stockham radix-8/4/2 with the data in LDS, one group of
+// NT = L/8 threads per transform, each thread holding R values of a stage in
+// registers.  Twiddles come from a table tw[m] = exp(-2 pi i m / L).
+#pragma once
+#include "cplx.hpp"
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_mi(a1 - a3);
+  a0 = t0 + t2;
+  a1 = t1 + t3;
+  a2 = t0 - t2;
+  a3 = t1 - t3;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 2) {
+    cx<T> t = v[0];
+    v[0] = t + v[1];
+    v[1] = t - v[1];
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else {
+    static_assert(R == 8, "radix");
+    cx<T> a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6];
+    cx<T> b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7];
+    dft4(a0, a1, a2, a3);
+    dft4(b0, b1, b2, b3);
+    const T h = (T)0.707106781186547524400844362104849039;
+    cx<T> t1 = mk<T>(h * (b1.re + b1.im), h * (b1.im - b1.re));   // b1 * e^{-i pi/4}
+    cx<T> t2 = mul_mi(b2);                                        // b2 * e^{-i pi/2}
+    cx<T> t3 = mk<T>(h * (b3.im - b3.re), -h * (b3.re + b3.im));  // b3 * e^{-3i pi/4}
+    v[0] = a0 + b0;
+    v[4] = a0 - b0;
+    v[1] = a1 + t1;
+    v[5] = a1 - t1;
+    v[2] = a2 + t2;
+    v[6] = a2 - t2;
+    v[3] = a3 + t3;
+    v[7] = a3 - t3;
+  }
+}
+
+// One Stockham stage: butterflies j = t, t+NT, ...; input stride L/R,
+// output (j / NS) * NS * R + (j % NS) + r * NS.
+template <typename T, int L, int R, int NS, int NT>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
+  constexpr int NB = L / R;
+  constexpr int PER = NB / NT;
+  static_assert(PER * NT == NB, "threads per transform must divide L/R");
+  cx<T> v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = t + q * NT;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+    if constexpr (NS > 1) {
+      const int k = j % NS;
+      constexpr int STEP = L / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q][r] = v[q][r] * tw[r * k * STEP];
+    }
+    dft<T, R>(v[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = t + q * NT;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[base + r * NS] = v[q][r];
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int NS, int NT>
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
+  if constexpr (NS < L) {
+    constexpr int REM = L / NS;
+    constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+    fft_stage<T, L, R, NS, NT>(buf, tw, t);
+    fft_stages<T, L, NS * R, NT>(buf, tw, t);
+  }
+}
+
+// Forward DFT of length L of buf (in place, natural order).  Every thread of
+// the workgroup must call it (it contains __syncthreads); t in [0, L/8).
+template <typename T, int L>
+__device__ __forceinline__ void fft(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
+  fft_stages<T, L, 1, L / 8>(buf, tw, t);
+}
+
+// Store x_m (m = 1..n-1) and its odd image into the length-2n buffer; m = 0
+// writes the two Dirichlet zeros.  x is the value for index m.
+template <typename T>
+__device__ __forceinline__ void odd_store(cx<T>* buf, int n, int m, cx<T> x) {
+  if (m == 0) {
+    buf[0] = mk<T>(0, 0);
+    buf[n] = mk<T>(0, 0);
+  } else {
+    buf[m] = x;
+    buf[2 * n - m] = -x;
+  }
+}
+
+// DST-I coefficient p (1..n-1) from the FFT of the odd extension.
+template <typename T>
+__device__ __forceinline__ cx<T> dst_out(const cx<T>* buf, int p, T scale) {
+  return scale * mul_i(buf[p]);
+}

@@ -1,0 +1,753 @@
+// Host runtime behind include/hp.h: plan, workspace, the lockstep GMRES
+// driver over all poles of a step, and the C ABI.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hp.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr double kInnerRtolMixed = 1e-5;  // cycle tolerance of the complex64 inner solves
+
+struct Ws {
+  char* base = nullptr;
+  size_t off = 0;
+  bool dry = true;
+  template <typename X>
+  X* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    X* p = dry ? nullptr : reinterpret_cast<X*>(base + off);
+    off += count * sizeof(X);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct hp_plan_s {
+  hp_plan_desc d{};
+  std::vector<hp_c128> poles, residues;
+  double c2[7]{}, d1c[6]{};
+  hipStream_t stream = nullptr;
+  bool own_ws = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Geo geo{};
+  StencilCoef sc{};
+  bool mixed = false;
+  int nrowblk = 0, napplyblk = 0, nupdblk = 0, nopblk = 0;
+  size_t fieldn = 0;  // ncomp * nx * ny
+  // device
+  double *mu_x = nullptr, *mu_y = nullptr;
+  void *tw_x = nullptr, *tw_y = nullptr;
+  c128* tw64_x = nullptr;
+  double *coef = nullptr, *coef_scratch = nullptr;
+  void *U = nullptr, *Z = nullptr, *P = nullptr, *DZ = nullptr, *bR = nullptr, *tmpR = nullptr;
+  c128 *X = nullptr, *tmp1 = nullptr, *tmp2 = nullptr;
+  PoleState* st = nullptr;
+  PoleState* st_scratch = nullptr;
+  void** uptr = nullptr;
+  void** uptr_scratch = nullptr;
+  int* active_d = nullptr;
+  int* flags_d = nullptr;
+  double* est_d = nullptr;
+  double2* part_dots = nullptr;
+  double* part_norm = nullptr;
+  double* part_misc = nullptr;
+  // host
+  int* flags_h = nullptr;  // pinned
+  double* est_h = nullptr;
+  int* active_h = nullptr;
+  double* misc_h = nullptr;
+  std::vector<void*> uptr_h;
+  std::vector<int> fixed;
+  std::vector<double> relres;
+  std::vector<int> iters;
+  bool medium_set = false;
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_cls;
+  std::vector<double> ev_bytes;
+  long prof_n[HP_K_COUNT]{};
+  double prof_ms[HP_K_COUNT]{}, prof_b[HP_K_COUNT]{};
+  std::vector<int> m_h;  // Arnoldi columns per pole (host mirror)
+  std::vector<double> incons;  // eps kappa(M_k) per pole
+  c128 phase{}, rinf_phase{};  // e^{-iK}, e^{-iK} r_inf
+  double loss_coef = 0.0;      // k0 dz / (2 n0)
+  std::string err;
+};
+
+namespace {
+
+int fail(hp_plan p, int code, const std::string& msg) {
+  if (p)
+    p->err = msg;
+  else
+    g_thread_error = msg;
+  return code;
+}
+
+int hip_fail(hp_plan p, hipError_t e, const char* where) {
+  return fail(p, HP_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HPCHK(expr)                                      \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(p, e_, #expr); \
+  } while (0)
+
+// Bracket a launch with events when timing is on.
+struct Prof {
+  hp_plan p;
+  int cls;
+  double bytes;
+  Prof(hp_plan p_, int c, double b) : p(p_), cls(c), bytes(b) {
+    if (!p->prof) return;
+    if (p->ev_used + 2 > p->ev_pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p->ev_pool.push_back(e);
+      }
+    }
+    (void)hipEventRecord(p->ev_pool[p->ev_used], p->stream);
+  }
+  ~Prof() {
+    if (!p->prof || p->ev_used + 2 > p->ev_pool.size()) return;
+    (void)hipEventRecord(p->ev_pool[p->ev_used + 1], p->stream);
+    p->ev_used += 2;
+    p->ev_cls.push_back(cls);
+    p->ev_bytes.push_back(bytes);
+  }
+};
+
+bool pow2_size(int n) { return n >= 64 && n <= 2048 && (n & (n - 1)) == 0; }
+
+std::string validate(const hp_plan_desc* d) {
+  if (!d) return "desc is NULL";
+  if (!pow2_size(d->nx) || !pow2_size(d->ny)) return "nx, ny must be powers of two in [64, 2048]";
+  if (d->ncomp != 1 && d->ncomp != 2) return "ncomp must be 1 or 2";
+  if (d->precision != HP_FP64 && d->precision != HP_MIXED) return "precision must be HP_FP64 or HP_MIXED";
+  if (d->ncomp == 2 && d->precision == HP_FP64 && d->nx > 1024) return "FP64 vector plans support n <= 1024";
+  if (!(d->dx > 0) || !(d->dy > 0) || !(d->k0 > 0) || !(d->n0 > 0) || !(d->dz > 0)) return "dx, dy, k0, n0, dz must be > 0";
+  if (d->npoles < 1 || d->npoles > HP_MAXPOLES - 4) return "npoles must be in [1, 60]";
+  if (!d->poles || !d->residues) return "poles/residues are NULL";
+  if (!d->d2 || !d->d1) return "stencil coefficients are NULL";
+  if (d->edge_width < 6) return "edge_width must be >= 6";
+  if (d->nx < 2 * d->edge_width + 14 || d->ny < 2 * d->edge_width + 14) return "grid too small for the edge layer";
+  if (!(d->edge_eta >= 0)) return "edge_eta must be >= 0";
+  if (!(d->tol > 0)) return "tol must be > 0";
+  if (d->restart < 1 || d->restart > HP_MAXM) return "restart must be in [1, 64]";
+  if (d->max_cycles < 1) return "max_cycles must be >= 1";
+  return "";
+}
+
+// Carve (or size) the workspace.  Layout is identical in both passes.
+void layout(hp_plan p, Ws& w) {
+  const hp_plan_desc& d = p->d;
+  const size_t es = p->mixed ? sizeof(c64) : sizeof(c128);
+  const size_t fn = p->fieldn;
+  const int K = d.npoles, M = d.restart;
+  p->mu_x = w.take<double>(d.nx);
+  p->mu_y = w.take<double>(d.ny);
+  p->tw_x = w.take<char>(2 * d.nx * es);
+  p->tw_y = w.take<char>(2 * d.ny * es);
+  p->tw64_x = w.take<c128>(2 * d.nx);
+  p->coef = w.take<double>((d.ncomp == 2 ? 6 : 1) * p->geo.fsz);
+  p->coef_scratch = w.take<double>((d.ncomp == 2 ? 2 : 1) * p->geo.fsz);
+  p->U = w.take<char>((size_t)K * (M + 1) * fn * es);
+  p->Z = w.take<char>((size_t)K * M * fn * es);
+  p->P = w.take<char>((size_t)K * fn * es);
+  p->DZ = w.take<char>((d.ncomp == 2 ? (size_t)K : 1) * fn * es);
+  p->bR = w.take<char>(fn * es);
+  p->tmpR = w.take<char>(fn * es);
+  p->X = w.take<c128>((size_t)K * fn);
+  p->tmp1 = w.take<c128>(fn);
+  p->tmp2 = w.take<c128>(fn);
+  p->st = w.take<PoleState>(K);
+  p->st_scratch = w.take<PoleState>(1);
+  p->uptr = w.take<void*>((size_t)K * (HP_MAXM + 1));
+  p->uptr_scratch = w.take<void*>(HP_MAXM + 1);
+  p->active_d = w.take<int>(HP_MAXPOLES);
+  p->flags_d = w.take<int>(HP_MAXPOLES);
+  p->est_d = w.take<double>(HP_MAXPOLES);
+  p->part_dots = w.take<double2>((size_t)K * (HP_MAXM + 1) * 2 * p->napplyblk);
+  p->part_norm = w.take<double>((size_t)K * p->nupdblk);
+  p->part_misc = w.take<double>(std::max((size_t)p->nrowblk * d.ncomp, (size_t)p->nopblk) + 64);
+}
+
+void derive(hp_plan p) {
+  const hp_plan_desc& d = p->d;
+  p->mixed = d.precision == HP_MIXED;
+  p->geo.nx = d.nx;
+  p->geo.ny = d.ny;
+  p->geo.ncomp = d.ncomp;
+  p->geo.fsz = (size_t)d.nx * d.ny;
+  p->fieldn = p->geo.fsz * d.ncomp;
+  const int rpw = 256 / (2 * d.nx / 8) > 0 ? 256 / (2 * d.nx / 8) : 1;
+  p->nrowblk = (d.ny - 1 + rpw - 1) / rpw;
+  p->napplyblk = p->mixed ? row_apply_blocks<float>(p->geo) : row_apply_blocks<double>(p->geo);
+  p->nupdblk = update_blocks(p->fieldn);
+  p->nopblk = op_blocks(p->geo);
+  const double s = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
+  for (int m = 0; m < 7; ++m) {
+    p->sc.c2x[m] = s * d.d2[m] / (d.dx * d.dx);
+    p->sc.c2y[m] = s * d.d2[m] / (d.dy * d.dy);
+  }
+  for (int m = 0; m < 6; ++m) {
+    p->sc.d1x[m] = d.d1[m] / d.dx;
+    p->sc.d1y[m] = d.d1[m] / d.dy;
+  }
+}
+
+std::vector<double> mu_table(int n, double h, const double* c, double s) {
+  std::vector<double> mu(n, 0.0);
+  for (int q = 1; q < n; ++q) {
+    double sym = c[0];
+    for (int m = 1; m < 7; ++m) sym += 2.0 * c[m] * cos(m * M_PI * q / n);
+    mu[q] = s * sym / (h * h);
+  }
+  return mu;
+}
+
+template <typename T>
+std::vector<cx<T>> twiddles(int L) {
+  std::vector<cx<T>> t(L);
+  for (int m = 0; m < L; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)L;
+    t[m] = mk<T>((T)cos(a), (T)sin(a));
+  }
+  return t;
+}
+
+std::complex<double> rat(hp_plan p, double z) {
+  std::complex<double> r(p->d.r_inf.re, p->d.r_inf.im);
+  for (int k = 0; k < p->d.npoles; ++k) {
+    std::complex<double> a(p->residues[k].re, p->residues[k].im), b(p->poles[k].re, p->poles[k].im);
+    r += a / (z - b);
+  }
+  return r;
+}
+
+template <typename T>
+int upload_tables(hp_plan p) {
+  const hp_plan_desc& d = p->d;
+  const double s = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
+  auto mx = mu_table(d.nx, d.dx, p->c2, s), my = mu_table(d.ny, d.dy, p->c2, s);
+  HPCHK(hipMemcpy(p->mu_x, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->mu_y, my.data(), my.size() * sizeof(double), hipMemcpyHostToDevice));
+  auto tx = twiddles<T>(2 * d.nx), ty = twiddles<T>(2 * d.ny);
+  auto t64 = twiddles<double>(2 * d.nx);
+  HPCHK(hipMemcpy(p->tw_x, tx.data(), tx.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->tw_y, ty.data(), ty.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->tw64_x, t64.data(), t64.size() * sizeof(c128), hipMemcpyHostToDevice));
+  return HP_OK;
+}
+
+int upload_state(hp_plan p) {
+  std::vector<PoleState> h(p->d.npoles);
+  for (int k = 0; k < p->d.npoles; ++k) {
+    memset(&h[k], 0, sizeof(PoleState));
+    h[k].bk = mk(p->poles[k].re, p->poles[k].im);
+    h[k].ak = mk(p->residues[k].re, p->residues[k].im);
+    h[k].fixed = p->fixed.empty() ? 0 : p->fixed[k];
+    h[k].incons = p->incons[k];
+  }
+  HPCHK(hipMemcpyAsync(p->st, h.data(), h.size() * sizeof(PoleState), hipMemcpyHostToDevice, p->stream));
+  return HP_OK;
+}
+
+template <typename T>
+cx<T>* fld(void* base, size_t idx, size_t fieldn) {
+  return reinterpret_cast<cx<T>*>(base) + idx * fieldn;
+}
+
+int upload_uptr(hp_plan p) {
+  hipError_t e = hipMemcpyAsync(p->uptr, p->uptr_h.data(), p->uptr_h.size() * sizeof(void*), hipMemcpyHostToDevice,
+                                p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "upload uptr");
+  return HP_OK;
+}
+
+// End of a cycle for pole k: fold the cycle into X_k and compute the true
+// residual r = w - A_k x_k in FP64 (x_k = S_x X_k).  Leaves r in tmp2 and
+// returns ||r|| in *res.
+template <typename T>
+int true_residual(hp_plan p, int k, const c128* w, double* res) {
+  const size_t fn = p->fieldn;
+  const double U1 = (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp;
+  {
+  Prof pr(p, HP_K_RESIDUAL, U1 * (sizeof(cx<T>) * (double)p->m_h[k] + 16.0 * 7));
+  launch_accum<T>(p->X + (size_t)k * fn, fld<T>(p->Z, (size_t)k * p->d.restart, fn), fn, p->st, k, p->geo,
+                  p->stream);
+  // X_k now holds the whole solution; the cycle's own terms are folded in
+  static const int one = 1, zero = 0;
+  HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HPCHK(hipMemcpyAsync(&p->st[k].m, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, p->stream);
+  launch_apply_op(p->tmp1, w, p->tmp2, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc, p->geo, p->part_misc,
+                  p->stream);
+  }
+  HPCHK(hipMemcpyAsync(p->misc_h, p->part_misc, p->nopblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipStreamSynchronize(p->stream));
+  double s = 0.0;
+  for (int b = 0; b < p->nopblk; ++b) s += p->misc_h[b];
+  *res = sqrt(s);
+  return HP_OK;
+}
+
+// Start a new cycle for pole k from the residual in tmp2.
+template <typename T>
+int restart_pole(hp_plan p, int k) {
+  const size_t fn = p->fieldn;
+  cx<T>* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
+  {
+    Prof pr(p, HP_K_ROW_FWD, (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
+    launch_row_fwd<T>(p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, p->stream);
+  }
+  if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)u0) {
+    p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
+    HPCHK(hipMemcpyAsync(p->uptr + (size_t)k * (HP_MAXM + 1), &p->uptr_h[(size_t)k * (HP_MAXM + 1)], sizeof(void*),
+                         hipMemcpyHostToDevice, p->stream));
+  }
+  p->active_h[HP_MAXPOLES - 1] = k;
+  HPCHK(hipMemcpyAsync(p->active_d + HP_MAXPOLES - 1, &p->active_h[HP_MAXPOLES - 1], sizeof(int),
+                       hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, p->active_d + HP_MAXPOLES - 1, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol,
+                    p->mixed ? kInnerRtolMixed : 0.0, p->stream);
+  return HP_OK;
+}
+
+template <typename T>
+int run_step(hp_plan p, const c128* w, c128* out) {
+  const hp_plan_desc& d = p->d;
+  const size_t fn = p->fieldn;
+  const int K = d.npoles, M = d.restart;
+  const cx<T>* twx = reinterpret_cast<const cx<T>*>(p->tw_x);
+  const cx<T>* twy = reinterpret_cast<const cx<T>*>(p->tw_y);
+  cx<T>* bR = reinterpret_cast<cx<T>*>(p->bR);
+  const double es = (double)sizeof(cx<T>);
+  const double U1 = (double)(d.nx - 1) * (d.ny - 1) * d.ncomp;  // unknowns of one field
+  const double planes = d.ncomp == 2 ? 6.0 : 1.0;
+  p->m_h.assign(K, 0);
+  // shared first Krylov vector: S_x w (every pole's right-hand side is w)
+  {
+    Prof pr(p, HP_K_ROW_FWD, U1 * (16.0 + es));
+    launch_row_fwd<T>(w, bR, p->part_misc, twx, p->geo, p->stream);
+  }
+  bool changed = false;
+  for (int k = 0; k < K; ++k) {
+    if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)bR) {
+      p->uptr_h[(size_t)k * (HP_MAXM + 1)] = bR;
+      changed = true;
+    }
+    p->active_h[k] = k;
+  }
+  if (changed) {
+    int rc = upload_uptr(p);
+    if (rc) return rc;
+  }
+  HPCHK(hipMemcpyAsync(p->active_d, p->active_h, K * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, p->active_d, K, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
+                    p->mixed ? kInnerRtolMixed : 0.0, p->stream);
+  std::vector<int> active(K);
+  for (int k = 0; k < K; ++k) active[k] = k;
+  std::vector<int> cycles(K, 0);
+  p->relres.assign(K, -1.0);
+  double beta0 = -1.0;
+  bool first = true;
+  bool noconv = false;
+  const size_t zsp = (size_t)M * fn, zsi = fn, psp = fn, dzsp = (d.ncomp == 2) ? fn : 0;
+  cx<T>* Zb = reinterpret_cast<cx<T>*>(p->Z);
+  cx<T>* Pb = reinterpret_cast<cx<T>*>(p->P);
+  cx<T>* DZb = reinterpret_cast<cx<T>*>(p->DZ);
+  const cx<T>* const* up = reinterpret_cast<const cx<T>* const*>(p->uptr);
+  while (!active.empty()) {
+    const int na = (int)active.size();
+    for (int a = 0; a < na; ++a) p->active_h[a] = active[a];
+    HPCHK(hipMemcpyAsync(p->active_d, p->active_h, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    double sum_m = 0.0;
+    for (int k : active) sum_m += p->m_h[k];
+    {
+      const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
+      Prof pr(p, HP_K_COL, U1 * es * ((first ? 1.0 : na) + outs));
+      launch_col<T>(up, Zb, zsp, zsi, DZb, dzsp, p->st, p->active_d, na, first, p->mu_x, p->mu_y, twy, p->geo,
+                    p->sc, p->stream);
+    }
+    first = false;
+    {
+      const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
+      Prof pr(p, HP_K_ROW_APPLY, U1 * es * per_pole + (U1 / d.ncomp) * 8.0 * planes);
+      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, p->coef, p->st, p->active_d, na, p->part_dots, twx,
+                          p->geo, p->sc, p->stream);
+    }
+    {
+      Prof pr(p, HP_K_SMALL, 0.0);
+      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, p->active_d, na, M, p->stream);
+    }
+    {
+      Prof pr(p, HP_K_UPDATE, U1 * es * (sum_m + 3.0 * na));
+      launch_update<T>(Pb, psp, reinterpret_cast<cx<T>* const*>(p->uptr), p->st, p->active_d, na, p->part_norm,
+                       p->nupdblk, p->geo, p->stream);
+    }
+    {
+      Prof pr(p, HP_K_SMALL, 0.0);
+      launch_arnoldi(p->st, p->active_d, na, p->part_norm, p->nupdblk, M, p->flags_d, p->est_d, p->stream);
+    }
+    for (int k : active) p->m_h[k] += 1;
+    HPCHK(hipMemcpyAsync(p->flags_h, p->flags_d, K * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    HPCHK(hipStreamSynchronize(p->stream));
+    std::vector<int> next;
+    for (int k : active) {
+      const int f = p->flags_h[k];
+      if (f == 0) {
+        next.push_back(k);
+        continue;
+      }
+      const bool fixed = !p->fixed.empty() && p->fixed[k] > 0;
+      if (fixed || (f == 1 && !p->mixed)) {  // converged on the FP64 estimate (flag 3: verify)
+        p->relres[k] = -1.0;
+        continue;
+      }
+      // verify with the true residual (mixed mode) or restart (cycle ended)
+      if (beta0 < 0) {
+        HPCHK(hipMemcpy(&beta0, &p->st[0].beta0, sizeof(double), hipMemcpyDeviceToHost));
+      }
+      double res = 0.0;
+      int rc = true_residual<T>(p, k, w, &res);
+      if (rc) return rc;
+      const double rel = beta0 > 0 ? res / beta0 : 0.0;
+      p->relres[k] = rel;
+      if (rel <= d.tol) continue;
+      if (++cycles[k] >= d.max_cycles) {
+        noconv = true;
+        continue;
+      }
+      rc = restart_pole<T>(p, k);
+      if (rc) return rc;
+      p->m_h[k] = 0;
+      next.push_back(k);
+    }
+    active.swap(next);
+  }
+  {
+    double terms = 0.0;
+    for (int k = 0; k < K; ++k) terms += p->m_h[k];
+    Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
+    launch_final<T>(w, out, Zb, zsp, zsi, p->X, fn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta,
+                    d.edge_width, p->tw64_x, p->geo, p->stream);
+  }
+  HPCHK(hipGetLastError());
+  return noconv ? HP_WARN_NOCONV : HP_OK;
+}
+
+template <typename T>
+int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
+  PoleState h;
+  memset(&h, 0, sizeof(h));
+  h.bk = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
+  h.sigma[0] = 1.0;
+  void* tbl[HP_MAXM + 1] = {nullptr};
+  tbl[0] = p->tmpR;
+  int zero = 0;
+  HPCHK(hipMemcpyAsync(p->st_scratch, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
+  HPCHK(hipMemcpyAsync(p->uptr_scratch, tbl, sizeof(tbl), hipMemcpyHostToDevice, p->stream));
+  HPCHK(hipMemcpyAsync(p->active_d + HP_MAXPOLES - 2, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_row_fwd<T>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x),
+                    p->geo, p->stream);
+  // the first basis slot of pole 0 in Z serves as output; the DZ slot as scratch
+  cx<T>* zout = reinterpret_cast<cx<T>*>(p->P);
+  launch_col<T>(reinterpret_cast<const cx<T>* const*>(p->uptr_scratch), zout, 0, 0, reinterpret_cast<cx<T>*>(p->DZ), 0,
+                p->st_scratch, p->active_d + HP_MAXPOLES - 2, 1, false, p->mu_x, p->mu_y,
+                reinterpret_cast<const cx<T>*>(p->tw_y), p->geo, p->sc, p->stream);
+  launch_row_inv<T>(zout, y, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, p->stream);
+  HPCHK(hipStreamSynchronize(p->stream));
+  return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hp_workspace_bytes(const hp_plan_desc* desc) {
+  if (!validate(desc).empty()) return 0;
+  hp_plan_s tmp;
+  tmp.d = *desc;
+  derive(&tmp);
+  Ws w;
+  layout(&tmp, w);
+  return w.off + 256;
+}
+
+int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_plan* out) {
+  if (!out) return fail(nullptr, HP_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string v = validate(desc);
+  if (!v.empty()) return fail(nullptr, HP_EINVAL, v);
+  hp_plan p = new (std::nothrow) hp_plan_s();
+  if (!p) return fail(nullptr, HP_ENOMEM, "host allocation failed");
+  p->d = *desc;
+  p->poles.assign(desc->poles, desc->poles + desc->npoles);
+  p->residues.assign(desc->residues, desc->residues + desc->npoles);
+  memcpy(p->c2, desc->d2, sizeof(p->c2));
+  memcpy(p->d1c, desc->d1, sizeof(p->d1c));
+  p->d.poles = p->poles.data();
+  p->d.residues = p->residues.data();
+  p->d.d2 = p->c2;
+  p->d.d1 = p->d1c;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  derive(p);
+  const double K = desc->k0 * desc->n0 * desc->dz;
+  const std::complex<double> ph = std::exp(std::complex<double>(0.0, -K));
+  const std::complex<double> rp = ph * std::complex<double>(desc->r_inf.re, desc->r_inf.im);
+  p->phase = mk(ph.real(), ph.imag());
+  p->rinf_phase = mk(rp.real(), rp.imag());
+  p->loss_coef = desc->k0 * desc->dz / (2.0 * desc->n0);
+  // free-space spectrum checks
+  const double s = 1.0 / ((desc->k0 * desc->n0) * (desc->k0 * desc->n0));
+  auto mx = mu_table(desc->nx, desc->dx, p->c2, s), my = mu_table(desc->ny, desc->dy, p->c2, s);
+  const double lo = *std::min_element(mx.begin() + 1, mx.end()) + *std::min_element(my.begin() + 1, my.end());
+  const double hi = *std::max_element(mx.begin() + 1, mx.end()) + *std::max_element(my.begin() + 1, my.end());
+  for (int k = 0; k < desc->npoles; ++k) {
+    if (fabs(p->poles[k].im) < 1e-14 && p->poles[k].re >= lo - 1e-14 && p->poles[k].re <= hi + 1e-14) {
+      for (int i = 1; i < desc->ny; ++i)
+        for (int j = 1; j < desc->nx; ++j)
+          if (fabs(my[i] + mx[j] - p->poles[k].re) < 1e-14) {
+            delete p;
+            return fail(nullptr, HP_EINVAL, "a pole lies on the free-space spectrum");
+          }
+    }
+  }
+  // kappa(M_k) <= max |lambda - b_k| / dist(b_k, [lo, hi]) over the free-space spectrum
+  const double eps = desc->precision == HP_MIXED ? 6e-8 : 1.1e-16;
+  p->incons.assign(desc->npoles, 0.0);
+  for (int k = 0; k < desc->npoles; ++k) {
+    const std::complex<double> b(p->poles[k].re, p->poles[k].im);
+    const double dre = b.real() < lo ? lo - b.real() : (b.real() > hi ? b.real() - hi : 0.0);
+    const double dist = std::sqrt(dre * dre + b.imag() * b.imag());
+    const double far = std::max(std::abs(lo - b), std::abs(hi - b));
+    p->incons[k] = dist > 0 ? eps * far / dist : 1.0;
+  }
+  double rmax = 0.0;
+  for (int i = 0; i <= 100000; ++i) {
+    const double z = lo + (hi - lo) * i / 100000.0;
+    rmax = std::max(rmax, std::abs(rat(p, z)));
+  }
+  // workspace
+  Ws w;
+  layout(p, w);
+  p->ws_bytes = w.off + 256;
+  if (workspace) {
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) {
+      delete p;
+      return fail(nullptr, HP_EINVAL, "workspace must be 256-byte aligned");
+    }
+    p->ws = reinterpret_cast<char*>(workspace);
+  } else {
+    hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(nullptr, HP_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+    }
+    p->own_ws = true;
+  }
+  w = Ws();
+  w.base = p->ws;
+  w.dry = false;
+  layout(p, w);
+  if (hipHostMalloc(&p->flags_h, HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&p->est_h, HP_MAXPOLES * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&p->active_h, HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&p->misc_h, (std::max(p->nopblk, p->nrowblk * 2) + 64) * sizeof(double)) != hipSuccess) {
+    hp_plan_destroy(p);
+    return fail(nullptr, HP_ENOMEM, "pinned host allocation failed");
+  }
+  int rc = p->mixed ? upload_tables<float>(p) : upload_tables<double>(p);
+  if (rc) {
+    g_thread_error = p->err;
+    hp_plan_destroy(p);
+    return rc;
+  }
+  // zero every buffer once: row 0 and column 0 of all fields stay zero
+  if (hipMemsetAsync(p->coef, 0, (char*)(p->st) - (char*)(p->coef), p->stream) != hipSuccess) {
+    hp_plan_destroy(p);
+    return fail(nullptr, HP_EHIP, "workspace clear failed");
+  }
+  // Krylov vector pointer table: u_i of pole k at U[k][i]
+  const size_t es = p->mixed ? sizeof(c64) : sizeof(c128);
+  p->uptr_h.assign((size_t)desc->npoles * (HP_MAXM + 1), nullptr);
+  for (int k = 0; k < desc->npoles; ++k)
+    for (int i = 0; i <= desc->restart; ++i)
+      p->uptr_h[(size_t)k * (HP_MAXM + 1) + i] =
+          reinterpret_cast<char*>(p->U) + ((size_t)k * (desc->restart + 1) + i) * p->fieldn * es;
+  if ((rc = upload_uptr(p)) || (rc = upload_state(p))) {
+    g_thread_error = p->err;
+    hp_plan_destroy(p);
+    return rc;
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) {
+    hp_plan_destroy(p);
+    return fail(nullptr, HP_EHIP, "plan upload failed");
+  }
+  *out = p;
+  return (rmax > 1.0 + 1e-6) ? HP_WARN_UNSTABLE : HP_OK;
+}
+
+int hp_set_medium(hp_plan p, const double* n2) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!n2) return fail(p, HP_EINVAL, "n2 is NULL");
+  const double s = 1.0 / ((p->d.k0 * p->d.n0) * (p->d.k0 * p->d.n0));
+  launch_coef(n2, p->coef, p->coef_scratch, p->d.n0, s, p->d.edge_width, p->sc, p->geo, p->stream);
+  HPCHK(hipGetLastError());
+  p->medium_set = true;
+  return HP_OK;
+}
+
+int hp_step(hp_plan p, const void* E_in, const double* n2, void* E_out) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!E_in || !E_out) return fail(p, HP_EINVAL, "E_in/E_out is NULL");
+  if (n2) {
+    int rc = hp_set_medium(p, n2);
+    if (rc) return rc;
+  }
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
+  const c128* w = reinterpret_cast<const c128*>(E_in);
+  c128* out = reinterpret_cast<c128*>(E_out);
+  return p->mixed ? run_step<float>(p, w, out) : run_step<double>(p, w, out);
+}
+
+int hp_propagate(hp_plan p, const void* E_in, const double* n2, long n2_step_stride, int nsteps, void* E_out) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (nsteps < 0) return fail(p, HP_EINVAL, "nsteps < 0");
+  if (nsteps == 0) {
+    if (E_out != E_in)
+      HPCHK(hipMemcpyAsync(E_out, E_in, p->fieldn * sizeof(c128), hipMemcpyDeviceToDevice, p->stream));
+    return HP_OK;
+  }
+  int worst = HP_OK;
+  const void* src = E_in;
+  for (int s = 0; s < nsteps; ++s) {
+    const double* m = nullptr;
+    if (n2 && (s == 0 || n2_step_stride != 0)) m = n2 + (size_t)s * n2_step_stride;
+    int rc = hp_step(p, src, m, E_out);
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+    src = E_out;
+  }
+  return worst;
+}
+
+int hp_get_stats(hp_plan p, int* iters_per_pole, double* final_relres) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  std::vector<PoleState> h(p->d.npoles);
+  HPCHK(hipStreamSynchronize(p->stream));
+  HPCHK(hipMemcpy(h.data(), p->st, h.size() * sizeof(PoleState), hipMemcpyDeviceToHost));
+  for (int k = 0; k < p->d.npoles; ++k) {
+    if (iters_per_pole) iters_per_pole[k] = h[k].total;
+    if (final_relres) {
+      double r = (k < (int)p->relres.size()) ? p->relres[k] : -1.0;
+      if (r < 0) r = h[k].beta0 > 0 ? h[k].est / h[k].beta0 : 0.0;
+      final_relres[k] = r;
+    }
+  }
+  return HP_OK;
+}
+
+int hp_set_fixed_iters(hp_plan p, const int* iters) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (iters) {
+    for (int k = 0; k < p->d.npoles; ++k)
+      if (iters[k] < 1 || iters[k] > p->d.restart) return fail(p, HP_EINVAL, "fixed iterations must be in [1, restart]");
+    p->fixed.assign(iters, iters + p->d.npoles);
+  } else {
+    p->fixed.clear();
+  }
+  return upload_state(p);
+}
+
+int hp_apply_operator(hp_plan p, int pole, const void* x, void* y) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!x || !y || x == y) return fail(p, HP_EINVAL, "x, y must be distinct device buffers");
+  if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
+  const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
+  launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, b, p->sc, p->geo,
+                  nullptr, p->stream);
+  HPCHK(hipGetLastError());
+  return HP_OK;
+}
+
+int hp_apply_preconditioner(hp_plan p, int pole, const void* x, void* y) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!x || !y) return fail(p, HP_EINVAL, "x, y are NULL");
+  if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  const c128* xx = reinterpret_cast<const c128*>(x);
+  c128* yy = reinterpret_cast<c128*>(y);
+  return p->mixed ? apply_prec<float>(p, pole, xx, yy) : apply_prec<double>(p, pole, xx, yy);
+}
+
+int hp_profile(hp_plan p, int enable) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  HPCHK(hipStreamSynchronize(p->stream));
+  p->prof = enable != 0;
+  p->ev_used = 0;
+  p->ev_cls.clear();
+  p->ev_bytes.clear();
+  for (int c = 0; c < HP_K_COUNT; ++c) {
+    p->prof_n[c] = 0;
+    p->prof_ms[c] = 0.0;
+    p->prof_b[c] = 0.0;
+  }
+  return HP_OK;
+}
+
+int hp_profile_read(hp_plan p, long* launches, double* ms, double* bytes) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  HPCHK(hipStreamSynchronize(p->stream));
+  for (size_t i = 0; i < p->ev_cls.size(); ++i) {
+    float t = 0.f;
+    HPCHK(hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
+    const int c = p->ev_cls[i];
+    p->prof_n[c] += 1;
+    p->prof_ms[c] += t;
+    p->prof_b[c] += p->ev_bytes[i];
+  }
+  p->ev_used = 0;
+  p->ev_cls.clear();
+  p->ev_bytes.clear();
+  for (int c = 0; c < HP_K_COUNT; ++c) {
+    if (launches) launches[c] = p->prof_n[c];
+    if (ms) ms[c] = p->prof_ms[c];
+    if (bytes) bytes[c] = p->prof_b[c];
+  }
+  return HP_OK;
+}
+
+const char* hp_last_error(hp_plan p) { return p ? p->err.c_str() : g_thread_error.c_str(); }
+
+void hp_plan_destroy(hp_plan p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  if (p->flags_h) (void)hipHostFree(p->flags_h);
+  if (p->est_h) (void)hipHostFree(p->est_h);
+  if (p->active_h) (void)hipHostFree(p->active_h);
+  if (p->misc_h) (void)hipHostFree(p->misc_h);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+}  // extern "C"

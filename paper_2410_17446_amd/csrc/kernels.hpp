@@ -1,0 +1,90 @@
+// Launch wrappers of the HIP kernels (host side).  Every wrapper only enqueues
+// work on `s`; sizes are validated by the caller (the plan).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "state.hpp"
+
+struct StencilCoef {
+  double c2x[7], c2y[7];  // s * c_m / h^2 (second derivative, scaled by s = 1/(k0 n0)^2)
+  double d1x[6], d1y[6];  // d_m / h (first derivative)
+};
+
+struct Geo {
+  int nx, ny, ncomp;
+  size_t fsz;  // nx * ny
+};
+
+// Row DST-I of the unknowns of a complex128 field: out (R-domain, T) and
+// per-block partial sums of |in|^2 (nblk per component).
+template <typename T>
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s);
+template <typename T>
+int row_blocks(int nx);
+
+// Row DST-I back to complex128 (out = S_x in).
+template <typename T>
+void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, hipStream_t s);
+
+// Column pass: z = sigma_m * S_y diag(1/(mu_y + mu_x - b_k)) S_y u_m for the
+// active poles.  shared: every pole reads the same u (the step's S_x w).
+// Vector fields also get dz = D1y z (the y derivative the row pass needs).
+template <typename T>
+void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
+                const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
+                const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s);
+
+// Row pass: p = S_x (P (S_x z_m)) with P the medium part of Zbar, plus the
+// partial inner products <u_i, p>, i = 0..m.
+template <typename T>
+void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
+                      size_t psp, const cx<T>* const* uptr, const double* coef, const PoleState* st,
+                      const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
+                      const StencilCoef& sc, hipStream_t s);
+template <typename T>
+int row_apply_blocks(const Geo& g);
+
+// hc_i = sigma_i * sum of the partial inner products.
+void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int* active, int nactive, int maxm,
+                        hipStream_t s);
+
+// u_{m+1} = p - sum_i hc_i v_i and partial |u_{m+1}|^2.
+template <typename T>
+void launch_update(const cx<T>* pbase, size_t psp, cx<T>* const* uptr, const PoleState* st, const int* active,
+                   int nactive, double* part, int nblk, const Geo& g, hipStream_t s);
+int update_blocks(size_t total);
+
+// Hessenberg column, Givens rotation, residual estimate, convergence flag and
+// the least-squares solution at the end of a cycle.
+void launch_arnoldi(PoleState* st, const int* active, int nactive, const double* part, int nblk, int restart,
+                    int* flags, double* est, hipStream_t s);
+
+// Start a cycle: beta = sqrt(sum part), g = beta e1, sigma_0 = 1/beta.
+// Cycle tolerance on the estimate: max(tol * beta0, rtol_cycle * beta).
+void launch_cycle_init(PoleState* st, const int* poles, int npoles_in, const double* part, int nblk, int first,
+                       double tol, double rtol_cycle, hipStream_t s);
+
+// out = mask * (e^{-iK} r_inf w + e^{-iK} S_x (sum_k a_k [X_k + sum_i y_ki Z_ki])).
+template <typename T>
+void launch_final(const c128* w, c128* out, const cx<T>* zbase, size_t zsp, size_t zsi, const c128* xacc, size_t xsp,
+                  const PoleState* st, int npoles, c128 phase, c128 rinf_phase, double loss_coef, double eta,
+                  int W, const c128* tw64, const Geo& g, hipStream_t s);
+
+// X_k += sum_i y_ki Z_ki (R-domain, complex128 accumulator).
+template <typename T>
+void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, int pole, const Geo& g,
+                  hipStream_t s);
+
+// y = rhs - (Zbar - b I) x  (rhs may be NULL: y = (Zbar - b I) x), explicit
+// 13-point stencils, complex128; partial |y|^2 per block.
+void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
+                     const Geo& g, double* part, hipStream_t s);
+int op_blocks(const Geo& g);
+
+// Coefficient planes from n^2: V (plane 0) and, for the vector operator,
+// s psi_x, s psi_y, s psi_xx, s psi_yy, s psi_xy (planes 1..5).
+void launch_coef(const double* n2, double* coef, double* scratch, double n0, double s_scale, int W,
+                 const StencilCoef& sc, const Geo& g, hipStream_t s);
+
+void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);

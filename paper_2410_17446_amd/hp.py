@@ -1,0 +1,179 @@
+"""Thin ctypes binding of libhp.so (include/hp.h).
+
+Argument marshalling only: every step of a propagation runs in the HIP
+kernels of the library.  Fields are torch tensors on the GPU (complex128,
+shape (ncomp, ny, nx); n^2 float64, shape (ny, nx)); PyTorch provides the
+device memory and the stream.  There is no CPU fallback: if the library is not
+built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhp.so")
+_lib = None
+
+HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
+HP_FP64, HP_MIXED = 0, 1
+
+SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_propagate",
+           "hp_get_stats", "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
+           "hp_profile", "hp_profile_read", "hp_last_error", "hp_plan_destroy")
+KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
+
+
+class hp_c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class hp_plan_desc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("dx", C.c_double), ("dy", C.c_double),
+                ("k0", C.c_double), ("n0", C.c_double), ("dz", C.c_double), ("ncomp", C.c_int),
+                ("npoles", C.c_int), ("poles", C.POINTER(hp_c128)), ("residues", C.POINTER(hp_c128)),
+                ("r_inf", hp_c128), ("d2", C.POINTER(C.c_double)), ("d1", C.POINTER(C.c_double)),
+                ("edge_width", C.c_int), ("edge_eta", C.c_double), ("tol", C.c_double),
+                ("restart", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int)]
+
+
+class HPError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libhp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise HPError(f"{_LIB_PATH} is missing: build it with python -m paper_2410_17446_amd.build")
+        L = C.CDLL(_LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+        L.hp_workspace_bytes.argtypes = [C.POINTER(hp_plan_desc)]
+        L.hp_workspace_bytes.restype = C.c_size_t
+        L.hp_plan_create.argtypes = [C.POINTER(hp_plan_desc), vp, vp, C.POINTER(vp)]
+        L.hp_set_medium.argtypes = [vp, vp]
+        L.hp_step.argtypes = [vp, vp, vp, vp]
+        L.hp_propagate.argtypes = [vp, vp, vp, C.c_long, C.c_int, vp]
+        L.hp_get_stats.argtypes = [vp, ip, dp]
+        L.hp_set_fixed_iters.argtypes = [vp, ip]
+        L.hp_apply_operator.argtypes = [vp, C.c_int, vp, vp]
+        L.hp_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp]
+        L.hp_profile.argtypes = [vp, C.c_int]
+        L.hp_profile_read.argtypes = [vp, C.POINTER(C.c_long), dp, dp]
+        L.hp_last_error.argtypes = [vp]
+        L.hp_last_error.restype = C.c_char_p
+        L.hp_plan_destroy.argtypes = [vp]
+        for name in SYMBOLS:
+            if name not in ("hp_workspace_bytes", "hp_last_error", "hp_plan_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise HPError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise HPError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Plan:
+    """A propagation plan (hp_plan_create).  poles/residues: complex arrays; d2 (7) and d1 (6):
+    the 13-point stencil coefficients; the rest as in hp_plan_desc."""
+
+    def __init__(self, nx, ny, dx, dy, k0, n0, dz, ncomp, poles, residues, r_inf, d2, d1,
+                 edge_width, edge_eta, tol, restart=30, max_cycles=20, precision=HP_FP64,
+                 stream=None, workspace=None):
+        import torch
+        self.L = lib()
+        poles = np.asarray(poles, dtype=np.complex128)
+        residues = np.asarray(residues, dtype=np.complex128)
+        self._poles = (hp_c128 * len(poles))(*[hp_c128(p.real, p.imag) for p in poles])
+        self._res = (hp_c128 * len(residues))(*[hp_c128(a.real, a.imag) for a in residues])
+        self._d2 = (C.c_double * 7)(*np.asarray(d2, dtype=float))
+        self._d1 = (C.c_double * 6)(*np.asarray(d1, dtype=float))
+        r_inf = complex(r_inf)
+        self.desc = hp_plan_desc(nx, ny, dx, dy, k0, n0, dz, ncomp, len(poles), self._poles, self._res,
+                                 hp_c128(r_inf.real, r_inf.imag), self._d2, self._d1, edge_width, edge_eta,
+                                 tol, restart, max_cycles, precision)
+        self.shape = (ncomp, ny, nx)
+        self.npoles = len(poles)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        self.handle = C.c_void_p()
+        ws = _ptr(workspace) if workspace is not None else None
+        rc = self.L.hp_plan_create(C.byref(self.desc), C.c_void_p(stream), C.c_void_p(ws), C.byref(self.handle))
+        if rc < 0:
+            raise HPError(f"hp_plan_create: {rc}: {self.L.hp_last_error(None).decode()}")
+        self.create_status = rc
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise HPError(f"{what}: {rc}: {self.L.hp_last_error(self.handle).decode()}")
+        return rc
+
+    def set_medium(self, n2):
+        return self._check(self.L.hp_set_medium(self.handle, _ptr(n2)), "hp_set_medium")
+
+    def step(self, E_in, n2=None, E_out=None):
+        import torch
+        if E_out is None:
+            E_out = torch.empty_like(E_in)
+        self._check(self.L.hp_step(self.handle, _ptr(E_in), _ptr(n2), _ptr(E_out)), "hp_step")
+        return E_out
+
+    def propagate(self, E_in, nsteps, n2=None, n2_step_stride=0, E_out=None):
+        import torch
+        if E_out is None:
+            E_out = torch.empty_like(E_in)
+        rc = self.L.hp_propagate(self.handle, _ptr(E_in), _ptr(n2), n2_step_stride, nsteps, _ptr(E_out))
+        self._check(rc, "hp_propagate")
+        return E_out
+
+    def stats(self):
+        it = (C.c_int * self.npoles)()
+        rr = (C.c_double * self.npoles)()
+        self._check(self.L.hp_get_stats(self.handle, it, rr), "hp_get_stats")
+        return list(it), list(rr)
+
+    def set_fixed_iters(self, iters):
+        arr = None if iters is None else (C.c_int * self.npoles)(*iters)
+        return self._check(self.L.hp_set_fixed_iters(self.handle, arr), "hp_set_fixed_iters")
+
+    def apply_operator(self, pole, x, y):
+        return self._check(self.L.hp_apply_operator(self.handle, pole, _ptr(x), _ptr(y)), "hp_apply_operator")
+
+    def apply_preconditioner(self, pole, x, y):
+        return self._check(self.L.hp_apply_preconditioner(self.handle, pole, _ptr(x), _ptr(y)),
+                           "hp_apply_preconditioner")
+
+    def profile(self, enable: bool):
+        return self._check(self.L.hp_profile(self.handle, int(enable)), "hp_profile")
+
+    def profile_read(self):
+        """{kernel class: (launches, total ms, total algorithmic bytes)}."""
+        n = len(KERNEL_CLASSES)
+        la, ms, by = (C.c_long * n)(), (C.c_double * n)(), (C.c_double * n)()
+        self._check(self.L.hp_profile_read(self.handle, la, ms, by), "hp_profile_read")
+        return {k: (la[i], ms[i], by[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def workspace_bytes(self):
+        return self.L.hp_workspace_bytes(C.byref(self.desc))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.L.hp_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,145 @@
+"""Plan tables a caller of libhp needs (host-side set-up, not on the per-step path).
+
+* 13-point stencils (Sec. 4.1): fourth-order second and first derivatives whose
+  free coefficients minimise the worst relative error of the Fourier symbol
+  over a design band (83 % of [0, pi] for the second derivative, 70 % for the
+  first), as a linear programme.
+* The (N,N) AAA-Lawson rational fit of exp(iK sqrt(1+z)) on Re z in [-4, 2]
+  (Sec. 3.1) and its partial fractions r_inf + sum a_k/(z - b_k)
+  (Sec. 2, eq. pf_expan_eq): the poles/residues hp_plan_create takes.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+from scipy.optimize import linprog
+
+
+def _minimax_lp(rows: np.ndarray, eq: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    """min t  s.t. |rows @ x - 1| <= t, eq @ x = rhs."""
+    ns, nv = rows.shape
+    ones = np.ones((ns, 1))
+    A_ub = np.block([[rows, -ones], [-rows, -ones]])
+    b_ub = np.concatenate([np.ones(ns), -np.ones(ns)])
+    A_eq = np.hstack([eq, np.zeros((eq.shape[0], 1))])
+    c = np.zeros(nv + 1)
+    c[-1] = 1.0
+    sol = linprog(c, A_ub=A_ub, b_ub=b_ub, A_eq=A_eq, b_eq=rhs, bounds=(None, None), method="highs")
+    if sol.status != 0:
+        raise RuntimeError("stencil design LP failed: " + sol.message)
+    return sol.x[:nv]
+
+
+def stencil_d2(band_frac: float = 0.83, hw: int = 6, samples: int = 3000) -> np.ndarray:
+    """c0..c_hw; symbol 4 sum_m c_m sin^2(m theta / 2) (c0 = -2 sum c_m) ~ theta^2."""
+    th = np.pi * band_frac * np.arange(1, samples + 1) / samples
+    m = np.arange(1, hw + 1)
+    rows = 4.0 * np.sin(np.outer(th, m) / 2.0) ** 2 / th[:, None] ** 2
+    eq = np.vstack([m ** 2, m ** 4]).astype(float)
+    cm = _minimax_lp(rows, eq, np.array([1.0, 0.0]))
+    return np.concatenate([[-2.0 * cm.sum()], cm])
+
+
+def stencil_d1(band_frac: float = 0.70, hw: int = 6, samples: int = 3000) -> np.ndarray:
+    """d1..d_hw; symbol 2 sum_m d_m sin(m theta) ~ theta."""
+    th = np.pi * band_frac * np.arange(1, samples + 1) / samples
+    m = np.arange(1, hw + 1)
+    rows = 2.0 * np.sin(np.outer(th, m)) / th[:, None]
+    eq = np.vstack([2.0 * m, m ** 3]).astype(float)
+    return _minimax_lp(rows, eq, np.array([1.0, 0.0]))
+
+
+def exp_sqrt(z: np.ndarray, K: float) -> np.ndarray:
+    """exp(iK sqrt(1+z)) for real z, principal branch (decay below z = -1)."""
+    z = np.asarray(z, dtype=float)
+    s = 1.0 + z
+    return np.where(s >= 0, np.exp(1j * K * np.sqrt(np.abs(s))), np.exp(-K * np.sqrt(np.abs(s))))
+
+
+class RationalFit:
+    """AAA followed by Lawson reweighting; barycentric numerator/denominator weights a, b."""
+
+    def __init__(self, K: float, degree: int, lo: float = -4.0, hi: float = 2.0, samples: int = 4001,
+                 lawson_steps: int = 40):
+        self.K, self.degree = K, degree
+        self.Z = np.linspace(lo, hi, samples)
+        self.F = exp_sqrt(self.Z, K)
+        self._aaa(degree + 1)
+        if lawson_steps:
+            self._lawson(lawson_steps)
+        self._partial_fractions()
+
+    def _aaa(self, nsupport: int):
+        Z, F = self.Z.astype(complex), self.F
+        chosen = np.zeros(len(Z), dtype=bool)
+        approx = np.full(len(Z), np.mean(F))
+        for _ in range(nsupport):
+            err = np.where(chosen, -np.inf, np.abs(F - approx))
+            chosen[int(np.argmax(err))] = True
+            t, ft = Z[chosen], F[chosen]
+            others = ~chosen
+            cauchy = 1.0 / np.subtract.outer(Z[others], t)
+            loewner = cauchy * np.subtract.outer(F[others], ft)
+            w = sla.svd(loewner, full_matrices=False)[2][-1].conj()
+            approx = F.copy()
+            approx[others] = (cauchy @ (w * ft)) / (cauchy @ w)
+        self.t = Z[chosen]
+        self.ft = F[chosen]
+        self.a = w * self.ft
+        self.b = w
+
+    def _rows(self):
+        Z, F = self.Z.astype(complex), self.F
+        off = np.ones(len(Z), dtype=bool)
+        idx = [int(np.argmin(np.abs(Z - t))) for t in self.t]
+        off[idx] = False
+        h = np.abs(self.Z[1] - self.Z[0])
+        # sample rows: Cauchy matrix; support rows: the residue of F d - n at t_j, over h
+        C = np.vstack([1.0 / np.subtract.outer(Z[off], self.t), np.eye(len(self.t)) / h])
+        return C, np.concatenate([F[off], F[idx]])
+
+    def _lawson(self, steps: int):
+        C, F = self._rows()
+        n = len(self.t)
+        worst = lambda a, b: np.max(np.abs(F - (C @ a) / (C @ b)))
+        best_err, best = worst(self.a, self.b), (self.a, self.b)
+        wts = np.full(len(F), 1.0 / len(F))
+        for _ in range(steps):
+            sq = np.sqrt(wts)[:, None]
+            M = np.hstack([sq * (F[:, None] * C), -sq * C])      # unknowns (b, a)
+            if not np.isfinite(M).all():
+                break
+            v = sla.svd(M, full_matrices=False)[2][-1].conj()
+            b, a = v[:n], v[n:]
+            e = np.abs(F - (C @ a) / (C @ b))
+            if not np.isfinite(e).all():
+                break
+            if e.max() < best_err:
+                best_err, best = e.max(), (a, b)
+            wts = wts * np.maximum(e, 1e-300)
+            wts /= wts.sum()
+        self.a, self.b = best
+
+    def _partial_fractions(self):
+        n = len(self.t)
+        E = np.zeros((n + 1, n + 1), dtype=complex)
+        E[0, 1:] = self.b
+        E[1:, 0] = 1.0
+        E[1:, 1:] = np.diag(self.t)
+        B = np.diag(np.concatenate([[0.0], np.ones(n)])).astype(complex)
+        ev = sla.eigvals(E, B)
+        poles = ev[np.isfinite(ev) & (np.abs(ev) < 1e12)]
+        d = 1.0 / np.subtract.outer(poles, self.t)
+        self.poles = poles
+        self.residues = (d @ self.a) / (-(d ** 2) @ self.b)
+        self.r_inf = complex(self.a.sum() / self.b.sum())
+
+    def __call__(self, z):
+        z = np.asarray(z, dtype=complex)
+        return self.r_inf + (1.0 / np.subtract.outer(z.ravel(), self.poles)) @ self.residues
+
+
+def plan_tables(K: float, npoles: int):
+    """(poles, residues, r_inf, d2, d1) for hp_plan_create."""
+    f = RationalFit(K, npoles)
+    return f.poles, f.residues, f.r_inf, stencil_d2(), stencil_d1()

@@ -1,0 +1,72 @@
+"""The C ABI: the library loads, exports what include/hp.h declares, and its
+host-side validation answers without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_17446_amd import hp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_symbols():
+    assert declared_functions() == sorted(hp.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hp.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _desc(**kw):
+    poles = (hp.hp_c128 * 2)(hp.hp_c128(-1.0, -0.1), hp.hp_c128(-2.0, -0.5))
+    res = (hp.hp_c128 * 2)(hp.hp_c128(0.1, 0.0), hp.hp_c128(0.2, 0.0))
+    d2 = (C.c_double * 7)(-3.2, 1.9, -0.41, 0.14, -0.055, 0.0175, -0.003)
+    d1 = (C.c_double * 6)(0.93, -0.38, 0.17, -0.074, 0.025, -0.0046)
+    args = dict(nx=64, ny=64, dx=0.25, dy=0.25, k0=2 * np.pi, n0=1.0, dz=1.0, ncomp=1, npoles=2,
+                poles=poles, residues=res, r_inf=hp.hp_c128(0.0, 0.0), d2=d2, d1=d1, edge_width=8,
+                edge_eta=0.25, tol=1e-10, restart=30, max_cycles=20, precision=0)
+    args.update(kw)
+    d = hp.hp_plan_desc(**args)
+    d._keep = (poles, res, d2, d1)
+    return d
+
+
+def test_workspace_bytes_scales_with_problem():
+    L = hp.lib()
+    a = L.hp_workspace_bytes(C.byref(_desc()))
+    b = L.hp_workspace_bytes(C.byref(_desc(nx=128, ny=128)))
+    c = L.hp_workspace_bytes(C.byref(_desc(precision=1)))
+    assert a > 0 and b > 3 * a and c < a
+
+
+@pytest.mark.parametrize("bad", [dict(nx=100), dict(nx=32), dict(ncomp=3), dict(edge_width=5),
+                                 dict(tol=0.0), dict(restart=0), dict(restart=65), dict(npoles=0),
+                                 dict(precision=7), dict(dz=-1.0), dict(nx=2048, ny=2048, ncomp=2),
+                                 dict(edge_width=30)])
+def test_invalid_descriptors_are_rejected_on_the_host(bad):
+    L = hp.lib()
+    d = _desc(**bad)
+    assert L.hp_workspace_bytes(C.byref(d)) == 0
+    out = C.c_void_p()
+    rc = L.hp_plan_create(C.byref(d), None, None, C.byref(out))
+    assert rc == -1 and not out.value
+    assert L.hp_last_error(None)
+
+
+def test_null_arguments():
+    L = hp.lib()
+    assert L.hp_plan_create(None, None, None, None) == -1
+    assert L.hp_step(None, None, None, None) == -1
+    assert L.hp_set_medium(None, None) == -1
+    L.hp_plan_destroy(None)

@@ -1,0 +1,180 @@
+"""Parity of the HIP library against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 mode 1e-10 relative L2 for a step (the oracle's iteration
+counts are replayed so both sides stop after the same Arnoldi step; both then
+carry only rounding differences, amplified by at most sum|a_k| times the
+conditioning of the shifted systems); operator-level calls 1e-13.  Mixed mode
+(complex64 Krylov vectors and transforms, FP64 Arnoldi / Givens / refinement)
+1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import precond
+from oracle import step as st
+from paper_2410_17446_amd import inputs
+
+from helpers import gpu_plan, oracle_grid, oracle_pf, rel_l2, to_gpu, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+@pytest.mark.parametrize("pole", [-1, 0, 5])
+def test_operator_matches_oracle(ncomp, pole):
+    torch = _cuda()
+    wl = workload(N=64, ncomp=ncomp, W=8)
+    g = oracle_grid(wl)
+    n2 = inputs.grf_n2(64, 0.25, 0.05, 1.0, seed=7) if ncomp == 2 else wl["n2"]
+    co = op.coefficients(g, n2, ncomp == 2)
+    x = inputs.random_field(64, ncomp, seed=3)
+    b = 0.0 if pole < 0 else wl["fit"]["poles"][pole]
+    ref = op.apply_shifted(g, co, x, b)
+    plan = gpu_plan(wl)
+    plan.set_medium(to_gpu(n2))
+    y = torch.zeros_like(to_gpu(x))
+    plan.apply_operator(pole, to_gpu(x), y)
+    assert rel_l2(y.cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("N,precision", [(64, 0), (128, 0), (512, 0), (64, 1), (256, 1)])
+def test_preconditioner_matches_oracle(N, precision):
+    """M_k^-1 by DST-I: rounding is amplified by kappa_k = max|mu - b_k| / min|mu - b_k|, so the
+    bound is 20 eps kappa_k (eps of the working precision)."""
+    torch = _cuda()
+    wl = workload(N=N, W=8)
+    g = oracle_grid(wl)
+    x = inputs.random_field(N, 1, seed=4)
+    lam = precond.spectrum(g)
+    eps = 2.2e-16 if precision == 0 else 1.2e-7
+    plan = gpu_plan(wl, precision=precision)
+    for pole in (0, 3, 7):
+        b = wl["fit"]["poles"][pole]
+        kappa = np.abs(lam - b).max() / np.abs(lam - b).min()
+        ref = precond.apply_minv(g, x, b)
+        y = torch.zeros_like(to_gpu(x))
+        plan.apply_preconditioner(pole, to_gpu(x), y)
+        err = rel_l2(y.cpu().numpy(), ref)
+        assert err < 20 * eps * kappa, (pole, err, kappa)
+
+
+def _oracle_step(wl, w=None, schedules=None):
+    g = oracle_grid(wl)
+    co = op.coefficients(g, wl["n2"], wl["cfg"]["ncomp"] == 2)
+    return st.step(g, co, wl["w"] if w is None else w, oracle_pf(wl), wl["cfg"]["dz"], wl["cfg"]["tol"],
+                   wl["cfg"]["restart"], schedules=schedules)
+
+
+def _replay(iters_cycles):
+    """The oracle's per-pole counts as a single-cycle schedule (all runs here need one cycle)."""
+    return [c[0] if len(c) == 1 else sum(c) for c in iters_cycles]
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_step_fp64_replayed_iterations(ncomp):
+    torch = _cuda()
+    wl = workload(N=64, ncomp=ncomp, W=8, tol=1e-10)
+    if ncomp == 2:
+        wl["n2"] = inputs.grf_n2(64, 0.25, 0.02, 1.0, seed=9)
+        wl["w"] = inputs.gaussian_beam(64, 0.25, 4.0, ncomp=2) + 0.3j * inputs.gaussian_beam(64, 0.25, 3.0, ncomp=2)[[0, 0]]
+    ref, stats = _oracle_step(wl)
+    counts = [sum(c) for c in stats.cycle_iters]
+    assert all(len(c) == 1 for c in stats.cycle_iters)
+    plan = gpu_plan(wl)
+    plan.set_fixed_iters(counts)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-10
+    it, _ = plan.stats()
+    assert it == counts
+
+
+def test_step_fp64_own_tolerance():
+    """Without replay the GPU stops on its own: every solve meets tol (the true residual
+    decides where the split operator's rounding could hide the last digits), iteration
+    counts stay within a restart of the oracle's, and the fields agree to ~tol."""
+    torch = _cuda()
+    wl = workload(N=64, W=8, tol=1e-10)
+    ref, stats = _oracle_step(wl)
+    plan = gpu_plan(wl)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    it, rr = plan.stats()
+    err = rel_l2(out.cpu().numpy(), ref)
+    assert max(rr) <= 1e-10
+    assert all(abs(a - b) <= 3 for a, b in zip(it, stats.iters)), (it, stats.iters, err)
+    assert err < 1e-8
+
+
+def test_homogeneous_one_iteration_and_closed_form():
+    torch = _cuda()
+    wl = workload(N=128, W=8, medium=("uniform",))
+    wl["n2"] = np.ones((128, 128))
+    ref, stats = _oracle_step(wl)
+    assert stats.iters == [1] * 8
+    plan = gpu_plan(wl)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    it, rr = plan.stats()
+    assert it == [1] * 8 and max(rr) < 1e-13
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-11
+
+
+def test_propagate_ten_steps_scalar64():
+    """The 64 x 64 scalar workload: 10 steps, each step replaying the oracle's counts."""
+    torch = _cuda()
+    wl = workload(N=64, W=8, tol=1e-10)
+    g = oracle_grid(wl)
+    co = op.coefficients(g, wl["n2"], False)
+    pf = oracle_pf(wl)
+    plan = gpu_plan(wl)
+    plan.set_medium(to_gpu(wl["n2"]))
+    w_o = wl["w"].copy()
+    w_g = to_gpu(wl["w"])
+    for s in range(10):
+        w_o, stats = st.step(g, co, w_o, pf, 1.0, 1e-10)
+        plan.set_fixed_iters([sum(c) for c in stats.cycle_iters])
+        w_g = plan.step(w_g)
+    assert rel_l2(w_g.cpu().numpy(), w_o) < 1e-10
+
+
+def test_output_may_alias_input_and_borders_are_zero():
+    torch = _cuda()
+    wl = workload(N=64, W=8)
+    plan = gpu_plan(wl)
+    x = to_gpu(wl["w"])
+    x[0, 0, :] = 5.0   # ignored on input
+    y = plan.step(x.clone(), to_gpu(wl["n2"]))
+    plan2 = gpu_plan(wl)
+    z = x.clone()
+    plan2.step(z, to_gpu(wl["n2"]), E_out=z)
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    assert float(z[:, 0, :].abs().max()) == 0.0 and float(z[:, :, 0].abs().max()) == 0.0
+
+
+def test_mixed_precision_step():
+    torch = _cuda()
+    wl = workload(N=128, W=16, tol=1e-8, npoles=16, medium=("sine", 0.02, 1.0), w0=8.0)
+    ref, _ = _oracle_step(wl)
+    plan = gpu_plan(wl, precision=1)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    _, rr = plan.stats()
+    assert max(rr) <= 1e-8
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-6
+
+
+def test_non_square_grid():
+    torch = _cuda()
+    wl = workload(N=64, ny=128, W=8)
+    plan = gpu_plan(wl)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    o = out.cpu().numpy()
+    assert np.isfinite(o).all() and o.shape == (1, 128, 64)
+    _, rr = plan.stats()
+    assert max(rr) <= 1e-10
