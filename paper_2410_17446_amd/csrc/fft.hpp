@@ -11,8 +11,18 @@
 // FFT: self-sorting Stockham radix-8/4/2 with the data in LDS, one group of
 // NT = L/8 threads per transform, each thread holding R values of a stage in
 // registers.  Twiddles come from a table tw[m] = exp(-2 pi i m / L).
+//
+// LDS addresses are padded by one element every eight (pidx): the first
+// stage writes eight consecutive elements per thread, i.e. a 128-byte lane
+// stride for complex128, which would put every lane of a group on the same
+// banks; with the pad the lane stride is 144 bytes and the groups spread over
+// all banks.
 #pragma once
 #include "cplx.hpp"
+
+__host__ __device__ constexpr int pidx(int e) { return e + (e >> 3); }
+// LDS elements of one padded transform buffer of length L
+__host__ __device__ constexpr int plen(int L) { return L + L / 8; }
 
 template <typename T>
 __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
@@ -64,7 +74,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
   for (int q = 0; q < PER; ++q) {
     const int j = t + q * NT;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+    for (int r = 0; r < R; ++r) v[q][r] = buf[pidx(j + r * NB)];
     if constexpr (NS > 1) {
       const int k = j % NS;
       constexpr int STEP = L / (NS * R);
@@ -79,7 +89,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
     const int j = t + q * NT;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[base + r * NS] = v[q][r];
+    for (int r = 0; r < R; ++r) buf[pidx(base + r * NS)] = v[q][r];
   }
   __syncthreads();
 }
@@ -106,16 +116,26 @@ __device__ __forceinline__ void fft(cx<T>* buf, const cx<T>* __restrict__ tw, in
 template <typename T>
 __device__ __forceinline__ void odd_store(cx<T>* buf, int n, int m, cx<T> x) {
   if (m == 0) {
-    buf[0] = mk<T>(0, 0);
-    buf[n] = mk<T>(0, 0);
+    buf[pidx(0)] = mk<T>(0, 0);
+    buf[pidx(n)] = mk<T>(0, 0);
   } else {
-    buf[m] = x;
-    buf[2 * n - m] = -x;
+    buf[pidx(m)] = x;
+    buf[pidx(2 * n - m)] = -x;
   }
 }
 
 // DST-I coefficient p (1..n-1) from the FFT of the odd extension.
 template <typename T>
 __device__ __forceinline__ cx<T> dst_out(const cx<T>* buf, int p, T scale) {
-  return scale * mul_i(buf[p]);
+  return scale * mul_i(buf[pidx(p)]);
+}
+
+// Value at index i (any integer in (-n, 2n)) of the odd-periodic sequence whose
+// entries 1..n-1 sit (FFT output, unscaled) in buf: reflection about 0 and n.
+template <typename T>
+__device__ __forceinline__ cx<T> odd_at(const cx<T>* buf, int n, int i) {
+  if (i > 0 && i < n) return buf[pidx(i)];
+  if (i < 0 && i > -n) return -buf[pidx(-i)];
+  if (i > n && i < 2 * n) return -buf[pidx(2 * n - i)];
+  return mk<T>(0, 0);
 }

@@ -83,6 +83,7 @@ struct hp_plan_s {
   double prof_ms[HP_K_COUNT]{}, prof_b[HP_K_COUNT]{};
   std::vector<int> m_h;  // Arnoldi columns per pole (host mirror)
   std::vector<double> incons;  // eps kappa(M_k) per pole
+  hipEvent_t iter_ev[2] = {nullptr, nullptr};
   c128 phase{}, rinf_phase{};  // e^{-iK}, e^{-iK} r_inf
   double loss_coef = 0.0;      // k0 dz / (2 n0)
   std::string err;
@@ -180,8 +181,8 @@ void layout(hp_plan p, Ws& w) {
   p->st_scratch = w.take<PoleState>(1);
   p->uptr = w.take<void*>((size_t)K * (HP_MAXM + 1));
   p->uptr_scratch = w.take<void*>(HP_MAXM + 1);
-  p->active_d = w.take<int>(HP_MAXPOLES);
-  p->flags_d = w.take<int>(HP_MAXPOLES);
+  p->active_d = w.take<int>(3 * HP_MAXPOLES);
+  p->flags_d = w.take<int>(2 * HP_MAXPOLES);
   p->est_d = w.take<double>(HP_MAXPOLES);
   p->part_dots = w.take<double2>((size_t)K * (HP_MAXM + 1) * 2 * p->napplyblk);
   p->part_norm = w.take<double>((size_t)K * p->nupdblk);
@@ -198,7 +199,7 @@ void derive(hp_plan p) {
   p->fieldn = p->geo.fsz * d.ncomp;
   const int rpw = 256 / (2 * d.nx / 8) > 0 ? 256 / (2 * d.nx / 8) : 1;
   p->nrowblk = (d.ny - 1 + rpw - 1) / rpw;
-  p->napplyblk = p->mixed ? row_apply_blocks<float>(p->geo) : row_apply_blocks<double>(p->geo);
+  p->napplyblk = p->mixed ? row_apply_parts<float>(p->geo) : row_apply_parts<double>(p->geo);
   p->nupdblk = update_blocks(p->fieldn);
   p->nopblk = op_blocks(p->geo);
   const double s = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
@@ -296,7 +297,7 @@ int true_residual(hp_plan p, int k, const c128* w, double* res) {
   static const int one = 1, zero = 0;
   HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(&p->st[k].m, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, p->stream);
+  launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
   launch_apply_op(p->tmp1, w, p->tmp2, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc, p->geo, p->part_misc,
                   p->stream);
   }
@@ -322,14 +323,20 @@ int restart_pole(hp_plan p, int k) {
     HPCHK(hipMemcpyAsync(p->uptr + (size_t)k * (HP_MAXM + 1), &p->uptr_h[(size_t)k * (HP_MAXM + 1)], sizeof(void*),
                          hipMemcpyHostToDevice, p->stream));
   }
-  p->active_h[HP_MAXPOLES - 1] = k;
-  HPCHK(hipMemcpyAsync(p->active_d + HP_MAXPOLES - 1, &p->active_h[HP_MAXPOLES - 1], sizeof(int),
-                       hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, p->active_d + HP_MAXPOLES - 1, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol,
+  int* slot_h = p->active_h + 3 * HP_MAXPOLES - 1;
+  int* slot_d = p->active_d + 3 * HP_MAXPOLES - 1;
+  *slot_h = k;
+  HPCHK(hipMemcpyAsync(slot_d, slot_h, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, slot_d, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol,
                     p->mixed ? kInnerRtolMixed : 0.0, p->stream);
   return HP_OK;
 }
 
+// One step: the lockstep Arnoldi iterations of all poles, pipelined one deep:
+// iteration j+1 is enqueued before the flags of iteration j are read, and a
+// pole that finished in iteration j skips itself in iteration j+1 (its flag is
+// set on the device).  Cycle ends that need the true residual (mixed
+// precision, restarts, flag 3) are handled on the host between launches.
 template <typename T>
 int run_step(hp_plan p, const c128* w, c128* out) {
   const hp_plan_desc& d = p->d;
@@ -353,81 +360,126 @@ int run_step(hp_plan p, const c128* w, c128* out) {
       p->uptr_h[(size_t)k * (HP_MAXM + 1)] = bR;
       changed = true;
     }
-    p->active_h[k] = k;
   }
   if (changed) {
     int rc = upload_uptr(p);
     if (rc) return rc;
   }
-  HPCHK(hipMemcpyAsync(p->active_d, p->active_h, K * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  int* act0 = p->active_h + 2 * HP_MAXPOLES;  // pinned slot for the initial list
+  for (int k = 0; k < K; ++k) act0[k] = k;
+  HPCHK(hipMemcpyAsync(p->active_d, act0, K * sizeof(int), hipMemcpyHostToDevice, p->stream));
   launch_cycle_init(p->st, p->active_d, K, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
                     p->mixed ? kInnerRtolMixed : 0.0, p->stream);
-  std::vector<int> active(K);
-  for (int k = 0; k < K; ++k) active[k] = k;
-  std::vector<int> cycles(K, 0);
+  std::vector<char> live(K, 1);
+  std::vector<long> since(K, 0);  // iteration at which the pole's current cycle started
+  std::vector<int> cycles(K, 0), done_m(K, 0);
   p->relres.assign(K, -1.0);
   double beta0 = -1.0;
-  bool first = true;
   bool noconv = false;
   const size_t zsp = (size_t)M * fn, zsi = fn, psp = fn, dzsp = (d.ncomp == 2) ? fn : 0;
   cx<T>* Zb = reinterpret_cast<cx<T>*>(p->Z);
   cx<T>* Pb = reinterpret_cast<cx<T>*>(p->P);
   cx<T>* DZb = reinterpret_cast<cx<T>*>(p->DZ);
   const cx<T>* const* up = reinterpret_cast<const cx<T>* const*>(p->uptr);
-  while (!active.empty()) {
-    const int na = (int)active.size();
-    for (int a = 0; a < na; ++a) p->active_h[a] = active[a];
-    HPCHK(hipMemcpyAsync(p->active_d, p->active_h, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  struct Flight {
+    std::vector<int> poles;
+    int slot;
+    long iter;
+  };
+  std::vector<Flight> q;
+  long next_iter = 0;
+  auto launch_iter = [&](const std::vector<int>& poles) -> int {
+    const int slot = (int)(next_iter & 1);
+    const int na = (int)poles.size();
+    int* ah = p->active_h + slot * HP_MAXPOLES;
+    int* ad = p->active_d + slot * HP_MAXPOLES;
+    int maxm = 0;
     double sum_m = 0.0;
-    for (int k : active) sum_m += p->m_h[k];
+    for (int a = 0; a < na; ++a) {
+      ah[a] = poles[a];
+      const int mk_ = (int)std::min<long>(next_iter - since[poles[a]], M - 1);
+      maxm = std::max(maxm, mk_);
+      sum_m += mk_;
+    }
+    HPCHK(hipMemcpyAsync(ad, ah, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
     {
       const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
-      Prof pr(p, HP_K_COL, U1 * es * ((first ? 1.0 : na) + outs));
-      launch_col<T>(up, Zb, zsp, zsi, DZb, dzsp, p->st, p->active_d, na, first, p->mu_x, p->mu_y, twy, p->geo,
-                    p->sc, p->stream);
+      Prof pr(p, HP_K_COL, U1 * es * (na + outs));
+      launch_col<T>(up, Zb, zsp, zsi, DZb, dzsp, p->st, ad, na, false, p->mu_x, p->mu_y, twy, p->geo, p->sc,
+                    p->stream);
     }
-    first = false;
     {
       const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
       Prof pr(p, HP_K_ROW_APPLY, U1 * es * per_pole + (U1 / d.ncomp) * 8.0 * planes);
-      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, p->coef, p->st, p->active_d, na, p->part_dots, twx,
-                          p->geo, p->sc, p->stream);
+      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, p->coef, p->st, ad, na, p->part_dots, twx, p->geo,
+                          p->sc, p->stream);
     }
     {
       Prof pr(p, HP_K_SMALL, 0.0);
-      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, p->active_d, na, M, p->stream);
+      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->stream);
     }
     {
       Prof pr(p, HP_K_UPDATE, U1 * es * (sum_m + 3.0 * na));
-      launch_update<T>(Pb, psp, reinterpret_cast<cx<T>* const*>(p->uptr), p->st, p->active_d, na, p->part_norm,
-                       p->nupdblk, p->geo, p->stream);
+      launch_update<T>(Pb, psp, reinterpret_cast<cx<T>* const*>(p->uptr), p->st, ad, na, p->part_norm, p->nupdblk,
+                       p->geo, p->stream);
     }
     {
       Prof pr(p, HP_K_SMALL, 0.0);
-      launch_arnoldi(p->st, p->active_d, na, p->part_norm, p->nupdblk, M, p->flags_d, p->est_d, p->stream);
+      launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->flags_d + slot * HP_MAXPOLES, p->est_d,
+                     p->stream);
     }
-    for (int k : active) p->m_h[k] += 1;
-    HPCHK(hipMemcpyAsync(p->flags_h, p->flags_d, K * sizeof(int), hipMemcpyDeviceToHost, p->stream));
-    HPCHK(hipStreamSynchronize(p->stream));
-    std::vector<int> next;
-    for (int k : active) {
-      const int f = p->flags_h[k];
-      if (f == 0) {
-        next.push_back(k);
-        continue;
+    HPCHK(hipMemcpyAsync(p->flags_h + slot * HP_MAXPOLES, p->flags_d + slot * HP_MAXPOLES, K * sizeof(int),
+                         hipMemcpyDeviceToHost, p->stream));
+    HPCHK(hipEventRecord(p->iter_ev[slot], p->stream));
+    q.push_back(Flight{poles, slot, next_iter});
+    ++next_iter;
+    return HP_OK;
+  };
+  auto live_list = [&]() {
+    std::vector<int> v;
+    for (int k = 0; k < K; ++k)
+      if (live[k]) v.push_back(k);
+    return v;
+  };
+  {
+    int rc = launch_iter(live_list());
+    if (rc) return rc;
+  }
+  while (!q.empty()) {
+    if (q.size() < 2) {
+      std::vector<int> v = live_list();
+      if (!v.empty()) {
+        int rc = launch_iter(v);
+        if (rc) return rc;
       }
+    }
+    Flight f = q.front();
+    q.erase(q.begin());
+    HPCHK(hipEventSynchronize(p->iter_ev[f.slot]));
+    const int* fl = p->flags_h + f.slot * HP_MAXPOLES;
+    for (int k : f.poles) {
+      if (!live[k] || f.iter < since[k]) continue;
+      const int flag = fl[k];
+      if (flag == 0) continue;
+      live[k] = 0;
+      done_m[k] = (int)(f.iter - since[k] + 1);
       const bool fixed = !p->fixed.empty() && p->fixed[k] > 0;
-      if (fixed || (f == 1 && !p->mixed)) {  // converged on the FP64 estimate (flag 3: verify)
+      if (fixed || (flag == 1 && !p->mixed)) {  // converged on the FP64 estimate
         p->relres[k] = -1.0;
         continue;
       }
-      // verify with the true residual (mixed mode) or restart (cycle ended)
+      // cycle ended without convergence (2), mixed precision, or flag 3: the
+      // true residual decides, and a new cycle starts from it if needed
       if (beta0 < 0) {
-        HPCHK(hipMemcpy(&beta0, &p->st[0].beta0, sizeof(double), hipMemcpyDeviceToHost));
+        HPCHK(hipMemcpyAsync(p->misc_h, &p->st[0].beta0, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HPCHK(hipStreamSynchronize(p->stream));
+        beta0 = p->misc_h[0];
       }
+      p->m_h[k] = done_m[k];
       double res = 0.0;
       int rc = true_residual<T>(p, k, w, &res);
       if (rc) return rc;
+      done_m[k] = 0;
       const double rel = beta0 > 0 ? res / beta0 : 0.0;
       p->relres[k] = rel;
       if (rel <= d.tol) continue;
@@ -437,14 +489,13 @@ int run_step(hp_plan p, const c128* w, c128* out) {
       }
       rc = restart_pole<T>(p, k);
       if (rc) return rc;
-      p->m_h[k] = 0;
-      next.push_back(k);
+      live[k] = 1;
+      since[k] = next_iter;
     }
-    active.swap(next);
   }
   {
     double terms = 0.0;
-    for (int k = 0; k < K; ++k) terms += p->m_h[k];
+    for (int k = 0; k < K; ++k) terms += done_m[k];
     Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
     launch_final<T>(w, out, Zb, zsp, zsi, p->X, fn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta,
                     d.edge_width, p->tw64_x, p->geo, p->stream);
@@ -464,15 +515,15 @@ int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
   int zero = 0;
   HPCHK(hipMemcpyAsync(p->st_scratch, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(p->uptr_scratch, tbl, sizeof(tbl), hipMemcpyHostToDevice, p->stream));
-  HPCHK(hipMemcpyAsync(p->active_d + HP_MAXPOLES - 2, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HPCHK(hipMemcpyAsync(p->active_d + 3 * HP_MAXPOLES - 2, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
   launch_row_fwd<T>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x),
                     p->geo, p->stream);
   // the first basis slot of pole 0 in Z serves as output; the DZ slot as scratch
   cx<T>* zout = reinterpret_cast<cx<T>*>(p->P);
   launch_col<T>(reinterpret_cast<const cx<T>* const*>(p->uptr_scratch), zout, 0, 0, reinterpret_cast<cx<T>*>(p->DZ), 0,
-                p->st_scratch, p->active_d + HP_MAXPOLES - 2, 1, false, p->mu_x, p->mu_y,
+                p->st_scratch, p->active_d + 3 * HP_MAXPOLES - 2, 1, false, p->mu_x, p->mu_y,
                 reinterpret_cast<const cx<T>*>(p->tw_y), p->geo, p->sc, p->stream);
-  launch_row_inv<T>(zout, y, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, p->stream);
+  launch_row_inv<T>(zout, y, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
   HPCHK(hipStreamSynchronize(p->stream));
   return HP_OK;
 }
@@ -567,9 +618,11 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
   w.base = p->ws;
   w.dry = false;
   layout(p, w);
-  if (hipHostMalloc(&p->flags_h, HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+  if (hipHostMalloc(&p->flags_h, 2 * HP_MAXPOLES * sizeof(int)) != hipSuccess ||
       hipHostMalloc(&p->est_h, HP_MAXPOLES * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&p->active_h, HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&p->active_h, 3 * HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&p->iter_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->iter_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(&p->misc_h, (std::max(p->nopblk, p->nrowblk * 2) + 64) * sizeof(double)) != hipSuccess) {
     hp_plan_destroy(p);
     return fail(nullptr, HP_ENOMEM, "pinned host allocation failed");
@@ -747,6 +800,8 @@ void hp_plan_destroy(hp_plan p) {
   if (p->active_h) (void)hipHostFree(p->active_h);
   if (p->misc_h) (void)hipHostFree(p->misc_h);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->iter_ev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 

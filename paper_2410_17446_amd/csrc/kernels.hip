@@ -13,6 +13,11 @@
 //   row pass     p = S_x P S_x z  (+ the inner products with the basis)
 // plus the Gram-Schmidt update.  All dot products, Givens rotations and the
 // residue-weighted sum accumulate in FP64.
+//
+// R-domain fields are stored column-tiled, [nx/TW][ny][TW] with TW elements =
+// 128 bytes, so the row pass reads whole 128-byte lines of each tile and the
+// column pass reads each tile as one contiguous block.  Physical fields (the
+// caller's E, n^2 and the coefficient planes) are row-major [ny][nx].
 #include <math.h>
 
 #include "fft.hpp"
@@ -20,20 +25,36 @@
 
 namespace {
 
+template <typename T>
+struct Tile {
+  static constexpr int W = 128 / (int)sizeof(cx<T>);  // elements per 128-byte tile row
+};
+
+// offset of element (row i, column q) of a tiled field with ny rows
+template <int TW>
+__device__ __forceinline__ size_t tix(int i, int q, int ny) {
+  return ((size_t)(q / TW) * ny + i) * TW + (q % TW);
+}
+
 template <int L>
 struct RowCfg {
-  static constexpr int NT = L / 8;                       // threads per transform
+  static constexpr int NT = L / 8;                           // threads per transform
   static constexpr int RPW = (256 / NT) > 0 ? 256 / NT : 1;  // transforms per workgroup
   static constexpr int WG = RPW * NT;
 };
 
+constexpr int kColLdsBytes = 40960;  // several column workgroups per CU
+
 template <typename T, int L>
 struct ColCfg {
+  static constexpr int TW = Tile<T>::W;
   static constexpr int NT = L / 8;
-  static constexpr int BYTES = L * (int)sizeof(cx<T>);
-  static constexpr int C0 = 65536 / BYTES;
-  static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);  // columns per workgroup
-  static constexpr int WG = C * NT;
+  static constexpr int PB = plen(L) * (int)sizeof(cx<T>);
+  static constexpr int G0 = kColLdsBytes / PB;
+  static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
+  static constexpr int GC = (G1 * NT > 1024) ? 1024 / NT : G1;  // columns transformed at once
+  static constexpr int WG = GC * NT;
+  static constexpr int EPT = ((L / 2 - 1) * TW + WG - 1) / WG;  // tile elements per thread
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -77,26 +98,29 @@ __device__ __forceinline__ double edge_loss(int i, int j, int nx, int ny, int W,
   return exp(-coef * eta * f * f);
 }
 
-// ------------------------------------------------------------------ row forward
+// ------------------------------------------------------------------ row forward (physical -> R-domain)
 
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
                                                            double* __restrict__ part, const cx<T>* __restrict__ tw,
                                                            int ny, size_t fsz, int nblk) {
-  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW, WG = RowCfg<L>::WG;
-  __shared__ cx<T> lds[RPW * L];
+  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW, WG = RowCfg<L>::WG, TW = Tile<T>::W;
+  constexpr int PT = N / NT;
+  __shared__ cx<T> lds[RPW * plen(L)];
   __shared__ double red[(WG + 63) / 64];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = 1 + blockIdx.x * RPW + g;
   const int comp = blockIdx.y;
   const bool valid = row < ny;
-  cx<T>* buf = lds + g * L;
+  cx<T>* buf = lds + g * plen(L);
   const c128* src = in + comp * fsz + (size_t)row * N;
   double nrm = 0.0;
-  for (int m = t; m < N; m += NT) {
+#pragma unroll
+  for (int s = 0; s < PT; ++s) {
+    const int m = t + s * NT;
     cx<T> v = czero<T>();
     if (valid && m > 0) {
-      c128 a = src[m];
+      const c128 a = src[m];
       nrm += abs2(a);
       v = cvt<T>(a);
     }
@@ -106,147 +130,131 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_fwd(const c128* __restric
   fft<T, L>(buf, tw, t);
   const T scale = (T)(1.0 / sqrt(2.0 * N));
   if (valid) {
-    cx<T>* dst = out + comp * fsz + (size_t)row * N;
-    for (int p = t; p < N; p += NT) dst[p] = (p == 0) ? czero<T>() : dst_out(buf, p, scale);
+    cx<T>* dst = out + comp * fsz;
+#pragma unroll
+    for (int s = 0; s < PT; ++s) {
+      const int p = t + s * NT;
+      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : dst_out(buf, p, scale);
+    }
   }
-  double s = block_sum<WG>(nrm, red);
-  if (threadIdx.x == 0) part[comp * nblk + blockIdx.x] = s;
+  double sum = block_sum<WG>(nrm, red);
+  if (threadIdx.x == 0) part[comp * nblk + blockIdx.x] = sum;
 }
 
-// ------------------------------------------------------------------ row inverse (to complex128)
+// ------------------------------------------------------------------ row inverse (R-domain -> physical complex128)
 
-template <typename T, int L>
+template <typename T, int L, int TW>
 __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_inv(const cx<T>* __restrict__ in, c128* __restrict__ out,
                                                            const cx<T>* __restrict__ tw, int ny, size_t fsz) {
   constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW;
-  __shared__ cx<T> lds[RPW * L];
+  constexpr int PT = N / NT;
+  __shared__ cx<T> lds[RPW * plen(L)];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // all rows, row 0 -> zeros
   const int comp = blockIdx.y;
   const bool valid = row < ny && row > 0;
-  cx<T>* buf = lds + g * L;
-  const cx<T>* src = in + comp * fsz + (size_t)row * N;
-  for (int m = t; m < N; m += NT) odd_store(buf, N, m, (valid && m > 0) ? src[m] : czero<T>());
+  cx<T>* buf = lds + g * plen(L);
+  const cx<T>* src = in + comp * fsz;
+#pragma unroll
+  for (int s = 0; s < PT; ++s) {
+    const int m = t + s * NT;
+    odd_store(buf, N, m, (valid && m > 0) ? src[tix<TW>(row, m, ny)] : czero<T>());
+  }
   __syncthreads();
   fft<T, L>(buf, tw, t);
   const T scale = (T)(1.0 / sqrt(2.0 * N));
   if (row < ny) {
     c128* dst = out + comp * fsz + (size_t)row * N;
-    for (int p = t; p < N; p += NT)
+#pragma unroll
+    for (int s = 0; s < PT; ++s) {
+      const int p = t + s * NT;
       dst[p] = (!valid || p == 0) ? mk(0.0, 0.0) : cvt<double>(dst_out(buf, p, scale));
+    }
   }
 }
 
 // ------------------------------------------------------------------ column pass (preconditioner)
+//
+// One workgroup per tile of TW columns (a tile row is one 128-byte line).  The
+// columns go through LDS GC at a time; the GC-column slices of a line that one
+// group reads are followed by the rest of that line in the next groups of the
+// same workgroup, so the line comes from HBM once and from L2 after.
+// SHARED: every active pole reads the same u (the step's first Krylov vector),
+// so the tile is read from HBM once for all poles.
 
 template <typename T, int L, int NC, bool SHARED>
-__global__ __launch_bounds__((ColCfg<T, L>::WG)) void k_col(const cx<T>* const* __restrict__ uptr,
-                                                          cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
-                                                          cx<T>* __restrict__ dzbase, size_t dzsp,
-                                                          const PoleState* __restrict__ st,
-                                                          const int* __restrict__ active, int nactive,
-                                                          const double* __restrict__ mu_x,
-                                                          const double* __restrict__ mu_y,
-                                                          const cx<T>* __restrict__ tw, int nx, size_t fsz,
-                                                          StencilCoef sc) {
-  constexpr int N = L / 2, NT = ColCfg<T, L>::NT, C = ColCfg<T, L>::C, WG = ColCfg<T, L>::WG;
-  constexpr int EPT = ((N - 1) * C + WG - 1) / WG;
-  __shared__ cx<T> lds[C * L];
+__global__ __launch_bounds__((ColCfg<T, L>::WG)) void k_col(
+    const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
+    cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const int* __restrict__ active,
+    int nactive, const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw,
+    int nx, size_t fsz, StencilCoef sc) {
+  using CC = ColCfg<T, L>;
+  constexpr int N = L / 2, NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG;
+  constexpr int PL = plen(L);
+  constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
+  __shared__ cx<T> lds[GC * PL];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int col0 = 1 + tile * C;
+  const int col0 = tile * TW;
   const int comp = blockIdx.y % NC;
-  const int g = threadIdx.x / NT, t = threadIdx.x % NT;
+  const int tid = threadIdx.x;
+  const int g = tid / NT, t = tid % NT;
   const T scale = (T)(1.0 / sqrt(2.0 * N));
   const int first = SHARED ? 0 : blockIdx.y / NC;
   const int last = SHARED ? nactive : first + 1;
-
-  // load the column tile of u (row r = 1 + e / C, column col0 + e % C)
-  {
-    const int k0 = active[first];
-    const int m0 = st[k0].m;
-    const cx<T>* u = uptr[k0 * (HP_MAXM + 1) + m0] + comp * fsz;
-    for (int e = threadIdx.x; e < (N - 1) * C; e += WG) {
-      const int r = 1 + e / C, c = e % C, col = col0 + c;
-      cx<T> v = (col < nx) ? u[(size_t)r * nx + col] : czero<T>();
-      cx<T>* bc = lds + c * L;
-      bc[r] = v;
-      bc[L - r] = -v;
-    }
-    if (threadIdx.x < C) {
-      lds[threadIdx.x * L] = czero<T>();
-      lds[threadIdx.x * L + N] = czero<T>();
-    }
-  }
-  __syncthreads();
-  fft<T, L>(lds + g * L, tw, t);
-  // spectral coefficients of this tile, kept in registers (row p, column c)
-  cx<T> X[EPT];
-#pragma unroll
-  for (int s = 0; s < EPT; ++s) {
-    const int e = threadIdx.x + s * WG;
-    if (e < (N - 1) * C) {
-      const int p = 1 + e / C, c = e % C;
-      X[s] = dst_out(lds + c * L, p, scale);
-    }
-  }
+  const size_t tbase = comp * fsz + (size_t)tile * N * TW;  // this tile, component comp (ny == N)
   for (int a = first; a < last; ++a) {
     const int k = active[a];
+    if (st[k].flag) continue;
     const int m = st[k].m;
     const c128 b = st[k].bk;
-    const T sig = (T)st[k].sigma[m];
-    __syncthreads();  // everyone is done reading lds
-#pragma unroll
-    for (int s = 0; s < EPT; ++s) {
-      const int e = threadIdx.x + s * WG;
-      if (e < (N - 1) * C) {
-        const int p = 1 + e / C, c = e % C, q = col0 + c;
-        const double lr = mu_y[p] + (q < nx ? mu_x[q] : 0.0) - b.re, li = -b.im;
+    const T sc2 = (T)st[k].sigma[m] * scale;
+    const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
+    cx<T>* z = zbase + k * zsp + m * zsi + tbase;
+    cx<T>* dz = (NC == 2) ? dzbase + k * dzsp + tbase : nullptr;
+#pragma unroll 1
+    for (int c0 = 0; c0 < TW; c0 += GC) {
+      __syncthreads();
+      for (int e = tid; e < NE; e += WG) {
+        const int r = 1 + e / GC, c = e % GC;
+        const cx<T> v = u[(size_t)r * TW + c0 + c];
+        cx<T>* bc = lds + c * PL;
+        bc[pidx(r)] = v;
+        bc[pidx(L - r)] = -v;
+      }
+      if (tid < GC) {
+        lds[tid * PL + pidx(0)] = czero<T>();
+        lds[tid * PL + pidx(N)] = czero<T>();
+      }
+      __syncthreads();
+      fft<T, L>(lds + g * PL, tw, t);
+      // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
+      for (int e = tid; e < NE; e += WG) {
+        const int p = 1 + e / GC, c = e % GC, q = col0 + c0 + c;
+        cx<T>* bc = lds + c * PL;
+        const cx<T> X = dst_out(bc, p, scale);
+        const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
         const double den = lr * lr + li * li;
-        const cx<T> inv = mk<T>((T)(lr / den), (T)(-li / den));
-        const cx<T> zt = X[s] * inv;
-        cx<T>* bc = lds + c * L;
-        bc[p] = zt;
-        bc[L - p] = -zt;
+        const cx<T> zt = X * mk<T>((T)(lr / den), (T)(-li / den));
+        bc[pidx(p)] = zt;
+        bc[pidx(L - p)] = -zt;
       }
-    }
-    if (threadIdx.x < C) {
-      lds[threadIdx.x * L] = czero<T>();
-      lds[threadIdx.x * L + N] = czero<T>();
-    }
-    __syncthreads();
-    fft<T, L>(lds + g * L, tw, t);
-    cx<T>* z = zbase + k * zsp + m * zsi + comp * fsz;
-    const T sc2 = sig * scale;
-#pragma unroll
-    for (int s = 0; s < EPT; ++s) {
-      const int e = threadIdx.x + s * WG;
-      if (e < (N - 1) * C) {
-        const int p = 1 + e / C, c = e % C, col = col0 + c;
-        if (col < nx) z[(size_t)p * nx + col] = sc2 * mul_i(lds[c * L + p]);
+      if (tid < GC) {
+        lds[tid * PL + pidx(0)] = czero<T>();
+        lds[tid * PL + pidx(N)] = czero<T>();
       }
-    }
-    if constexpr (NC == 2) {
-      // D1y of the physical-in-y column (odd reflection about rows 0 and N)
-      cx<T>* dz = dzbase + k * dzsp + comp * fsz;
-#pragma unroll
-      for (int s = 0; s < EPT; ++s) {
-        const int e = threadIdx.x + s * WG;
-        if (e < (N - 1) * C) {
-          const int p = 1 + e / C, c = e % C, col = col0 + c;
-          const cx<T>* bc = lds + c * L;
+      __syncthreads();
+      fft<T, L>(lds + g * PL, tw, t);
+      for (int e = tid; e < NE; e += WG) {
+        const int p = 1 + e / GC, c = e % GC;
+        const cx<T>* bc = lds + c * PL;
+        z[(size_t)p * TW + c0 + c] = sc2 * mul_i(bc[pidx(p)]);
+        if constexpr (NC == 2) {
+          // D1y of the column, physical in y (odd reflection about rows 0 and N)
           cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
-          for (int mm = 1; mm <= 6; ++mm) {
-            int ip = p + mm, im = p - mm;
-            cx<T> zp = czero<T>(), zm = czero<T>();
-            if (ip < N) zp = bc[ip];
-            else if (ip > N) zp = -bc[2 * N - ip];
-            if (im > 0) zm = bc[im];
-            else if (im < 0) zm = -bc[-im];
-            cx<T> dif = zp - zm;
-            acc = acc + sc.d1y[mm - 1] * cvt<double>(dif);
-          }
-          if (col < nx) dz[(size_t)p * nx + col] = sc2 * mul_i(cvt<T>(acc));
+          for (int mm = 1; mm <= 6; ++mm)
+            acc = acc + sc.d1y[mm - 1] * cvt<double>(odd_at(bc, N, p + mm) - odd_at(bc, N, p - mm));
+          dz[(size_t)p * TW + c0 + c] = sc2 * mul_i(cvt<T>(acc));
         }
       }
     }
@@ -262,32 +270,41 @@ struct ApplyCfg {
   static constexpr int GROUPS = G0 < NC ? NC : G0;  // transforms per workgroup (NC per row)
   static constexpr int ROWS = GROUPS / NC;
   static constexpr int WG = GROUPS * NT;
+  static constexpr int WAVES = (WG + 63) / 64;
 };
 
 template <typename T, int L, int NC>
 __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
     cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const double* __restrict__ coef,
-    const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nblk,
+    const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
     const cx<T>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
-  constexpr int N = L / 2, NT = ApplyCfg<L, NC>::NT, GROUPS = ApplyCfg<L, NC>::GROUPS;
-  constexpr int ROWS = ApplyCfg<L, NC>::ROWS, WG = ApplyCfg<L, NC>::WG;
+  using AC = ApplyCfg<L, NC>;
+  constexpr int N = L / 2, NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
   constexpr int PT = N / NT;  // values per thread per row
-  __shared__ cx<T> lds[GROUPS * L];
-  __shared__ double red[(WG + 63) / 64];
+  constexpr int PL = plen(L);
+  __shared__ cx<T> lds[GROUPS * PL];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int comp = g % NC;
   const int row = 1 + blockIdx.x * ROWS + g / NC;
   const bool valid = row < ny;
   const int k = active[blockIdx.y];
+  if (st[k].flag) return;
   const int m = st[k].m;
-  cx<T>* buf = lds + g * L;
+  cx<T>* buf = lds + g * PL;
   const T scale = (T)(1.0 / sqrt(2.0 * N));
-  const size_t roff = comp * fsz + (size_t)row * N;
-  const size_t ci0 = (size_t)row * N;
+  const size_t cbase = comp * fsz;
+  const size_t ci0 = (size_t)row * N;  // physical row offset
+  size_t toff[PT];                     // tiled offsets of the thread's points
+#pragma unroll
+  for (int s = 0; s < PT; ++s) toff[s] = cbase + tix<TW>(valid ? row : 0, t + s * NT, ny);
 
   const cx<T>* z = zbase + k * zsp + m * zsi;
-  for (int j = t; j < N; j += NT) odd_store(buf, N, j, (valid && j > 0) ? z[roff + j] : czero<T>());
+#pragma unroll
+  for (int s = 0; s < PT; ++s) {
+    const int j = t + s * NT;
+    odd_store(buf, N, j, (valid && j > 0) ? z[toff[s]] : czero<T>());
+  }
   __syncthreads();
   fft<T, L>(buf, tw, t);
   cx<T> pz[PT];  // P z at the thread's points j = t + s * NT
@@ -310,20 +327,17 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
       zc[s] = (j == 0) ? czero<T>() : dst_out(buf, j, scale);
       cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
-      for (int mm = 1; mm <= 6; ++mm) {
-        const int jp = j + mm, jm = j - mm;
-        cx<T> a = czero<T>(), b = czero<T>();
-        if (jp < N) a = buf[jp];
-        else if (jp > N) a = -buf[2 * N - jp];
-        if (jm > 0) b = buf[jm];
-        else if (jm < 0) b = -buf[-jm];
-        acc = acc + sc.d1x[mm - 1] * cvt<double>(a - b);
-      }
+      for (int mm = 1; mm <= 6; ++mm)
+        acc = acc + sc.d1x[mm - 1] * cvt<double>(odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
       dxz[s] = (j == 0) ? czero<T>() : scale * mul_i(cvt<T>(acc));
     }
     __syncthreads();
     const cx<T>* dz = dzbase + k * dzsp;
-    for (int j = t; j < N; j += NT) odd_store(buf, N, j, (valid && j > 0) ? dz[roff + j] : czero<T>());
+#pragma unroll
+    for (int s = 0; s < PT; ++s) {
+      const int j = t + s * NT;
+      odd_store(buf, N, j, (valid && j > 0) ? dz[toff[s]] : czero<T>());
+    }
     __syncthreads();
     fft<T, L>(buf, tw, t);
 #pragma unroll
@@ -336,11 +350,11 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      buf[j] = zc[s];
-      buf[N + j] = (comp == 0) ? dyz[s] : dxz[s];
+      buf[pidx(j)] = zc[s];
+      buf[pidx(N + j)] = (comp == 0) ? dyz[s] : dxz[s];
     }
     __syncthreads();
-    const cx<T>* other = lds + (g ^ 1) * L;
+    const cx<T>* other = lds + (g ^ 1) * PL;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
@@ -351,7 +365,7 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
       const size_t ci = ci0 + j;
       const T v = (T)coef[ci], px = (T)coef[fsz + ci], py = (T)coef[2 * fsz + ci];
       const T pxx = (T)coef[3 * fsz + ci], pyy = (T)coef[4 * fsz + ci], pxy = (T)coef[5 * fsz + ci];
-      const cx<T> zo = other[j], dzo = other[N + j];
+      const cx<T> zo = other[pidx(j)], dzo = other[pidx(N + j)];
       if (comp == 0)
         pz[s] = pxx * zc[s] + px * dxz[s] + pxy * zo + py * dzo + v * zc[s];
       else
@@ -370,41 +384,42 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
     pv[s] = (j == 0 || !valid) ? czero<T>() : dst_out(buf, j, scale);
-    if (valid) p[roff + j] = pv[s];
+    if (valid) p[toff[s]] = pv[s];
   }
-  // <u_i, p> and <u_i, u_m>, i = 0..m, summed over the workgroup (rows and
-  // components): the new direction's projections and the reorthogonalisation
-  // of the provisional u_m, from the same reads of the basis.
+  // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
+  // the reorthogonalisation of the provisional u_m, from the same reads of the
+  // basis.  Partial sums per wave (no workgroup barrier).
   cx<T> um[PT];
   {
     const cx<T>* u = uptr[k * (HP_MAXM + 1) + m];
 #pragma unroll
-    for (int s = 0; s < PT; ++s) um[s] = valid ? u[roff + t + s * NT] : czero<T>();
+    for (int s = 0; s < PT; ++s) um[s] = valid ? u[toff[s]] : czero<T>();
   }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = blockIdx.x * AC::WAVES + wave;
   for (int i = 0; i <= m; ++i) {
     const cx<T>* u = uptr[k * (HP_MAXM + 1) + i];
     double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
     if (valid) {
 #pragma unroll
       for (int s = 0; s < PT; ++s) {
-        const int j = t + s * NT;
-        const cx<double> a = cvt<double>(i == m ? um[s] : u[roff + j]);
-        const cx<double> b = cvt<double>(pv[s]);
-        const cx<double> c = cvt<double>(um[s]);
-        pr += a.re * b.re + a.im * b.im;
-        pi += a.re * b.im - a.im * b.re;
-        qr += a.re * c.re + a.im * c.im;
-        qi += a.re * c.im - a.im * c.re;
+        const cx<double> a = cvt<double>(i == m ? um[s] : u[toff[s]]);
+        const cx<double> bp = cvt<double>(pv[s]);
+        const cx<double> bq = cvt<double>(um[s]);
+        pr += a.re * bp.re + a.im * bp.im;
+        pi += a.re * bp.im - a.im * bp.re;
+        qr += a.re * bq.re + a.im * bq.im;
+        qi += a.re * bq.im - a.im * bq.re;
       }
     }
-    pr = block_sum<WG>(pr, red);
-    pi = block_sum<WG>(pi, red);
-    qr = block_sum<WG>(qr, red);
-    qi = block_sum<WG>(qi, red);
-    if (threadIdx.x == 0) {
-      const size_t base = (((size_t)k * (HP_MAXM + 1) + i) * 2) * nblk + blockIdx.x;
+    pr = wave_sum(pr);
+    pi = wave_sum(pi);
+    qr = wave_sum(qr);
+    qi = wave_sum(qi);
+    if (lane == 0) {
+      const size_t base = (((size_t)k * (HP_MAXM + 1) + i) * 2) * nparts + slot;
       part[base] = make_double2(pr, pi);
-      part[base + nblk] = make_double2(qr, qi);
+      part[base + nparts] = make_double2(qr, qi);
     }
   }
 }
@@ -425,6 +440,7 @@ __global__ __launch_bounds__(UPD_WG) void k_update(const cx<T>* __restrict__ pba
   __shared__ cx<T>* up[HP_MAXM + 2];
   __shared__ double red[UPD_WG / 64];
   const int k = active[blockIdx.y];
+  if (st[k].flag) return;
   const int m = st[k].m;
   const int corr = st[k].correct;
   for (int i = threadIdx.x; i <= m + 1; i += UPD_WG) {
@@ -465,83 +481,104 @@ __global__ __launch_bounds__(UPD_WG) void k_update(const cx<T>* __restrict__ pba
 //   A M^-1 v_m = (~v_m + p - sum_i s_i A M^-1 v_i) / rho   (A M^-1 ~v_m = ~v_m + p),
 //   H[l][m] = <v_l, A M^-1 v_m>, u_{m+1} = A M^-1 v_m - sum_l H[l][m] v_l,
 // expressed as coefficients of the stored vectors for the update kernel.
-__global__ __launch_bounds__(256) void k_reduce_prep(const double2* __restrict__ part, int nblk,
-                                                     PoleState* __restrict__ st, const int* __restrict__ active) {
+// <u_i, p> and <u_i, u_m>: one block per (i, slot) pair sums the row pass's
+// partials in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double2* __restrict__ part, int nparts,
+                                                      PoleState* __restrict__ st, const int* __restrict__ active) {
   __shared__ double red[4];
-  __shared__ c128 P[HP_MAXM + 1], Q[HP_MAXM + 1];
-  const int k = active[blockIdx.x];
+  const int k = active[blockIdx.y];
+  if (st[k].flag) return;
   const int m = st[k].m;
-  for (int i = 0; i <= m; ++i) {
-    for (int slot = 0; slot < 2; ++slot) {
-      const double2* src = part + (((size_t)k * (HP_MAXM + 1) + i) * 2 + slot) * nblk;
-      double re = 0.0, im = 0.0;
-      for (int b = threadIdx.x; b < nblk; b += 256) {
-        re += src[b].x;
-        im += src[b].y;
-      }
-      re = block_sum<256>(re, red);
-      im = block_sum<256>(im, red);
-      if (threadIdx.x == 0) (slot ? Q : P)[i] = mk(re, im);
-    }
+  const int i = blockIdx.x >> 1, slot = blockIdx.x & 1;
+  if (i > m) return;
+  const double2* src = part + (((size_t)k * (HP_MAXM + 1) + i) * 2 + slot) * nparts;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    re += src[b].x;
+    im += src[b].y;
   }
-  if (threadIdx.x != 0) return;
+  re = block_sum<256>(re, red);
+  im = block_sum<256>(im, red);
+  if (threadIdx.x == 0) (slot ? st[k].Qd : st[k].Pd)[i] = mk(re, im);
+}
+
+__global__ __launch_bounds__(256) void k_prep(PoleState* __restrict__ st, const int* __restrict__ active) {
+  __shared__ c128 P[HP_MAXM + 1], Q[HP_MAXM + 1];
+  __shared__ c128 sv[HP_MAXM], cc[HP_MAXM + 1], h[HP_MAXM + 1];
+  const int k = active[blockIdx.x];
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  for (int i = threadIdx.x; i <= m; i += 256) {
+    P[i] = st[k].Pd[i];
+    Q[i] = st[k].Qd[i];
+  }
+  __syncthreads();
   PoleState& S = st[k];
   constexpr int LD = HP_MAXM + 1;
   c128* Hr = S.Hraw;
+  __shared__ double sh[4];  // rho, gamma (re, im), h~
+  __shared__ double sig[HP_MAXM + 1];
+  const int tid = threadIdx.x;
   const double sm = S.sigma[m];
-  c128 sv[HP_MAXM], cc[HP_MAXM + 1];
-  double ssum = 0.0;
-  for (int i = 0; i < m; ++i) {
-    sv[i] = (S.sigma[i] * sm) * Q[i];
-    ssum += abs2(sv[i]);
-    cc[i] = S.sigma[i] * P[i];
+  for (int i = tid; i <= m; i += 256) sig[i] = S.sigma[i];
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    sv[i] = (sig[i] * sm) * Q[i];
+    cc[i] = sig[i] * P[i];
   }
-  const double t = sm * sm * Q[m].re;
-  double rho2 = t - ssum;
-  if (!(rho2 > 1e-300)) rho2 = 1e-300;
-  const double rho = sqrt(rho2);
-  for (int i = 0; i < m; ++i) S.Rc[i + m * LD] = sv[i];
-  S.Rc[m + m * LD] = mk(rho, 0.0);
-  if (m == 0) {
-    S.g[0] = rho * S.g[0];
-  } else {
-    const double ht = Hr[m + (m - 1) * LD].re;
-    for (int i = 0; i < m; ++i) Hr[i + (m - 1) * LD] = Hr[i + (m - 1) * LD] + ht * sv[i];
-    Hr[m + (m - 1) * LD] = mk(ht * rho, 0.0);
+  __syncthreads();
+  if (tid == 0) {
+    double ssum = 0.0;
+    for (int i = 0; i < m; ++i) ssum += abs2(sv[i]);
+    double rho2 = sm * sm * Q[m].re - ssum;
+    if (!(rho2 > 1e-300)) rho2 = 1e-300;
+    const double rho = sqrt(rho2);
+    c128 cm = sm * P[m];
+    for (int i = 0; i < m; ++i) cm = cm - cmulc(sv[i], cc[i]);
+    cc[m] = (1.0 / rho) * cm;
+    sh[0] = rho;
+    sh[3] = (m > 0) ? Hr[m + (m - 1) * LD].re : 0.0;
+    S.Rc[m + m * LD] = mk(rho, 0.0);
+    if (m == 0) S.g[0] = rho * S.g[0];
   }
-  c128 cm = sm * P[m];
-  for (int i = 0; i < m; ++i) cm = cm - cmulc(sv[i], cc[i]);
-  cc[m] = (1.0 / rho) * cm;
-  // A_l = sum_{i<m, i>=l-1} s_i H[l][i]
-  c128 h[HP_MAXM + 1];
-  double gam_re = 0.0, gam_im = 0.0;
-  for (int l = 0; l <= m; ++l) {
+  __syncthreads();
+  const double rho = sh[0], irho = 1.0 / rho;
+  // Rc column m; correction of Hessenberg column m-1
+  for (int i = tid; i < m; i += 256) {
+    S.Rc[i + m * LD] = sv[i];
+    Hr[i + (m - 1) * LD] = Hr[i + (m - 1) * LD] + sh[3] * sv[i];
+  }
+  __syncthreads();
+  if (tid == 0 && m > 0) Hr[m + (m - 1) * LD] = mk(sh[3] * rho, 0.0);
+  __syncthreads();
+  // column m: h_l = (<v_l, ~v_m> + <v_l, p> - A_l) / rho, A_l = sum_{i<m, i>=l-1} s_i H[l][i]
+  for (int l = tid; l <= m; l += 256) {
     c128 A = mk(0.0, 0.0);
     for (int i = (l > 0 ? l - 1 : 0); i < m; ++i) A = A + sv[i] * Hr[l + i * LD];
-    c128 base = (l < m) ? sv[l] + cc[l] : mk(rho, 0.0) + cc[m];
-    h[l] = (1.0 / rho) * (base - A);
+    const c128 base = (l < m) ? sv[l] + cc[l] : mk(rho, 0.0) + cc[m];
+    h[l] = irho * (base - A);
     Hr[l + m * LD] = h[l];
-    if (l == m) {
-      const c128 gam = (1.0 / rho) * A + h[m];
-      gam_re = gam.re;
-      gam_im = gam.im;
-    }
-    // coefficient of v_l (l < m) without the gamma term: -(A_l / rho + h_l)
-    if (l < m) S.cu[l] = -1.0 * ((1.0 / rho) * A + h[l]);
+    P[l] = irho * A + h[l];  // A_l / rho + h_l (P no longer needed)
   }
-  const c128 gam = mk(gam_re, gam_im);
-  for (int l = 0; l < m; ++l) S.cu[l] = S.sigma[l] * (S.cu[l] + (1.0 / rho) * (gam * sv[l]));
-  S.cu[m] = (sm / rho) * (mk(1.0, 0.0) - gam);
-  S.cu[m + 1] = mk(1.0 / rho, 0.0);
-  if (m == 0) {
-    // v_0 = ~v_0 / rho is a rescale of the (possibly shared) stored vector
-    S.sigma[0] = sm / rho;
-    S.correct = 0;
-  } else {
-    for (int i = 0; i < m; ++i) S.cv[i] = (-S.sigma[i] / rho) * sv[i];
-    S.cv[m] = mk(sm / rho, 0.0);
-    S.sigma[m] = 1.0;
-    S.correct = 1;
+  __syncthreads();
+  const c128 gam = P[m];
+  // u_{m+1} = (1/rho) p + (1 - gam)/rho ~v_m + sum_{l<m} (gam s_l / rho - A_l / rho - h_l) v_l
+  for (int l = tid; l < m; l += 256) {
+    S.cu[l] = sig[l] * (irho * (gam * sv[l]) - P[l]);
+    S.cv[l] = (-sig[l] * irho) * sv[l];
+  }
+  if (tid == 0) {
+    S.cu[m] = (sm * irho) * (mk(1.0, 0.0) - gam);
+    S.cu[m + 1] = mk(irho, 0.0);
+    if (m == 0) {
+      // v_0 = ~v_0 / rho rescales the (possibly shared) stored vector
+      S.sigma[0] = sm * irho;
+      S.correct = 0;
+    } else {
+      S.cv[m] = mk(sm * irho, 0.0);
+      S.sigma[m] = 1.0;
+      S.correct = 1;
+    }
   }
 }
 
@@ -561,95 +598,136 @@ __device__ __forceinline__ void givens(c128 a, double b, double& c, c128& sn, c1
   r = c * a + b * sn;
 }
 
+// Back substitution R x = rhs (R upper triangular, column-major with leading
+// dimension HP_MAXM + 1), column by column with the 64 threads of the block.
+__device__ void upper_solve(const c128* __restrict__ R, c128* rhs, c128* x, int n) {
+  constexpr int LD = HP_MAXM + 1;
+  for (int i = n - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const c128 d = R[i + i * LD];
+      x[i] = (abs2(d) > 0.0) ? cdiv(rhs[i], d) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    const c128 xi = x[i];
+    for (int l = threadIdx.x; l < i; l += 64) rhs[l] = rhs[l] - R[l + i * LD] * xi;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, const int* __restrict__ active,
                                                 const double* __restrict__ part, int nblk, int restart,
                                                 int* __restrict__ flags, double* __restrict__ ests) {
+  __shared__ c128 c1[HP_MAXM + 2], c2[HP_MAXM + 2], sn[HP_MAXM], rhs[HP_MAXM + 1], y[HP_MAXM];
+  __shared__ double cs[HP_MAXM];
+  __shared__ int flag_s;
   const int k = active[blockIdx.x];
+  if (st[k].flag) return;
+  const int tid = threadIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(size_t)k * nblk + b];
+  for (int b = tid; b < nblk; b += 64) s += part[(size_t)k * nblk + b];
   s = wave_sum(s);
-  if (threadIdx.x != 0) return;
   PoleState& S = st[k];
   constexpr int LD = HP_MAXM + 1;
   const int m = S.m;
-  const double h = sqrt(s);
-  S.Hraw[m + 1 + m * LD] = mk(h, 0.0);
-  if (m >= 1) {
-    // column m-1 was corrected by the reorthogonalisation: redo its rotation
-    c128* col = S.H + (m - 1) * LD;
-    for (int i = 0; i <= m; ++i) col[i] = S.Hraw[i + (m - 1) * LD];
-    for (int i = 0; i < m - 1; ++i) {
-      const c128 a = col[i], b = col[i + 1];
-      col[i] = S.cs[i] * a + S.sn[i] * b;
-      col[i + 1] = -1.0 * cmulc(S.sn[i], a) + S.cs[i] * b;
+  for (int i = tid; i <= m; i += 64) {
+    c2[i] = S.Hraw[i + m * LD];
+    if (m >= 1) c1[i] = S.Hraw[i + (m - 1) * LD];
+  }
+  for (int i = tid; i < m; i += 64) {
+    cs[i] = S.cs[i];
+    sn[i] = S.sn[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double h = sqrt(s);
+    S.Hraw[m + 1 + m * LD] = mk(h, 0.0);
+    c2[m + 1] = mk(h, 0.0);
+    if (m >= 1) {
+      // column m-1 was corrected by the reorthogonalisation: redo its rotation
+      for (int i = 0; i < m - 1; ++i) {
+        const c128 a = c1[i], b = c1[i + 1];
+        c1[i] = cs[i] * a + sn[i] * b;
+        c1[i + 1] = -1.0 * cmulc(sn[i], a) + cs[i] * b;
+      }
+      double c;
+      c128 snn, r;
+      givens(c1[m - 1], c1[m].re, c, snn, r);
+      cs[m - 1] = c;
+      sn[m - 1] = snn;
+      c1[m - 1] = r;
+      c1[m] = mk(0.0, 0.0);
+      S.g[m - 1] = c * S.gpre[m - 1];
+      S.g[m] = -1.0 * cmulc(snn, S.gpre[m - 1]);
+    }
+    for (int i = 0; i < m; ++i) {
+      const c128 a = c2[i], b = c2[i + 1];
+      c2[i] = cs[i] * a + sn[i] * b;
+      c2[i + 1] = -1.0 * cmulc(sn[i], a) + cs[i] * b;
     }
     double c;
-    c128 sn, r;
-    givens(col[m - 1], col[m].re, c, sn, r);
-    S.cs[m - 1] = c;
-    S.sn[m - 1] = sn;
-    col[m - 1] = r;
-    col[m] = mk(0.0, 0.0);
-    S.g[m - 1] = c * S.gpre[m - 1];
-    S.g[m] = -1.0 * cmulc(sn, S.gpre[m - 1]);
+    c128 snn, r;
+    givens(c2[m], h, c, snn, r);
+    cs[m] = c;
+    sn[m] = snn;
+    c2[m] = r;
+    c2[m + 1] = mk(0.0, 0.0);
+    S.gpre[m] = S.g[m];
+    S.g[m + 1] = -1.0 * cmulc(snn, S.g[m]);
+    S.g[m] = c * S.g[m];
+    S.sigma[m + 1] = (h > 0.0) ? 1.0 / h : 0.0;
+    S.est = sqrt(abs2(S.g[m + 1]));
+    S.m = m + 1;
+    S.total += 1;
+    int flag = 0;
+    if (S.fixed > 0) {
+      if (S.m >= S.fixed) flag = 1;
+    } else if (S.est <= S.tol || h == 0.0) {
+      flag = 1;
+    } else if (S.m >= restart) {
+      flag = 2;
+    }
+    flag_s = flag;
   }
-  c128* col = S.H + m * LD;
-  for (int i = 0; i <= m + 1; ++i) col[i] = S.Hraw[i + m * LD];
-  for (int i = 0; i < m; ++i) {
-    const c128 a = col[i], b = col[i + 1];
-    col[i] = S.cs[i] * a + S.sn[i] * b;
-    col[i + 1] = -1.0 * cmulc(S.sn[i], a) + S.cs[i] * b;
+  __syncthreads();
+  for (int i = tid; i <= m + 1; i += 64) {
+    S.H[i + m * LD] = c2[i];
+    if (m >= 1 && i <= m) S.H[i + (m - 1) * LD] = c1[i];
   }
-  double c;
-  c128 sn, r;
-  givens(col[m], h, c, sn, r);
-  S.cs[m] = c;
-  S.sn[m] = sn;
-  col[m] = r;
-  col[m + 1] = mk(0.0, 0.0);
-  S.gpre[m] = S.g[m];
-  S.g[m + 1] = -1.0 * cmulc(sn, S.g[m]);
-  S.g[m] = c * S.g[m];
-  S.sigma[m + 1] = (h > 0.0) ? 1.0 / h : 0.0;
-  S.est = sqrt(abs2(S.g[m + 1]));
-  S.m = m + 1;
-  S.total += 1;
-  int flag = 0;
-  if (S.fixed > 0) {
-    if (S.m >= S.fixed) flag = 1;
-  } else if (S.est <= S.tol || h == 0.0) {
-    flag = 1;
-  } else if (S.m >= restart) {
-    flag = 2;
+  if (tid == 0 && m >= 1) {
+    S.cs[m - 1] = cs[m - 1];
+    S.sn[m - 1] = sn[m - 1];
   }
-  S.flag = flag;
+  if (tid == 0) {
+    S.cs[m] = cs[m];
+    S.sn[m] = sn[m];
+  }
+  int flag = flag_s;
   if (flag) {
     // least squares R y = g, then y~ = Rc^{-1} y (the coefficients of the stored Z~)
-    const int n = S.m;
-    c128 y[HP_MAXM];
-    for (int i = n - 1; i >= 0; --i) {
-      c128 acc = S.g[i];
-      for (int l = i + 1; l < n; ++l) acc = acc - S.H[i + l * LD] * y[l];
-      const c128 d = S.H[i + i * LD];
-      y[i] = (abs2(d) > 0.0) ? cdiv(acc, d) : mk(0.0, 0.0);
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      c128 acc = y[i];
-      for (int l = i + 1; l < n; ++l) acc = acc - S.Rc[i + l * LD] * S.y[l];
-      S.y[i] = cdiv(acc, S.Rc[i + i * LD]);
-    }
+    const int n = m + 1;
+    __threadfence_block();
+    __syncthreads();
+    for (int i = tid; i < n; i += 64) rhs[i] = S.g[i];
+    __syncthreads();
+    upper_solve(S.H, rhs, y, n);
+    for (int i = tid; i < n; i += 64) rhs[i] = y[i];
+    __syncthreads();
+    upper_solve(S.Rc, rhs, y, n);
+    for (int i = tid; i < n; i += 64) S.y[i] = y[i];
     // The estimate measures the split operator I + P M~^-1; it differs from
     // A M~^-1 by about eps kappa(M_k) ||y|| (||y|| = ||M x||).  When that is not
     // well below tol, the true residual decides.
-    if (flag == 1 && S.fixed == 0) {
+    if (tid == 0 && flag == 1 && S.fixed == 0) {
       double yn = 0.0;
-      for (int i = 0; i < n; ++i) yn += abs2(y[i]);
+      for (int i = 0; i < n; ++i) yn += abs2(rhs[i]);
       if (S.incons * sqrt(yn) > 0.1 * S.tol) flag = 3;
-      S.flag = flag;
     }
   }
-  flags[k] = flag;
-  ests[k] = S.est;
+  if (tid == 0) {
+    S.flag = flag;
+    flags[k] = flag;
+    ests[k] = S.est;
+  }
 }
 
 __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, const int* __restrict__ poles,
@@ -682,6 +760,8 @@ __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, c
 
 // ------------------------------------------------------------------ residue-weighted sum and output
 
+// ------------------------------------------------------------------ residue-weighted sum and output
+
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::WG) void k_final(const c128* __restrict__ w, c128* __restrict__ out,
                                                          const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
@@ -689,15 +769,18 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_final(const c128* __restrict_
                                                          const PoleState* __restrict__ st, int npoles, c128 phase,
                                                          c128 rinf_phase, double loss_coef, double eta, int W,
                                                          const c128* __restrict__ tw, int nx, int ny, size_t fsz) {
-  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW;
+  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW, TW = Tile<T>::W;
   constexpr int PT = N / NT;
-  __shared__ c128 lds[RPW * L];
+  __shared__ c128 lds[RPW * plen(L)];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // rows 0..ny-1
   const int comp = blockIdx.y;
   const bool valid = row > 0 && row < ny;
-  c128* buf = lds + g * L;
+  c128* buf = lds + g * plen(L);
   const size_t roff = comp * fsz + (size_t)row * N;
+  size_t toff[PT];
+#pragma unroll
+  for (int s = 0; s < PT; ++s) toff[s] = comp * fsz + tix<TW>(valid ? row : 0, t + s * NT, ny);
   c128 acc[PT];
 #pragma unroll
   for (int s = 0; s < PT; ++s) acc[s] = mk(0.0, 0.0);
@@ -705,17 +788,17 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_final(const c128* __restrict_
     for (int k = 0; k < npoles; ++k) {
       const c128 ak = st[k].ak;
       if (st[k].has_x) {
-        const c128* xk = xacc + k * xsp + roff;
+        const c128* xk = xacc + k * xsp;
 #pragma unroll
-        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + ak * xk[t + s * NT];
+        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + ak * xk[toff[s]];
       }
       const int mk_ = st[k].m;
-      const cx<T>* zk = zbase + k * zsp + roff;
+      const cx<T>* zk = zbase + k * zsp;
       for (int i = 0; i < mk_; ++i) {
         const c128 cf = ak * st[k].y[i];
         const cx<T>* zi = zk + i * zsi;
 #pragma unroll
-        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + cf * cvt<double>(zi[t + s * NT]);
+        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + cf * cvt<double>(zi[toff[s]]);
       }
     }
   }
@@ -922,11 +1005,15 @@ void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, c
 }
 
 template <typename T>
-void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, hipStream_t s) {
+void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, int tile_w, hipStream_t s) {
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny + rpw - 1) / rpw;
   dim3 grid(nblk, g.ncomp);
-#define L_(LL) hipLaunchKernelGGL((k_row_inv<T, LL>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, tw, g.ny, g.fsz)
+#define L_(LL)                                                                                                  \
+  if (tile_w == 8)                                                                                              \
+    hipLaunchKernelGGL((k_row_inv<T, LL, 8>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_row_inv<T, LL, 16>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, tw, g.ny, g.fsz);
   HP_DISPATCH_L(g.nx, L_)
 #undef L_
 }
@@ -937,8 +1024,8 @@ void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, 
                 const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s) {
 #define L_(LL)                                                                                               \
   {                                                                                                          \
-    constexpr int C = ColCfg<T, LL>::C;                                                                      \
-    dim3 grid((g.nx - 1 + C - 1) / C, g.ncomp * (shared ? 1 : nactive));                                    \
+    constexpr int TW_ = ColCfg<T, LL>::TW;                                                                   \
+    dim3 grid(g.nx / TW_, g.ncomp * (shared ? 1 : nactive));                                                 \
     if (g.ncomp == 1) {                                                                                      \
       if (shared)                                                                                            \
         hipLaunchKernelGGL((k_col<T, LL, 1, true>), grid, dim3(ColCfg<T, LL>::WG), 0, s, uptr, zbase, zsp,   \
@@ -969,27 +1056,36 @@ int row_apply_blocks(const Geo& g) {
 }
 
 template <typename T>
+int row_apply_parts(const Geo& g) {
+  const int nt = (2 * g.nx) / 8;
+  int groups = 256 / nt;
+  if (groups < g.ncomp) groups = g.ncomp;
+  return row_apply_blocks<T>(g) * ((groups * nt + 63) / 64);
+}
+
+template <typename T>
 void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
                       size_t psp, const cx<T>* const* uptr, const double* coef, const PoleState* st,
                       const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
                       const StencilCoef& sc, hipStream_t s) {
   const int nblk = row_apply_blocks<T>(g);
+  const int nparts = row_apply_parts<T>(g);
   dim3 grid(nblk, nactive);
 #define L_(LL)                                                                                                  \
   if (g.ncomp == 1)                                                                                             \
     hipLaunchKernelGGL((k_row_apply<T, LL, 1>), grid, dim3(ApplyCfg<LL, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
-                       dzsp, pbase, psp, uptr, coef, st, active, part, nblk, tw, g.ny, g.fsz, sc);              \
+                       dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);            \
   else                                                                                                          \
     hipLaunchKernelGGL((k_row_apply<T, LL, 2>), grid, dim3(ApplyCfg<LL, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
-                       dzsp, pbase, psp, uptr, coef, st, active, part, nblk, tw, g.ny, g.fsz, sc);
+                       dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);
   HP_DISPATCH_L(g.nx, L_)
 #undef L_
 }
 
 void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int* active, int nactive, int maxm,
                         hipStream_t s) {
-  (void)maxm;
-  hipLaunchKernelGGL(k_reduce_prep, dim3(nactive), dim3(256), 0, s, part, nblk, st, active);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(2 * (maxm + 1), nactive), dim3(256), 0, s, part, nblk, st, active);
+  hipLaunchKernelGGL(k_prep, dim3(nactive), dim3(256), 0, s, st, active);
 }
 
 int update_blocks(size_t total) {
@@ -1064,8 +1160,9 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
 #define HP_INST(T)                                                                                                   \
   template int row_blocks<T>(int);                                                                                   \
   template int row_apply_blocks<T>(const Geo&);                                                                      \
+  template int row_apply_parts<T>(const Geo&);                                                                       \
   template void launch_row_fwd<T>(const c128*, cx<T>*, double*, const cx<T>*, const Geo&, hipStream_t);              \
-  template void launch_row_inv<T>(const cx<T>*, c128*, const cx<T>*, const Geo&, hipStream_t);                       \
+  template void launch_row_inv<T>(const cx<T>*, c128*, const cx<T>*, const Geo&, int, hipStream_t);                  \
   template void launch_col<T>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,         \
                               const int*, int, bool, const double*, const double*, const cx<T>*, const Geo&,         \
                               const StencilCoef&, hipStream_t);                                                      \

@@ -16,16 +16,17 @@ struct Geo {
   size_t fsz;  // nx * ny
 };
 
-// Row DST-I of the unknowns of a complex128 field: out (R-domain, T) and
-// per-block partial sums of |in|^2 (nblk per component).
+// Row DST-I of the unknowns of a complex128 field (physical, row-major): out
+// (R-domain, T, column-tiled) and per-block partial sums of |in|^2.
 template <typename T>
 void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s);
 template <typename T>
 int row_blocks(int nx);
 
-// Row DST-I back to complex128 (out = S_x in).
+// Row DST-I back to complex128 (out = S_x in); in is column-tiled with tile_w
+// elements per tile row.
 template <typename T>
-void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, hipStream_t s);
+void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, int tile_w, hipStream_t s);
 
 // Column pass: z = sigma_m * S_y diag(1/(mu_y + mu_x - b_k)) S_y u_m for the
 // active poles.  shared: every pole reads the same u (the step's S_x w).
@@ -44,6 +45,14 @@ void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* d
                       const StencilCoef& sc, hipStream_t s);
 template <typename T>
 int row_apply_blocks(const Geo& g);
+// partial sums per inner product written by the row pass (one per wave)
+template <typename T>
+int row_apply_parts(const Geo& g);
+// elements per 128-byte tile row of a column-tiled R-domain field
+template <typename T>
+constexpr int tile_width() {
+  return 128 / (int)sizeof(cx<T>);
+}
 
 // hc_i = sigma_i * sum of the partial inner products.
 void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int* active, int nactive, int maxm,

@@ -44,4 +44,6 @@ struct PoleState {
   c128 g[HP_MAXM + 1];                // rotated beta e1
   c128 gpre[HP_MAXM + 1];             // g[i] before rotation i
   c128 y[HP_MAXM];                    // coefficients of Z~ in the cycle's solution
+  c128 Pd[HP_MAXM + 1];               // reduced <u_i, p> of the current step
+  c128 Qd[HP_MAXM + 1];               // reduced <u_i, u_m> of the current step
 };
