@@ -3,10 +3,17 @@
 // The free-space preconditioner (Sec. 4.2.2, eq. fs_sylvester) is
 // diagonalised by the orthonormal DST-I of length n-1 on each axis:
 //   X_p = sqrt(2/n) sum_{j=1}^{n-1} x_j sin(pi p j / n).
-// With the odd extension y (y_j = x_j, y_{2n-j} = -x_j, y_0 = y_n = 0) of
-// period L = 2n, the forward DFT gives Y_p = -2i sum x_j sin(pi p j/n), so
-//   X_p = i Y_p / sqrt(2n).
 // S is symmetric and S S = I, so the same routine is its own inverse.
+//
+// dst1() computes it with one complex FFT of length n (not the 2n of the odd
+// extension).  With x_0 = x_n = 0 and
+//   y_j = sin(pi j/n) (x_j + x_{n-j}) + (x_j - x_{n-j}) / 2,   F = FFT_n(y),
+// the sums sum_j y_j sin(2 pi j k/n) and sum_j y_j cos(2 pi j k/n) reduce (the
+// terms pair up under j -> n - j) to
+//   X_{2k}   = (i/2) (F_k - F_{n-k}),
+//   X_{2k+1} = X_{2k-1} + (F_k + F_{n-k}) / 2,   X_1 = F_0 / 2,
+// so the odd outputs are a prefix sum (a shuffle scan here).  This holds for
+// complex x because every step is linear with real coefficients.
 //
 // FFT: self-sorting Stockham radix-8/4/2 with the data in LDS, one group of
 // NT = L/8 threads per transform, each thread holding R values of a stage in
@@ -138,4 +145,94 @@ __device__ __forceinline__ cx<T> odd_at(const cx<T>* buf, int n, int i) {
   if (i < 0 && i > -n) return -buf[pidx(-i)];
   if (i > n && i < 2 * n) return -buf[pidx(2 * n - i)];
   return mk<T>(0, 0);
+}
+
+// Inclusive prefix sum of v over the NT threads t = 0..NT-1 of one transform
+// (NT a power of two; groups of NT consecutive threads are independent).
+// scr: LDS scratch of NT/64 elements per group (unused when NT <= 64).
+// Contains __syncthreads: every thread of the workgroup must call it.
+template <typename T, int NT>
+__device__ __forceinline__ cx<T> group_scan(cx<T> v, cx<T>* scr, int t) {
+  constexpr int W = NT < 64 ? NT : 64;
+#pragma unroll
+  for (int d = 1; d < W; d <<= 1) {
+    const T re = __shfl_up(v.re, d, W), im = __shfl_up(v.im, d, W);
+    if ((t & (W - 1)) >= d) {
+      v.re += re;
+      v.im += im;
+    }
+  }
+  if constexpr (NT > 64) {
+    const int w = t >> 6;
+    if ((t & 63) == 63) scr[w] = v;
+    __syncthreads();
+    cx<T> off = mk<T>(0, 0);
+    for (int i = 0; i < w; ++i) off = off + scr[i];
+    v = v + off;
+    __syncthreads();
+  }
+  return v;
+}
+
+// In-place DST-I (unnormalised: X_p = sum_j x_j sin(pi p j/n)) of the LDS
+// buffer buf holding x_0..x_{n-1} in natural order (x_0 ignored); on return
+// buf holds X_0 = 0, X_1..X_{n-1}.  tw: n FFT twiddles followed by
+// sin(pi j/n), j = 0..n/2, in the real parts.  NT = n/8 threads per transform,
+// t in [0, NT).  The caller synchronises before (buf written) and reads after.
+template <typename T, int N>
+__device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t) {
+  constexpr int NT = N / 8;
+  const cx<T>* sintab = tw + N;
+  // pre-processing, one thread per pair (j, n - j), j = 1..n/2
+  for (int j = 1 + t; j <= N / 2; j += NT) {
+    const cx<T> a = buf[pidx(j)];
+    const T sj = sintab[j].re;
+    if (j == N / 2) {
+      buf[pidx(j)] = (T)2 * sj * a;
+    } else {
+      const cx<T> b = buf[pidx(N - j)];
+      const cx<T> sum = sj * (a + b), dif = (T)0.5 * (a - b);
+      buf[pidx(j)] = sum + dif;
+      buf[pidx(N - j)] = sum - dif;
+    }
+  }
+  if (t == 0) buf[pidx(0)] = mk<T>(0, 0);
+  __syncthreads();
+  fft<T, N>(buf, tw, t);
+  // post-processing: thread t owns k = 4t+1 .. 4t+4 (k <= n/2 - 1)
+  const cx<T> f0 = buf[pidx(0)];
+  cx<T> ev[4], od[4];
+  cx<T> run = mk<T>(0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = 4 * t + 1 + i;
+    if (k < N / 2) {
+      const cx<T> fk = buf[pidx(k)], fn = buf[pidx(N - k)];
+      ev[i] = (T)0.5 * mul_i(fk - fn);
+      run = run + (T)0.5 * (fk + fn);
+    }
+    od[i] = run;
+  }
+  cx<T> incl = group_scan<T, NT>(run, scr, t);
+  const cx<T> base = (T)0.5 * f0 + (incl - run);  // X_1 plus the sums of earlier threads
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = 4 * t + 1 + i;
+    if (k < N / 2) {
+      buf[pidx(2 * k)] = ev[i];
+      buf[pidx(2 * k + 1)] = base + od[i];
+    }
+  }
+  if (t == 0) {
+    buf[pidx(0)] = mk<T>(0, 0);
+    buf[pidx(1)] = (T)0.5 * f0;
+  }
+  __syncthreads();
+}
+
+// Orthonormal DST-I value p from dst1 output.
+template <typename T>
+__device__ __forceinline__ cx<T> dst_val(const cx<T>* buf, int p, T scale) {
+  return scale * buf[pidx(p)];
 }

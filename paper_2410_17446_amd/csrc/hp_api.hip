@@ -163,9 +163,9 @@ void layout(hp_plan p, Ws& w) {
   const int K = d.npoles, M = d.restart;
   p->mu_x = w.take<double>(d.nx);
   p->mu_y = w.take<double>(d.ny);
-  p->tw_x = w.take<char>(2 * d.nx * es);
-  p->tw_y = w.take<char>(2 * d.ny * es);
-  p->tw64_x = w.take<c128>(2 * d.nx);
+  p->tw_x = w.take<char>((d.nx + d.nx / 2 + 1) * es);
+  p->tw_y = w.take<char>((d.ny + d.ny / 2 + 1) * es);
+  p->tw64_x = w.take<c128>(d.nx + d.nx / 2 + 1);
   p->coef = w.take<double>((d.ncomp == 2 ? 6 : 1) * p->geo.fsz);
   p->coef_scratch = w.take<double>((d.ncomp == 2 ? 2 : 1) * p->geo.fsz);
   p->U = w.take<char>((size_t)K * (M + 1) * fn * es);
@@ -197,7 +197,7 @@ void derive(hp_plan p) {
   p->geo.ncomp = d.ncomp;
   p->geo.fsz = (size_t)d.nx * d.ny;
   p->fieldn = p->geo.fsz * d.ncomp;
-  const int rpw = 256 / (2 * d.nx / 8) > 0 ? 256 / (2 * d.nx / 8) : 1;
+  const int rpw = 256 / (d.nx / 8) > 0 ? 256 / (d.nx / 8) : 1;
   p->nrowblk = (d.ny - 1 + rpw - 1) / rpw;
   p->napplyblk = p->mixed ? row_apply_parts<float>(p->geo) : row_apply_parts<double>(p->geo);
   p->nupdblk = update_blocks(p->fieldn);
@@ -223,13 +223,16 @@ std::vector<double> mu_table(int n, double h, const double* c, double s) {
   return mu;
 }
 
+// FFT twiddles exp(-2 pi i m / n), m < n, then sin(pi j / n), j = 0..n/2, in
+// the real parts (the DST-I pre-processing factors).
 template <typename T>
-std::vector<cx<T>> twiddles(int L) {
-  std::vector<cx<T>> t(L);
-  for (int m = 0; m < L; ++m) {
-    const double a = -2.0 * M_PI * (double)m / (double)L;
+std::vector<cx<T>> twiddles(int n) {
+  std::vector<cx<T>> t(n + n / 2 + 1);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
     t[m] = mk<T>((T)cos(a), (T)sin(a));
   }
+  for (int j = 0; j <= n / 2; ++j) t[n + j] = mk<T>((T)sin(M_PI * (double)j / (double)n), (T)0);
   return t;
 }
 
@@ -249,8 +252,8 @@ int upload_tables(hp_plan p) {
   auto mx = mu_table(d.nx, d.dx, p->c2, s), my = mu_table(d.ny, d.dy, p->c2, s);
   HPCHK(hipMemcpy(p->mu_x, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->mu_y, my.data(), my.size() * sizeof(double), hipMemcpyHostToDevice));
-  auto tx = twiddles<T>(2 * d.nx), ty = twiddles<T>(2 * d.ny);
-  auto t64 = twiddles<double>(2 * d.nx);
+  auto tx = twiddles<T>(d.nx), ty = twiddles<T>(d.ny);
+  auto t64 = twiddles<double>(d.nx);
   HPCHK(hipMemcpy(p->tw_x, tx.data(), tx.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->tw_y, ty.data(), ty.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->tw64_x, t64.data(), t64.size() * sizeof(c128), hipMemcpyHostToDevice));

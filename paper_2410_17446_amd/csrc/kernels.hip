@@ -36,25 +36,27 @@ __device__ __forceinline__ size_t tix(int i, int q, int ny) {
   return ((size_t)(q / TW) * ny + i) * TW + (q % TW);
 }
 
-template <int L>
+template <int N>
 struct RowCfg {
-  static constexpr int NT = L / 8;                           // threads per transform
+  static constexpr int NT = N / 8;                           // threads per transform
   static constexpr int RPW = (256 / NT) > 0 ? 256 / NT : 1;  // transforms per workgroup
   static constexpr int WG = RPW * NT;
+  static constexpr int PT = N / NT;                          // values per thread per row (8)
+  static constexpr int SCR = NT > 64 ? NT / 64 : 1;          // scan scratch per transform
 };
 
 constexpr int kColLdsBytes = 40960;  // several column workgroups per CU
 
-template <typename T, int L>
+template <typename T, int N>
 struct ColCfg {
   static constexpr int TW = Tile<T>::W;
-  static constexpr int NT = L / 8;
-  static constexpr int PB = plen(L) * (int)sizeof(cx<T>);
+  static constexpr int NT = N / 8;
+  static constexpr int PB = plen(N) * (int)sizeof(cx<T>);
   static constexpr int G0 = kColLdsBytes / PB;
   static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
   static constexpr int GC = (G1 * NT > 1024) ? 1024 / NT : G1;  // columns transformed at once
   static constexpr int WG = GC * NT;
-  static constexpr int EPT = ((L / 2 - 1) * TW + WG - 1) / WG;  // tile elements per thread
+  static constexpr int SCR = NT > 64 ? NT / 64 : 1;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -100,19 +102,20 @@ __device__ __forceinline__ double edge_loss(int i, int j, int nx, int ny, int W,
 
 // ------------------------------------------------------------------ row forward (physical -> R-domain)
 
-template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
+template <typename T, int N>
+__global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
                                                            double* __restrict__ part, const cx<T>* __restrict__ tw,
                                                            int ny, size_t fsz, int nblk) {
-  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW, WG = RowCfg<L>::WG, TW = Tile<T>::W;
-  constexpr int PT = N / NT;
-  __shared__ cx<T> lds[RPW * plen(L)];
+  using RC = RowCfg<N>;
+  constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT, TW = Tile<T>::W;
+  __shared__ cx<T> lds[RPW * plen(N)];
+  __shared__ cx<T> scr[RPW * RC::SCR];
   __shared__ double red[(WG + 63) / 64];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = 1 + blockIdx.x * RPW + g;
   const int comp = blockIdx.y;
   const bool valid = row < ny;
-  cx<T>* buf = lds + g * plen(L);
+  cx<T>* buf = lds + g * plen(N);
   const c128* src = in + comp * fsz + (size_t)row * N;
   double nrm = 0.0;
 #pragma unroll
@@ -124,17 +127,17 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_fwd(const c128* __restric
       nrm += abs2(a);
       v = cvt<T>(a);
     }
-    odd_store(buf, N, m, v);
+    buf[pidx(m)] = v;
   }
   __syncthreads();
-  fft<T, L>(buf, tw, t);
-  const T scale = (T)(1.0 / sqrt(2.0 * N));
+  dst1<T, N>(buf, tw, scr + g * RC::SCR, t);
+  const T scale = (T)sqrt(2.0 / N);
   if (valid) {
     cx<T>* dst = out + comp * fsz;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int p = t + s * NT;
-      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : dst_out(buf, p, scale);
+      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : dst_val(buf, p, scale);
     }
   }
   double sum = block_sum<WG>(nrm, red);
@@ -143,32 +146,33 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_fwd(const c128* __restric
 
 // ------------------------------------------------------------------ row inverse (R-domain -> physical complex128)
 
-template <typename T, int L, int TW>
-__global__ __launch_bounds__(RowCfg<L>::WG) void k_row_inv(const cx<T>* __restrict__ in, c128* __restrict__ out,
+template <typename T, int N, int TW>
+__global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restrict__ in, c128* __restrict__ out,
                                                            const cx<T>* __restrict__ tw, int ny, size_t fsz) {
-  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW;
-  constexpr int PT = N / NT;
-  __shared__ cx<T> lds[RPW * plen(L)];
+  using RC = RowCfg<N>;
+  constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT;
+  __shared__ cx<T> lds[RPW * plen(N)];
+  __shared__ cx<T> scr[RPW * RC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // all rows, row 0 -> zeros
   const int comp = blockIdx.y;
   const bool valid = row < ny && row > 0;
-  cx<T>* buf = lds + g * plen(L);
+  cx<T>* buf = lds + g * plen(N);
   const cx<T>* src = in + comp * fsz;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int m = t + s * NT;
-    odd_store(buf, N, m, (valid && m > 0) ? src[tix<TW>(row, m, ny)] : czero<T>());
+    buf[pidx(m)] = (valid && m > 0) ? src[tix<TW>(row, m, ny)] : czero<T>();
   }
   __syncthreads();
-  fft<T, L>(buf, tw, t);
-  const T scale = (T)(1.0 / sqrt(2.0 * N));
+  dst1<T, N>(buf, tw, scr + g * RC::SCR, t);
+  const T scale = (T)sqrt(2.0 / N);
   if (row < ny) {
     c128* dst = out + comp * fsz + (size_t)row * N;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int p = t + s * NT;
-      dst[p] = (!valid || p == 0) ? mk(0.0, 0.0) : cvt<double>(dst_out(buf, p, scale));
+      dst[p] = (!valid || p == 0) ? mk(0.0, 0.0) : cvt<double>(dst_val(buf, p, scale));
     }
   }
 }
@@ -179,83 +183,67 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_row_inv(const cx<T>* __restri
 // columns go through LDS GC at a time; the GC-column slices of a line that one
 // group reads are followed by the rest of that line in the next groups of the
 // same workgroup, so the line comes from HBM once and from L2 after.
-// SHARED: every active pole reads the same u (the step's first Krylov vector),
-// so the tile is read from HBM once for all poles.
 
-template <typename T, int L, int NC, bool SHARED>
-__global__ __launch_bounds__((ColCfg<T, L>::WG)) void k_col(
+template <typename T, int N, int NC>
+__global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
     const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
     cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const int* __restrict__ active,
-    int nactive, const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw,
-    int nx, size_t fsz, StencilCoef sc) {
-  using CC = ColCfg<T, L>;
-  constexpr int N = L / 2, NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG;
-  constexpr int PL = plen(L);
+    const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw, size_t fsz,
+    StencilCoef sc) {
+  using CC = ColCfg<T, N>;
+  constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG;
+  constexpr int PL = plen(N);
   constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
   __shared__ cx<T> lds[GC * PL];
+  __shared__ cx<T> scr[GC * CC::SCR];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int col0 = tile * TW;
   const int comp = blockIdx.y % NC;
   const int tid = threadIdx.x;
   const int g = tid / NT, t = tid % NT;
-  const T scale = (T)(1.0 / sqrt(2.0 * N));
-  const int first = SHARED ? 0 : blockIdx.y / NC;
-  const int last = SHARED ? nactive : first + 1;
+  const T scale = (T)sqrt(2.0 / N);
+  const int k = active[blockIdx.y / NC];
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  const c128 b = st[k].bk;
+  const T sc2 = (T)st[k].sigma[m] * scale;
   const size_t tbase = comp * fsz + (size_t)tile * N * TW;  // this tile, component comp (ny == N)
-  for (int a = first; a < last; ++a) {
-    const int k = active[a];
-    if (st[k].flag) continue;
-    const int m = st[k].m;
-    const c128 b = st[k].bk;
-    const T sc2 = (T)st[k].sigma[m] * scale;
-    const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
-    cx<T>* z = zbase + k * zsp + m * zsi + tbase;
-    cx<T>* dz = (NC == 2) ? dzbase + k * dzsp + tbase : nullptr;
+  const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
+  cx<T>* z = zbase + k * zsp + m * zsi + tbase;
+  cx<T>* dz = (NC == 2) ? dzbase + k * dzsp + tbase : nullptr;
 #pragma unroll 1
-    for (int c0 = 0; c0 < TW; c0 += GC) {
-      __syncthreads();
-      for (int e = tid; e < NE; e += WG) {
-        const int r = 1 + e / GC, c = e % GC;
-        const cx<T> v = u[(size_t)r * TW + c0 + c];
-        cx<T>* bc = lds + c * PL;
-        bc[pidx(r)] = v;
-        bc[pidx(L - r)] = -v;
-      }
-      if (tid < GC) {
-        lds[tid * PL + pidx(0)] = czero<T>();
-        lds[tid * PL + pidx(N)] = czero<T>();
-      }
-      __syncthreads();
-      fft<T, L>(lds + g * PL, tw, t);
-      // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
-      for (int e = tid; e < NE; e += WG) {
-        const int p = 1 + e / GC, c = e % GC, q = col0 + c0 + c;
-        cx<T>* bc = lds + c * PL;
-        const cx<T> X = dst_out(bc, p, scale);
-        const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
-        const double den = lr * lr + li * li;
-        const cx<T> zt = X * mk<T>((T)(lr / den), (T)(-li / den));
-        bc[pidx(p)] = zt;
-        bc[pidx(L - p)] = -zt;
-      }
-      if (tid < GC) {
-        lds[tid * PL + pidx(0)] = czero<T>();
-        lds[tid * PL + pidx(N)] = czero<T>();
-      }
-      __syncthreads();
-      fft<T, L>(lds + g * PL, tw, t);
-      for (int e = tid; e < NE; e += WG) {
-        const int p = 1 + e / GC, c = e % GC;
-        const cx<T>* bc = lds + c * PL;
-        z[(size_t)p * TW + c0 + c] = sc2 * mul_i(bc[pidx(p)]);
-        if constexpr (NC == 2) {
-          // D1y of the column, physical in y (odd reflection about rows 0 and N)
-          cx<double> acc = mk(0.0, 0.0);
+  for (int c0 = 0; c0 < TW; c0 += GC) {
+    __syncthreads();
+    for (int e = tid; e < NE; e += WG) {
+      const int r = 1 + e / GC, c = e % GC;
+      lds[c * PL + pidx(r)] = u[(size_t)r * TW + c0 + c];
+    }
+    if (tid < GC) lds[tid * PL + pidx(0)] = czero<T>();
+    __syncthreads();
+    dst1<T, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
+    for (int e = tid; e < NE; e += WG) {
+      const int p = 1 + e / GC, c = e % GC, q = col0 + c0 + c;
+      cx<T>* bc = lds + c * PL;
+      const cx<T> X = dst_val(bc, p, scale);
+      const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
+      const double den = lr * lr + li * li;
+      bc[pidx(p)] = X * mk<T>((T)(lr / den), (T)(-li / den));
+    }
+    if (tid < GC) lds[tid * PL + pidx(0)] = czero<T>();
+    __syncthreads();
+    dst1<T, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    for (int e = tid; e < NE; e += WG) {
+      const int p = 1 + e / GC, c = e % GC;
+      const cx<T>* bc = lds + c * PL;
+      z[(size_t)p * TW + c0 + c] = sc2 * bc[pidx(p)];
+      if constexpr (NC == 2) {
+        // D1y of the column, physical in y (odd reflection about rows 0 and N)
+        cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
-          for (int mm = 1; mm <= 6; ++mm)
-            acc = acc + sc.d1y[mm - 1] * cvt<double>(odd_at(bc, N, p + mm) - odd_at(bc, N, p - mm));
-          dz[(size_t)p * TW + c0 + c] = sc2 * mul_i(cvt<T>(acc));
-        }
+        for (int mm = 1; mm <= 6; ++mm)
+          acc = acc + sc.d1y[mm - 1] * cvt<double>(odd_at(bc, N, p + mm) - odd_at(bc, N, p - mm));
+        dz[(size_t)p * TW + c0 + c] = sc2 * cvt<T>(acc);
       }
     }
   }
@@ -263,27 +251,29 @@ __global__ __launch_bounds__((ColCfg<T, L>::WG)) void k_col(
 
 // ------------------------------------------------------------------ row pass (medium part + inner products)
 
-template <int L, int NC>
+template <int N, int NC>
 struct ApplyCfg {
-  static constexpr int NT = L / 8;
+  static constexpr int NT = N / 8;
   static constexpr int G0 = 256 / NT;
   static constexpr int GROUPS = G0 < NC ? NC : G0;  // transforms per workgroup (NC per row)
   static constexpr int ROWS = GROUPS / NC;
   static constexpr int WG = GROUPS * NT;
   static constexpr int WAVES = (WG + 63) / 64;
+  static constexpr int SCR = NT > 64 ? NT / 64 : 1;
 };
 
-template <typename T, int L, int NC>
-__global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
+template <typename T, int N, int NC>
+__global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
     cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const double* __restrict__ coef,
     const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
     const cx<T>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
-  using AC = ApplyCfg<L, NC>;
-  constexpr int N = L / 2, NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
+  using AC = ApplyCfg<N, NC>;
+  constexpr int NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
   constexpr int PT = N / NT;  // values per thread per row
-  constexpr int PL = plen(L);
-  __shared__ cx<T> lds[GROUPS * PL];
+  constexpr int PL = plen(N);
+  __shared__ cx<T> lds[GROUPS * PL * NC];
+  __shared__ cx<T> scr[GROUPS * AC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int comp = g % NC;
   const int row = 1 + blockIdx.x * ROWS + g / NC;
@@ -292,7 +282,8 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
   if (st[k].flag) return;
   const int m = st[k].m;
   cx<T>* buf = lds + g * PL;
-  const T scale = (T)(1.0 / sqrt(2.0 * N));
+  cx<T>* sg = scr + g * AC::SCR;
+  const T scale = (T)sqrt(2.0 / N);
   const size_t cbase = comp * fsz;
   const size_t ci0 = (size_t)row * N;  // physical row offset
   size_t toff[PT];                     // tiled offsets of the thread's points
@@ -303,16 +294,16 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    odd_store(buf, N, j, (valid && j > 0) ? z[toff[s]] : czero<T>());
+    buf[pidx(j)] = (valid && j > 0) ? z[toff[s]] : czero<T>();
   }
   __syncthreads();
-  fft<T, L>(buf, tw, t);
+  dst1<T, N>(buf, tw, sg, t);
   cx<T> pz[PT];  // P z at the thread's points j = t + s * NT
   if constexpr (NC == 1) {
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      const cx<T> zj = (j == 0) ? czero<T>() : dst_out(buf, j, scale);
+      const cx<T> zj = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
       const T v = valid ? (T)coef[ci0 + j] : (T)0;
       pz[s] = v * zj;
     }
@@ -320,30 +311,31 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
+    cx<T>* buf2 = lds + (GROUPS + g) * PL;
     cx<T> zc[PT], dxz[PT], dyz[PT];
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      zc[s] = (j == 0) ? czero<T>() : dst_out(buf, j, scale);
+      zc[s] = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
       cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
       for (int mm = 1; mm <= 6; ++mm)
         acc = acc + sc.d1x[mm - 1] * cvt<double>(odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
-      dxz[s] = (j == 0) ? czero<T>() : scale * mul_i(cvt<T>(acc));
+      dxz[s] = (j == 0) ? czero<T>() : scale * cvt<T>(acc);
     }
     __syncthreads();
     const cx<T>* dz = dzbase + k * dzsp;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      odd_store(buf, N, j, (valid && j > 0) ? dz[toff[s]] : czero<T>());
+      buf[pidx(j)] = (valid && j > 0) ? dz[toff[s]] : czero<T>();
     }
     __syncthreads();
-    fft<T, L>(buf, tw, t);
+    dst1<T, N>(buf, tw, sg, t);
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      dyz[s] = (j == 0) ? czero<T>() : dst_out(buf, j, scale);
+      dyz[s] = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
     }
     __syncthreads();
     // exchange: component 0 needs w2 and D1x w2, component 1 needs w1 and D1y w1
@@ -351,10 +343,11 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
       buf[pidx(j)] = zc[s];
-      buf[pidx(N + j)] = (comp == 0) ? dyz[s] : dxz[s];
+      buf2[pidx(j)] = (comp == 0) ? dyz[s] : dxz[s];
     }
     __syncthreads();
     const cx<T>* other = lds + (g ^ 1) * PL;
+    const cx<T>* other2 = lds + (GROUPS + (g ^ 1)) * PL;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
@@ -365,7 +358,7 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
       const size_t ci = ci0 + j;
       const T v = (T)coef[ci], px = (T)coef[fsz + ci], py = (T)coef[2 * fsz + ci];
       const T pxx = (T)coef[3 * fsz + ci], pyy = (T)coef[4 * fsz + ci], pxy = (T)coef[5 * fsz + ci];
-      const cx<T> zo = other[pidx(j)], dzo = other[pidx(N + j)];
+      const cx<T> zo = other[pidx(j)], dzo = other2[pidx(j)];
       if (comp == 0)
         pz[s] = pxx * zc[s] + px * dxz[s] + pxy * zo + py * dzo + v * zc[s];
       else
@@ -375,15 +368,18 @@ __global__ __launch_bounds__((ApplyCfg<L, NC>::WG)) void k_row_apply(
   }
   // forward transform of P z
 #pragma unroll
-  for (int s = 0; s < PT; ++s) odd_store(buf, N, t + s * NT, pz[s]);
+  for (int s = 0; s < PT; ++s) {
+    const int j = t + s * NT;
+    buf[pidx(j)] = (j == 0) ? czero<T>() : pz[s];
+  }
   __syncthreads();
-  fft<T, L>(buf, tw, t);
+  dst1<T, N>(buf, tw, sg, t);
   cx<T> pv[PT];
   cx<T>* p = pbase + k * psp;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    pv[s] = (j == 0 || !valid) ? czero<T>() : dst_out(buf, j, scale);
+    pv[s] = (j == 0 || !valid) ? czero<T>() : dst_val(buf, j, scale);
     if (valid) p[toff[s]] = pv[s];
   }
   // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
@@ -760,23 +756,22 @@ __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, c
 
 // ------------------------------------------------------------------ residue-weighted sum and output
 
-// ------------------------------------------------------------------ residue-weighted sum and output
-
-template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::WG) void k_final(const c128* __restrict__ w, c128* __restrict__ out,
+template <typename T, int N>
+__global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict__ w, c128* __restrict__ out,
                                                          const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
                                                          const c128* __restrict__ xacc, size_t xsp,
                                                          const PoleState* __restrict__ st, int npoles, c128 phase,
                                                          c128 rinf_phase, double loss_coef, double eta, int W,
                                                          const c128* __restrict__ tw, int nx, int ny, size_t fsz) {
-  constexpr int N = L / 2, NT = RowCfg<L>::NT, RPW = RowCfg<L>::RPW, TW = Tile<T>::W;
-  constexpr int PT = N / NT;
-  __shared__ c128 lds[RPW * plen(L)];
+  using RC = RowCfg<N>;
+  constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT, TW = Tile<T>::W;
+  __shared__ c128 lds[RPW * plen(N)];
+  __shared__ c128 scr[RPW * RC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // rows 0..ny-1
   const int comp = blockIdx.y;
   const bool valid = row > 0 && row < ny;
-  c128* buf = lds + g * plen(L);
+  c128* buf = lds + g * plen(N);
   const size_t roff = comp * fsz + (size_t)row * N;
   size_t toff[PT];
 #pragma unroll
@@ -803,17 +798,17 @@ __global__ __launch_bounds__(RowCfg<L>::WG) void k_final(const c128* __restrict_
     }
   }
 #pragma unroll
-  for (int s = 0; s < PT; ++s) odd_store(buf, N, t + s * NT, acc[s]);
+  for (int s = 0; s < PT; ++s) buf[pidx(t + s * NT)] = acc[s];
   __syncthreads();
-  fft<double, L>(buf, tw, t);
-  const double scale = 1.0 / sqrt(2.0 * N);
+  dst1<double, N>(buf, tw, scr + g * RC::SCR, t);
+  const double scale = sqrt(2.0 / N);
   if (row < ny) {
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
       c128 v = mk(0.0, 0.0);
       if (valid && j > 0) {
-        const c128 sv = dst_out(buf, j, scale);
+        const c128 sv = dst_val(buf, j, scale);
         v = edge_loss(row, j, nx, ny, W, eta, loss_coef) * (phase * sv + rinf_phase * w[roff + j]);
       }
       out[roff + j] = v;
@@ -973,24 +968,22 @@ __global__ void k_fill_zero(c128* p, size_t n) {
 
 // ====================================================================== launchers
 
-#define HP_DISPATCH_L(n, MACRO) \
+#define HP_DISPATCH_N(n, MACRO) \
   switch (n) {                  \
-    case 64: MACRO(128); break; \
-    case 128: MACRO(256); break;  \
-    case 256: MACRO(512); break;  \
-    case 512: MACRO(1024); break; \
-    case 1024: MACRO(2048); break; \
-    case 2048: MACRO(4096); break; \
+    case 64: MACRO(64); break;  \
+    case 128: MACRO(128); break;  \
+    case 256: MACRO(256); break;  \
+    case 512: MACRO(512); break;  \
+    case 1024: MACRO(1024); break; \
+    case 2048: MACRO(2048); break; \
     default: break;             \
   }
 
 template <typename T>
 int row_blocks(int nx) {
-  int L = 2 * nx;
-  int NT = L / 8;
-  int RPW = (256 / NT) > 0 ? 256 / NT : 1;
+  const int NT = nx / 8;
   (void)sizeof(T);
-  return RPW;  // rows per workgroup
+  return (256 / NT) > 0 ? 256 / NT : 1;  // rows per workgroup
 }
 
 template <typename T>
@@ -998,9 +991,9 @@ void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, c
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny - 1 + rpw - 1) / rpw;
   dim3 grid(nblk, g.ncomp);
-#define L_(LL) \
-  hipLaunchKernelGGL((k_row_fwd<T, LL>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, part, tw, g.ny, g.fsz, nblk)
-  HP_DISPATCH_L(g.nx, L_)
+#define L_(NN) \
+  hipLaunchKernelGGL((k_row_fwd<T, NN>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz, nblk)
+  HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
@@ -1009,12 +1002,12 @@ void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, i
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny + rpw - 1) / rpw;
   dim3 grid(nblk, g.ncomp);
-#define L_(LL)                                                                                                  \
+#define L_(NN)                                                                                                  \
   if (tile_w == 8)                                                                                              \
-    hipLaunchKernelGGL((k_row_inv<T, LL, 8>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
+    hipLaunchKernelGGL((k_row_inv<T, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
   else                                                                                                          \
-    hipLaunchKernelGGL((k_row_inv<T, LL, 16>), grid, dim3(RowCfg<LL>::WG), 0, s, in, out, tw, g.ny, g.fsz);
-  HP_DISPATCH_L(g.nx, L_)
+    hipLaunchKernelGGL((k_row_inv<T, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);
+  HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
@@ -1022,33 +1015,24 @@ template <typename T>
 void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
                 const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
                 const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s) {
-#define L_(LL)                                                                                               \
-  {                                                                                                          \
-    constexpr int TW_ = ColCfg<T, LL>::TW;                                                                   \
-    dim3 grid(g.nx / TW_, g.ncomp * (shared ? 1 : nactive));                                                 \
-    if (g.ncomp == 1) {                                                                                      \
-      if (shared)                                                                                            \
-        hipLaunchKernelGGL((k_col<T, LL, 1, true>), grid, dim3(ColCfg<T, LL>::WG), 0, s, uptr, zbase, zsp,   \
-                           zsi, dzbase, dzsp, st, active, nactive, mu_x, mu_y, tw, g.nx, g.fsz, sc);         \
-      else                                                                                                   \
-        hipLaunchKernelGGL((k_col<T, LL, 1, false>), grid, dim3(ColCfg<T, LL>::WG), 0, s, uptr, zbase, zsp,  \
-                           zsi, dzbase, dzsp, st, active, nactive, mu_x, mu_y, tw, g.nx, g.fsz, sc);         \
-    } else {                                                                                                 \
-      if (shared)                                                                                            \
-        hipLaunchKernelGGL((k_col<T, LL, 2, true>), grid, dim3(ColCfg<T, LL>::WG), 0, s, uptr, zbase, zsp,   \
-                           zsi, dzbase, dzsp, st, active, nactive, mu_x, mu_y, tw, g.nx, g.fsz, sc);         \
-      else                                                                                                   \
-        hipLaunchKernelGGL((k_col<T, LL, 2, false>), grid, dim3(ColCfg<T, LL>::WG), 0, s, uptr, zbase, zsp,  \
-                           zsi, dzbase, dzsp, st, active, nactive, mu_x, mu_y, tw, g.nx, g.fsz, sc);         \
-    }                                                                                                        \
+  (void)shared;
+#define L_(NN)                                                                                                 \
+  {                                                                                                            \
+    dim3 grid(g.nx / ColCfg<T, NN>::TW, g.ncomp * nactive);                                                    \
+    if (g.ncomp == 1)                                                                                          \
+      hipLaunchKernelGGL((k_col<T, NN, 1>), grid, dim3(ColCfg<T, NN>::WG), 0, s, uptr, zbase, zsp, zsi, dzbase, \
+                         dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                         \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_col<T, NN, 2>), grid, dim3(ColCfg<T, NN>::WG), 0, s, uptr, zbase, zsp, zsi, dzbase, \
+                         dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                         \
   }
-  HP_DISPATCH_L(g.ny, L_)
+  HP_DISPATCH_N(g.ny, L_)
 #undef L_
 }
 
 template <typename T>
 int row_apply_blocks(const Geo& g) {
-  const int nt = (2 * g.nx) / 8;
+  const int nt = g.nx / 8;
   int groups = 256 / nt;
   if (groups < g.ncomp) groups = g.ncomp;
   const int rows = groups / g.ncomp;
@@ -1057,7 +1041,7 @@ int row_apply_blocks(const Geo& g) {
 
 template <typename T>
 int row_apply_parts(const Geo& g) {
-  const int nt = (2 * g.nx) / 8;
+  const int nt = g.nx / 8;
   int groups = 256 / nt;
   if (groups < g.ncomp) groups = g.ncomp;
   return row_apply_blocks<T>(g) * ((groups * nt + 63) / 64);
@@ -1071,14 +1055,14 @@ void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* d
   const int nblk = row_apply_blocks<T>(g);
   const int nparts = row_apply_parts<T>(g);
   dim3 grid(nblk, nactive);
-#define L_(LL)                                                                                                  \
+#define L_(NN)                                                                                                  \
   if (g.ncomp == 1)                                                                                             \
-    hipLaunchKernelGGL((k_row_apply<T, LL, 1>), grid, dim3(ApplyCfg<LL, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
+    hipLaunchKernelGGL((k_row_apply<T, NN, 1>), grid, dim3(ApplyCfg<NN, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
                        dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);            \
   else                                                                                                          \
-    hipLaunchKernelGGL((k_row_apply<T, LL, 2>), grid, dim3(ApplyCfg<LL, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
+    hipLaunchKernelGGL((k_row_apply<T, NN, 2>), grid, dim3(ApplyCfg<NN, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
                        dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);
-  HP_DISPATCH_L(g.nx, L_)
+  HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
@@ -1118,10 +1102,10 @@ void launch_final(const c128* w, c128* out, const cx<T>* zbase, size_t zsp, size
                   const c128* tw64, const Geo& g, hipStream_t s) {
   const int rpw = row_blocks<double>(g.nx);
   dim3 grid((g.ny + rpw - 1) / rpw, g.ncomp);
-#define L_(LL)                                                                                                     \
-  hipLaunchKernelGGL((k_final<T, LL>), grid, dim3(RowCfg<LL>::WG), 0, s, w, out, zbase, zsp, zsi, xacc, xsp, st, \
+#define L_(NN)                                                                                                     \
+  hipLaunchKernelGGL((k_final<T, NN>), grid, dim3(RowCfg<NN>::WG), 0, s, w, out, zbase, zsp, zsi, xacc, xsp, st, \
                      npoles, phase, rinf_phase, loss_coef, eta, W, tw64, g.nx, g.ny, g.fsz)
-  HP_DISPATCH_L(g.nx, L_)
+  HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
