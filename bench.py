@@ -39,7 +39,52 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="mixed,fp64")
     ap.add_argument("--cpu-poles", type=int, default=2, help="poles of one oracle step in the CPU sample")
+    ap.add_argument("--workers", type=int, default=8, help="batch workers (batch64 workload)")
     return ap.parse_args()
+
+
+def run_batch(args):
+    """The batch64 workload: 64 independent propagations (N in 256..1024, 8/12/16 poles, sine or random
+    media), each `steps` steps after `warmup`, run concurrently by the library's batch workers."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, tables
+    probs = inputs.batch_configs(64)
+    tabs = {}
+    problems, ins, meds = [], [], []
+    for cfg in probs:
+        key = cfg["npoles"]
+        if key not in tabs:
+            tabs[key] = tables.plan_tables(inputs.K0 * cfg["dz"], key)
+        poles, residues, r_inf, d2, d1 = tabs[key]
+        N = cfg["N"]
+        problems.append(dict(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=inputs.K0, n0=1.0, dz=cfg["dz"], ncomp=1,
+                             poles=poles, residues=residues, r_inf=r_inf, d2=d2, d1=d1, edge_width=cfg["W"],
+                             edge_eta=cfg["eta_max"], tol=cfg["tol"], restart=cfg["restart"]))
+        ins.append(torch.from_numpy(inputs.beam(cfg)).cuda())
+        meds.append(torch.from_numpy(inputs.medium_n2(cfg)).cuda())
+    b = hp.Batch(problems, nworkers=args.workers)
+    if args.warmup:
+        ins = b.propagate(ins, meds, [args.warmup] * len(problems))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = b.propagate(ins, meds, [args.steps] * len(problems))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it, sec = b.stats()
+    total_steps = args.steps * len(problems)
+    finite = all(bool(torch.isfinite(torch.view_as_real(o)).all()) for o in outs)
+    line = {"metric": "batch propagation steps/s (64 problems, N 256..1024, 8-16 poles)",
+            "value": total_steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * dt / total_steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "c128", "data": "synthetic",
+            "config": {"workload": "batch64", "problems": len(problems), "workers": args.workers,
+                       "sizes": sorted({p["nx"] for p in problems})},
+            "gmres_iterations": int(sum(it)), "all_finite": finite,
+            "busiest_problem_s": max(sec)}
+    print(json.dumps(line))
+    return 0
 
 
 def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps):
@@ -109,6 +154,8 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); run it with --gpus 1", file=sys.stderr)
         return 2
+    if args.config == "batch64":
+        return run_batch(args)
     import numpy as np
     import torch
 

@@ -69,7 +69,7 @@ enum {
 enum { HP_FP64 = 0, HP_MIXED = 1 };
 
 typedef struct {
-  int nx, ny;                 /* cells per axis = array dims; 64 <= n <= 2048, power of two */
+  int nx, ny;                 /* cells per axis = array dims; 2^k or 3 * 2^k, 64 <= n <= 2048 */
   double dx, dy;              /* grid spacing */
   double k0, n0, dz;          /* vacuum wavenumber, reference index, step; K = k0 n0 dz */
   int ncomp;                  /* 1 scalar, 2 vector */
@@ -115,6 +115,13 @@ int hp_step(hp_plan plan, const void* E_in, const double* n2, void* E_out);
 int hp_propagate(hp_plan plan, const void* E_in, const double* n2, long n2_step_stride,
                  int nsteps, void* E_out);
 
+/* One shifted solve of the step (Sec. 2 eq. W_k_def, Sec. 4.2): x = (Zbar -
+ * b_k I)^{-1} rhs by the same preconditioned GMRES as hp_step, to the plan's
+ * tolerance, on the medium of the last hp_set_medium.  rhs, x: device
+ * [ncomp][ny][nx] complex128 (distinct).  Synchronous.  Used to check single
+ * poles at full size and to generate solve pairs. */
+int hp_solve(hp_plan plan, int pole, const void* rhs, void* x);
+
 /* Statistics of the last step (synchronous): GMRES iterations and final
  * relative residual estimate per pole (either pointer may be NULL). */
 int hp_get_stats(hp_plan plan, int* iters_per_pole, double* final_relres);
@@ -145,6 +152,24 @@ int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
 
 const char* hp_last_error(hp_plan plan);
 void hp_plan_destroy(hp_plan plan);
+
+/* Batches of independent propagations (serving workload; the paper's pole
+ * parallelism, Sec. 3.1, extended across problems).  nworkers host threads,
+ * each with its own HIP stream on the current device, take problems
+ * longest-first (cost nx ny ncomp npoles nsteps), create the problem's plan
+ * in the worker's workspace (allocated on first use, sized for the largest
+ * problem, freed by hp_batch_destroy), propagate and destroy it; problems of
+ * different sizes run concurrently.  descs is copied (tables included).
+ * hp_batch_propagate blocks until every problem is done; per problem: E_in,
+ * E_out device [ncomp][ny][nx] complex128 (may alias), n2 device [ny][nx]
+ * (z-independent medium), nsteps >= 0.  Returns the most severe status. */
+typedef struct hp_batch_s* hp_batch;
+int hp_batch_create(const hp_plan_desc* descs, int nprob, int nworkers, hp_batch* out);
+int hp_batch_propagate(hp_batch batch, const void* const* E_in, const double* const* n2, const int* nsteps,
+                       void* const* E_out);
+/* Per problem: GMRES iterations summed over poles and steps, wall seconds. */
+int hp_batch_stats(hp_batch batch, long* iters, double* seconds);
+void hp_batch_destroy(hp_batch batch);
 
 #ifdef __cplusplus
 }

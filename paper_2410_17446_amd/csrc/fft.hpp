@@ -42,7 +42,16 @@ __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3)
 
 template <typename T, int R>
 __device__ __forceinline__ void dft(cx<T>* v) {
-  if constexpr (R == 2) {
+  if constexpr (R == 3) {
+    // X1 = a + w b + w^2 c, w = exp(-2 pi i / 3)
+    const T h3 = (T)0.866025403784438646763723170752936183;
+    const cx<T> t1 = v[1] + v[2];
+    const cx<T> t2 = v[0] - (T)0.5 * t1;
+    const cx<T> t3 = h3 * mul_mi(v[1] - v[2]);
+    v[0] = v[0] + t1;
+    v[1] = t2 + t3;
+    v[2] = t2 - t3;
+  } else if constexpr (R == 2) {
     cx<T> t = v[0];
     v[0] = t + v[1];
     v[1] = t - v[1];
@@ -69,17 +78,18 @@ __device__ __forceinline__ void dft(cx<T>* v) {
   }
 }
 
-// One Stockham stage: butterflies j = t, t+NT, ...; input stride L/R,
+// One Stockham stage: butterflies j = t, t+NT, ... (< L/R); input stride L/R,
 // output (j / NS) * NS * R + (j % NS) + r * NS.
 template <typename T, int L, int R, int NS, int NT>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
   constexpr int NB = L / R;
-  constexpr int PER = NB / NT;
-  static_assert(PER * NT == NB, "threads per transform must divide L/R");
+  constexpr int PER = (NB + NT - 1) / NT;
+  constexpr bool EXACT = PER * NT == NB;
   cx<T> v[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = t + q * NT;
+    if (!EXACT && j >= NB) continue;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q][r] = buf[pidx(j + r * NB)];
     if constexpr (NS > 1) {
@@ -94,6 +104,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = t + q * NT;
+    if (!EXACT && j >= NB) continue;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[pidx(base + r * NS)] = v[q][r];
@@ -105,7 +116,8 @@ template <typename T, int L, int NS, int NT>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
   if constexpr (NS < L) {
     constexpr int REM = L / NS;
-    constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+    constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3));
+    static_assert(REM % R == 0, "lengths are 2^k or 3 * 2^k");
     fft_stage<T, L, R, NS, NT>(buf, tw, t);
     fft_stages<T, L, NS * R, NT>(buf, tw, t);
   }
@@ -148,11 +160,36 @@ __device__ __forceinline__ cx<T> odd_at(const cx<T>* buf, int n, int i) {
 }
 
 // Inclusive prefix sum of v over the NT threads t = 0..NT-1 of one transform
-// (NT a power of two; groups of NT consecutive threads are independent).
-// scr: LDS scratch of NT/64 elements per group (unused when NT <= 64).
-// Contains __syncthreads: every thread of the workgroup must call it.
+// (groups of NT consecutive threads are independent).  Power-of-two NT: wave
+// shuffles, plus LDS across waves; scr holds NT/64 elements per group.  Other
+// NT (3 * 2^k lengths): Hillis-Steele in LDS; scr holds 2 NT elements per
+// group.  Contains __syncthreads: every thread of the workgroup must call it.
+template <int NT>
+struct ScanScratch {
+  static constexpr bool POW2 = (NT & (NT - 1)) == 0;
+  static constexpr int SIZE = POW2 ? (NT > 64 ? NT / 64 : 1) : 2 * NT;
+};
+
 template <typename T, int NT>
 __device__ __forceinline__ cx<T> group_scan(cx<T> v, cx<T>* scr, int t) {
+  if constexpr (!ScanScratch<NT>::POW2) {
+    cx<T>* a = scr;
+    cx<T>* b = scr + NT;
+    a[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int d = 1; d < NT; d <<= 1) {
+      const cx<T> x = (t >= d) ? a[t] + a[t - d] : a[t];
+      b[t] = x;
+      __syncthreads();
+      cx<T>* tmp = a;
+      a = b;
+      b = tmp;
+    }
+    const cx<T> r = a[t];
+    __syncthreads();
+    return r;
+  }
   constexpr int W = NT < 64 ? NT : 64;
 #pragma unroll
   for (int d = 1; d < W; d <<= 1) {
@@ -182,6 +219,7 @@ __device__ __forceinline__ cx<T> group_scan(cx<T> v, cx<T>* scr, int t) {
 template <typename T, int N>
 __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t) {
   constexpr int NT = N / 8;
+  static_assert(N % 8 == 0, "n must be a multiple of 8");
   const cx<T>* sintab = tw + N;
   // pre-processing, one thread per pair (j, n - j), j = 1..n/2
   for (int j = 1 + t; j <= N / 2; j += NT) {

@@ -4,9 +4,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <complex>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hp.h"
@@ -134,11 +138,17 @@ struct Prof {
   }
 };
 
-bool pow2_size(int n) { return n >= 64 && n <= 2048 && (n & (n - 1)) == 0; }
+// grid sizes with a compiled transform: 2^k (64..2048) and 3 * 2^k (192..1536)
+bool fft_size(int n) {
+  if (n < 64 || n > 2048) return false;
+  if ((n & (n - 1)) == 0) return true;
+  const int m = n / 3;
+  return n % 3 == 0 && (m & (m - 1)) == 0 && m >= 64;
+}
 
 std::string validate(const hp_plan_desc* d) {
   if (!d) return "desc is NULL";
-  if (!pow2_size(d->nx) || !pow2_size(d->ny)) return "nx, ny must be powers of two in [64, 2048]";
+  if (!fft_size(d->nx) || !fft_size(d->ny)) return "nx, ny must be 2^k or 3 * 2^k in [64, 2048]";
   if (d->ncomp != 1 && d->ncomp != 2) return "ncomp must be 1 or 2";
   if (d->precision != HP_FP64 && d->precision != HP_MIXED) return "precision must be HP_FP64 or HP_MIXED";
   if (d->ncomp == 2 && d->precision == HP_FP64 && d->nx > 1024) return "FP64 vector plans support n <= 1024";
@@ -341,7 +351,7 @@ int restart_pole(hp_plan p, int k) {
 // set on the device).  Cycle ends that need the true residual (mixed
 // precision, restarts, flag 3) are handled on the host between launches.
 template <typename T>
-int run_step(hp_plan p, const c128* w, c128* out) {
+int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* noconv_out) {
   const hp_plan_desc& d = p->d;
   const size_t fn = p->fieldn;
   const int K = d.npoles, M = d.restart;
@@ -358,7 +368,7 @@ int run_step(hp_plan p, const c128* w, c128* out) {
     launch_row_fwd<T>(w, bR, p->part_misc, twx, p->geo, p->stream);
   }
   bool changed = false;
-  for (int k = 0; k < K; ++k) {
+  for (int k : subset) {
     if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)bR) {
       p->uptr_h[(size_t)k * (HP_MAXM + 1)] = bR;
       changed = true;
@@ -369,11 +379,13 @@ int run_step(hp_plan p, const c128* w, c128* out) {
     if (rc) return rc;
   }
   int* act0 = p->active_h + 2 * HP_MAXPOLES;  // pinned slot for the initial list
-  for (int k = 0; k < K; ++k) act0[k] = k;
-  HPCHK(hipMemcpyAsync(p->active_d, act0, K * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, p->active_d, K, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
+  const int ns = (int)subset.size();
+  for (int a = 0; a < ns; ++a) act0[a] = subset[a];
+  HPCHK(hipMemcpyAsync(p->active_d, act0, ns * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
                     p->mixed ? kInnerRtolMixed : 0.0, p->stream);
-  std::vector<char> live(K, 1);
+  std::vector<char> live(K, 0);
+  for (int k : subset) live[k] = 1;
   std::vector<long> since(K, 0);  // iteration at which the pole's current cycle started
   std::vector<int> cycles(K, 0), done_m(K, 0);
   p->relres.assign(K, -1.0);
@@ -496,14 +508,47 @@ int run_step(hp_plan p, const c128* w, c128* out) {
       since[k] = next_iter;
     }
   }
+  p->m_h = done_m;
+  *noconv_out = noconv;
+  HPCHK(hipGetLastError());
+  return HP_OK;
+}
+
+template <typename T>
+int run_step(hp_plan p, const c128* w, c128* out) {
+  const hp_plan_desc& d = p->d;
+  const int K = d.npoles;
+  std::vector<int> all(K);
+  for (int k = 0; k < K; ++k) all[k] = k;
+  bool noconv = false;
+  int rc = run_poles<T>(p, w, all, &noconv);
+  if (rc) return rc;
   {
+    const double es = (double)sizeof(cx<T>);
+    const double U1 = (double)(d.nx - 1) * (d.ny - 1) * d.ncomp;
     double terms = 0.0;
-    for (int k = 0; k < K; ++k) terms += done_m[k];
+    for (int k = 0; k < K; ++k) terms += p->m_h[k];
     Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
-    launch_final<T>(w, out, Zb, zsp, zsi, p->X, fn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta,
-                    d.edge_width, p->tw64_x, p->geo, p->stream);
+    launch_final<T>(w, out, reinterpret_cast<cx<T>*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
+                    p->fieldn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta, d.edge_width, p->tw64_x,
+                    p->geo, p->stream);
   }
   HPCHK(hipGetLastError());
+  return noconv ? HP_WARN_NOCONV : HP_OK;
+}
+
+// One shifted solve (Zbar - b_k I) x = rhs; x physical complex128.
+template <typename T>
+int run_solve(hp_plan p, int k, const c128* rhs, c128* x) {
+  bool noconv = false;
+  int rc = run_poles<T>(p, rhs, std::vector<int>{k}, &noconv);
+  if (rc) return rc;
+  const size_t fn = p->fieldn;
+  launch_accum<T>(p->X + (size_t)k * fn, fld<T>(p->Z, (size_t)k * p->d.restart, fn), fn, p->st, k, p->geo,
+                  p->stream);
+  launch_row_inv<double>(p->X + (size_t)k * fn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+  HPCHK(hipGetLastError());
+  HPCHK(hipStreamSynchronize(p->stream));
   return noconv ? HP_WARN_NOCONV : HP_OK;
 }
 
@@ -684,6 +729,16 @@ int hp_step(hp_plan p, const void* E_in, const double* n2, void* E_out) {
   return p->mixed ? run_step<float>(p, w, out) : run_step<double>(p, w, out);
 }
 
+int hp_solve(hp_plan p, int pole, const void* rhs, void* x) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!rhs || !x) return fail(p, HP_EINVAL, "rhs/x is NULL");
+  if (pole < 0 || pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
+  const c128* r = reinterpret_cast<const c128*>(rhs);
+  c128* o = reinterpret_cast<c128*>(x);
+  return p->mixed ? run_solve<float>(p, pole, r, o) : run_solve<double>(p, pole, r, o);
+}
+
 int hp_propagate(hp_plan p, const void* E_in, const double* n2, long n2_step_stride, int nsteps, void* E_out) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
   if (nsteps < 0) return fail(p, HP_EINVAL, "nsteps < 0");
@@ -806,6 +861,169 @@ void hp_plan_destroy(hp_plan p) {
   for (hipEvent_t e : p->iter_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+
+struct hp_batch_s {
+  std::vector<hp_plan_desc> descs;
+  std::vector<std::vector<hp_c128>> poles, residues;
+  std::vector<std::vector<double>> d2, d1;
+  int nworkers = 1;
+  size_t ws_bytes = 0;                 // largest problem's workspace
+  std::vector<void*> worker_ws;        // one workspace per worker, kept across calls
+  std::vector<long> iters;
+  std::vector<double> seconds;
+};
+
+extern "C" {
+
+int hp_batch_create(const hp_plan_desc* descs, int nprob, int nworkers, hp_batch* out) {
+  if (!out) return fail(nullptr, HP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || nprob < 1) return fail(nullptr, HP_EINVAL, "no problems");
+  if (nworkers < 1 || nworkers > 64) return fail(nullptr, HP_EINVAL, "nworkers must be in [1, 64]");
+  for (int i = 0; i < nprob; ++i) {
+    std::string v = validate(&descs[i]);
+    if (!v.empty()) return fail(nullptr, HP_EINVAL, "problem " + std::to_string(i) + ": " + v);
+  }
+  hp_batch b = new (std::nothrow) hp_batch_s();
+  if (!b) return fail(nullptr, HP_ENOMEM, "host allocation failed");
+  b->nworkers = nworkers;
+  b->descs.assign(descs, descs + nprob);
+  b->poles.resize(nprob);
+  b->residues.resize(nprob);
+  b->d2.resize(nprob);
+  b->d1.resize(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const hp_plan_desc& d = descs[i];
+    b->poles[i].assign(d.poles, d.poles + d.npoles);
+    b->residues[i].assign(d.residues, d.residues + d.npoles);
+    b->d2[i].assign(d.d2, d.d2 + 7);
+    b->d1[i].assign(d.d1, d.d1 + 6);
+    b->descs[i].poles = b->poles[i].data();
+    b->descs[i].residues = b->residues[i].data();
+    b->descs[i].d2 = b->d2[i].data();
+    b->descs[i].d1 = b->d1[i].data();
+  }
+  b->iters.assign(nprob, 0);
+  b->seconds.assign(nprob, 0.0);
+  for (int i = 0; i < nprob; ++i) b->ws_bytes = std::max(b->ws_bytes, hp_workspace_bytes(&b->descs[i]));
+  b->worker_ws.assign(nworkers, nullptr);
+  *out = b;
+  return HP_OK;
+}
+
+int hp_batch_propagate(hp_batch b, const void* const* E_in, const double* const* n2, const int* nsteps,
+                       void* const* E_out) {
+  if (!b) return fail(nullptr, HP_EINVAL, "batch is NULL");
+  if (!E_in || !n2 || !nsteps || !E_out) return fail(nullptr, HP_EINVAL, "NULL argument");
+  const int nprob = (int)b->descs.size();
+  for (int i = 0; i < nprob; ++i)
+    if (!E_in[i] || !E_out[i] || !n2[i] || nsteps[i] < 0) return fail(nullptr, HP_EINVAL, "bad problem arguments");
+  // longest first
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const hp_plan_desc& d = b->descs[i];
+    return (double)d.nx * d.ny * d.ncomp * d.npoles * (double)nsteps[i];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(nullptr, HP_EHIP, "hipGetDevice failed");
+  std::atomic<int> next(0);
+  std::mutex mu;
+  int worst = HP_OK;
+  std::string first_err;
+  std::atomic<int> wid(0);
+  auto worker = [&]() {
+    if (hipSetDevice(device) != hipSuccess) return;
+    const int me = wid.fetch_add(1);
+    if (!b->worker_ws[me] && hipMalloc(&b->worker_ws[me], b->ws_bytes) != hipSuccess) {
+      b->worker_ws[me] = nullptr;
+      std::lock_guard<std::mutex> g(mu);
+      if (worst >= 0) worst = HP_ENOMEM, first_err = "worker workspace allocation failed";
+      return;
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreate(&s) != hipSuccess) {
+      std::lock_guard<std::mutex> g(mu);
+      if (worst >= 0) worst = HP_EHIP, first_err = "hipStreamCreate failed";
+      return;
+    }
+    for (;;) {
+      const int slot = next.fetch_add(1);
+      if (slot >= nprob) break;
+      const int i = order[slot];
+      const auto t0 = std::chrono::steady_clock::now();
+      hp_plan p = nullptr;
+      int rc = hp_plan_create(&b->descs[i], s, b->worker_ws[me], &p);
+      if (rc >= 0) {
+        const int mrc = hp_set_medium(p, n2[i]);
+        if (mrc < 0) rc = mrc;
+      }
+      long it = 0;
+      int worst_i = HP_OK;
+      if (rc >= 0) {
+        const void* src = E_in[i];
+        for (int st = 0; st < nsteps[i] && rc >= 0; ++st) {
+          rc = hp_step(p, src, nullptr, E_out[i]);
+          if (rc < 0) break;
+          worst_i = std::max(worst_i, rc);
+          std::vector<int> its(b->descs[i].npoles);
+          if (hp_get_stats(p, its.data(), nullptr) == HP_OK)
+            for (int v : its) it += v;
+          src = E_out[i];
+        }
+        if (rc >= 0 && nsteps[i] == 0 && E_out[i] != E_in[i]) {
+          const size_t bytes = (size_t)b->descs[i].nx * b->descs[i].ny * b->descs[i].ncomp * sizeof(hp_c128);
+          if (hipMemcpyAsync(E_out[i], E_in[i], bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) rc = HP_EHIP;
+        }
+      }
+      std::string msg = (rc < 0) ? std::string(p ? hp_last_error(p) : hp_last_error(nullptr)) : std::string();
+      if (p) hp_plan_destroy(p);
+      (void)hipStreamSynchronize(s);
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      std::lock_guard<std::mutex> g(mu);
+      b->iters[i] = it;
+      b->seconds[i] = sec;
+      if (rc < 0) {
+        if (worst >= 0) {
+          worst = rc;
+          first_err = "problem " + std::to_string(i) + ": " + msg;
+        }
+      } else if (worst >= 0) {
+        worst = std::max(worst, worst_i);
+      }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  };
+  const int nw = std::min(b->nworkers, nprob);
+  std::vector<std::thread> threads;
+  for (int w = 0; w < nw; ++w) threads.emplace_back(worker);
+  for (auto& t : threads) t.join();
+  if (worst < 0) return fail(nullptr, worst, first_err);
+  return worst;
+}
+
+int hp_batch_stats(hp_batch b, long* iters, double* seconds) {
+  if (!b) return fail(nullptr, HP_EINVAL, "batch is NULL");
+  for (size_t i = 0; i < b->descs.size(); ++i) {
+    if (iters) iters[i] = b->iters[i];
+    if (seconds) seconds[i] = b->seconds[i];
+  }
+  return HP_OK;
+}
+
+void hp_batch_destroy(hp_batch b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  for (void* w : b->worker_ws)
+    if (w) (void)hipFree(w);
+  delete b;
 }
 
 }  // extern "C"

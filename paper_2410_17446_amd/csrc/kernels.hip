@@ -42,7 +42,7 @@ struct RowCfg {
   static constexpr int RPW = (256 / NT) > 0 ? 256 / NT : 1;  // transforms per workgroup
   static constexpr int WG = RPW * NT;
   static constexpr int PT = N / NT;                          // values per thread per row (8)
-  static constexpr int SCR = NT > 64 ? NT / 64 : 1;          // scan scratch per transform
+  static constexpr int SCR = ScanScratch<NT>::SIZE;          // scan scratch per transform
 };
 
 constexpr int kColLdsBytes = 40960;  // several column workgroups per CU
@@ -54,9 +54,12 @@ struct ColCfg {
   static constexpr int PB = plen(N) * (int)sizeof(cx<T>);
   static constexpr int G0 = kColLdsBytes / PB;
   static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
-  static constexpr int GC = (G1 * NT > 1024) ? 1024 / NT : G1;  // columns transformed at once
+  static constexpr int G2 = (G1 * NT > 1024) ? 1024 / NT : G1;
+  // columns transformed at once: a power of two, so that it divides the tile width
+  static constexpr int GC = G2 >= 16 ? 16 : G2 >= 8 ? 8 : G2 >= 4 ? 4 : G2 >= 2 ? 2 : 1;
+  static_assert(TW % GC == 0, "column groups tile the 128-byte row");
   static constexpr int WG = GC * NT;
-  static constexpr int SCR = NT > 64 ? NT / 64 : 1;
+  static constexpr int SCR = ScanScratch<NT>::SIZE;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -254,12 +257,12 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
 template <int N, int NC>
 struct ApplyCfg {
   static constexpr int NT = N / 8;
-  static constexpr int G0 = 256 / NT;
+  static constexpr int G0 = (256 / NT) / NC * NC;
   static constexpr int GROUPS = G0 < NC ? NC : G0;  // transforms per workgroup (NC per row)
   static constexpr int ROWS = GROUPS / NC;
   static constexpr int WG = GROUPS * NT;
   static constexpr int WAVES = (WG + 63) / 64;
-  static constexpr int SCR = NT > 64 ? NT / 64 : 1;
+  static constexpr int SCR = ScanScratch<NT>::SIZE;
 };
 
 template <typename T, int N, int NC>
@@ -972,9 +975,13 @@ __global__ void k_fill_zero(c128* p, size_t n) {
   switch (n) {                  \
     case 64: MACRO(64); break;  \
     case 128: MACRO(128); break;  \
+    case 192: MACRO(192); break;  \
     case 256: MACRO(256); break;  \
+    case 384: MACRO(384); break;  \
     case 512: MACRO(512); break;  \
+    case 768: MACRO(768); break;  \
     case 1024: MACRO(1024); break; \
+    case 1536: MACRO(1536); break; \
     case 2048: MACRO(2048); break; \
     default: break;             \
   }
@@ -1030,21 +1037,22 @@ void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, 
 #undef L_
 }
 
+static int apply_groups(const Geo& g) {
+  const int nt = g.nx / 8;
+  int groups = (256 / nt) / g.ncomp * g.ncomp;
+  if (groups < g.ncomp) groups = g.ncomp;
+  return groups;
+}
+
 template <typename T>
 int row_apply_blocks(const Geo& g) {
-  const int nt = g.nx / 8;
-  int groups = 256 / nt;
-  if (groups < g.ncomp) groups = g.ncomp;
-  const int rows = groups / g.ncomp;
+  const int rows = apply_groups(g) / g.ncomp;
   return (g.ny - 1 + rows - 1) / rows;
 }
 
 template <typename T>
 int row_apply_parts(const Geo& g) {
-  const int nt = g.nx / 8;
-  int groups = 256 / nt;
-  if (groups < g.ncomp) groups = g.ncomp;
-  return row_apply_blocks<T>(g) * ((groups * nt + 63) / 64);
+  return row_apply_blocks<T>(g) * ((apply_groups(g) * (g.nx / 8) + 63) / 64);
 }
 
 template <typename T>

@@ -19,9 +19,10 @@ _lib = None
 HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
 HP_FP64, HP_MIXED = 0, 1
 
-SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_propagate",
+SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
            "hp_get_stats", "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
-           "hp_profile", "hp_profile_read", "hp_last_error", "hp_plan_destroy")
+           "hp_profile", "hp_profile_read", "hp_last_error", "hp_plan_destroy",
+           "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
 KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
 
 
@@ -56,6 +57,7 @@ def lib():
         L.hp_set_medium.argtypes = [vp, vp]
         L.hp_step.argtypes = [vp, vp, vp, vp]
         L.hp_propagate.argtypes = [vp, vp, vp, C.c_long, C.c_int, vp]
+        L.hp_solve.argtypes = [vp, C.c_int, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
         L.hp_set_fixed_iters.argtypes = [vp, ip]
         L.hp_apply_operator.argtypes = [vp, C.c_int, vp, vp]
@@ -65,8 +67,12 @@ def lib():
         L.hp_last_error.argtypes = [vp]
         L.hp_last_error.restype = C.c_char_p
         L.hp_plan_destroy.argtypes = [vp]
+        L.hp_batch_create.argtypes = [C.POINTER(hp_plan_desc), C.c_int, C.c_int, C.POINTER(vp)]
+        L.hp_batch_propagate.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), ip, C.POINTER(vp)]
+        L.hp_batch_stats.argtypes = [vp, C.POINTER(C.c_long), dp]
+        L.hp_batch_destroy.argtypes = [vp]
         for name in SYMBOLS:
-            if name not in ("hp_workspace_bytes", "hp_last_error", "hp_plan_destroy"):
+            if name not in ("hp_workspace_bytes", "hp_last_error", "hp_plan_destroy", "hp_batch_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -137,6 +143,13 @@ class Plan:
         self._check(rc, "hp_propagate")
         return E_out
 
+    def solve(self, pole, rhs, x=None):
+        import torch
+        if x is None:
+            x = torch.empty_like(rhs)
+        self._check(self.L.hp_solve(self.handle, pole, _ptr(rhs), _ptr(x)), "hp_solve")
+        return x
+
     def stats(self):
         it = (C.c_int * self.npoles)()
         rr = (C.c_double * self.npoles)()
@@ -170,6 +183,74 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             self.L.hp_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_desc(nx, ny, dx, dy, k0, n0, dz, ncomp, poles, residues, r_inf, d2, d1, edge_width, edge_eta, tol,
+              restart=30, max_cycles=20, precision=HP_FP64):
+    """An hp_plan_desc plus the ctypes arrays it points to (keep both alive)."""
+    poles = np.asarray(poles, dtype=np.complex128)
+    residues = np.asarray(residues, dtype=np.complex128)
+    keep = ((hp_c128 * len(poles))(*[hp_c128(p.real, p.imag) for p in poles]),
+            (hp_c128 * len(residues))(*[hp_c128(a.real, a.imag) for a in residues]),
+            (C.c_double * 7)(*np.asarray(d2, dtype=float)),
+            (C.c_double * 6)(*np.asarray(d1, dtype=float)))
+    r_inf = complex(r_inf)
+    d = hp_plan_desc(nx, ny, dx, dy, k0, n0, dz, ncomp, len(poles), keep[0], keep[1],
+                     hp_c128(r_inf.real, r_inf.imag), keep[2], keep[3], edge_width, edge_eta, tol, restart,
+                     max_cycles, precision)
+    return d, keep
+
+
+class Batch:
+    """Independent propagations run concurrently by the library (hp_batch_*).
+    problems: list of dicts with the Plan keyword arguments."""
+
+    def __init__(self, problems, nworkers=8):
+        self.L = lib()
+        descs, self._keep = [], []
+        for pr in problems:
+            d, keep = make_desc(**pr)
+            descs.append(d)
+            self._keep.append(keep)
+        self.n = len(descs)
+        self._descs = (hp_plan_desc * self.n)(*descs)
+        self.handle = C.c_void_p()
+        rc = self.L.hp_batch_create(self._descs, self.n, nworkers, C.byref(self.handle))
+        if rc < 0:
+            raise HPError(f"hp_batch_create: {rc}: {self.L.hp_last_error(None).decode()}")
+        self.shapes = [(pr["ncomp"], pr["ny"], pr["nx"]) for pr in problems]
+
+    def propagate(self, E_in, n2, nsteps, E_out=None):
+        import torch
+        if E_out is None:
+            E_out = [torch.empty_like(e) for e in E_in]
+        vp = C.c_void_p
+        a_in = (vp * self.n)(*[vp(_ptr(e)) for e in E_in])
+        a_n2 = (vp * self.n)(*[vp(_ptr(m)) for m in n2])
+        a_out = (vp * self.n)(*[vp(_ptr(e)) for e in E_out])
+        a_st = (C.c_int * self.n)(*nsteps)
+        rc = self.L.hp_batch_propagate(self.handle, a_in, a_n2, a_st, a_out)
+        if rc < 0:
+            raise HPError(f"hp_batch_propagate: {rc}: {self.L.hp_last_error(None).decode()}")
+        self.status = rc
+        return E_out
+
+    def stats(self):
+        it = (C.c_long * self.n)()
+        sec = (C.c_double * self.n)()
+        self.L.hp_batch_stats(self.handle, it, sec)
+        return list(it), list(sec)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.L.hp_batch_destroy(self.handle)
             self.handle = C.c_void_p()
 
     def __del__(self):

@@ -22,7 +22,7 @@ def workload(N=64, ncomp=1, W=8, eta=0.25, npoles=8, dz=1.0, medium=("sine", 0.0
     cfg = dict(N=N, dx=dx, ncomp=ncomp, W=W, eta_max=eta, dz=dz, npoles=npoles, tol=tol,
                restart=restart, medium=medium, w0=w0)
     if ny == N:
-        n2 = inputs.medium_n2(cfg)
+        n2 = inputs.medium_n2(cfg) if medium[0] != "uniform" else np.ones((N, N))
         w = inputs.beam(cfg)
     else:
         n2 = np.ones((ny, N))

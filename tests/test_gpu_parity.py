@@ -178,3 +178,107 @@ def test_non_square_grid():
     assert np.isfinite(o).all() and o.shape == (1, 128, 64)
     _, rr = plan.stats()
     assert max(rr) <= 1e-10
+
+
+def test_batch_equals_single_plans():
+    """Concurrent batch (uneven sizes, pole counts, media) gives the same fields as one plan at a time."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp
+    specs = [(64, 8, ("sine", 0.05, 2.0)), (128, 12, ("sine", 0.02, 1.0)), (64, 16, ("grf", 1e-3, 2.0, 5)),
+             (256, 8, ("sine", 0.02, 1.0)), (128, 8, ("grf", 1e-3, 2.0, 6)), (64, 12, ("sine", 0.05, 2.0))]
+    problems, ins, meds, singles = [], [], [], []
+    for N, npoles, med in specs:
+        wl = workload(N=N, W=N // 8, npoles=npoles, medium=med, w0=N * 0.25 / 8, tol=1e-8)
+        f = wl["fit"]
+        pr = dict(nx=N, ny=N, dx=0.25, dy=0.25, k0=2 * np.pi, n0=1.0, dz=1.0, ncomp=1, poles=f["poles"],
+                  residues=f["residues"], r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"], edge_width=N // 8,
+                  edge_eta=0.25, tol=1e-8)
+        problems.append(pr)
+        ins.append(to_gpu(wl["w"]))
+        meds.append(to_gpu(wl["n2"]))
+        plan = hp.Plan(**pr)
+        singles.append(plan.propagate(ins[-1], 3, n2=meds[-1]).cpu().numpy())
+        plan.close()
+    b = hp.Batch(problems, nworkers=4)
+    outs = b.propagate(ins, meds, [3] * len(specs))
+    torch.cuda.synchronize()
+    it, sec = b.stats()
+    for o, ref in zip(outs, singles):
+        assert np.array_equal(o.cpu().numpy(), ref)
+    assert all(i > 0 for i in it)
+
+
+def test_solve_full_size_scalar1024():
+    """Bench configuration (1024^2, 16 poles, sine medium): single-pole solves against the oracle at
+    full size, with the oracle's iteration count replayed."""
+    torch = _cuda()
+    from oracle import step as st_mod
+    wl = workload(N=1024, W=128, npoles=16, medium=("sine", 0.02, 1.0), w0=32.0, tol=1e-8)
+    g = oracle_grid(wl)
+    co = op.coefficients(g, wl["n2"], False)
+    plan = gpu_plan(wl)
+    plan.set_medium(to_gpu(wl["n2"]))
+    w = to_gpu(wl["w"])
+    for pole in (6, 12):
+        res = st_mod.solve_pole(g, co, wl["w"], wl["fit"]["poles"][pole], 1e-8, 30)
+        iters = [1] * 16
+        iters[pole] = res.iters
+        plan.set_fixed_iters(iters)
+        x = plan.solve(pole, w).cpu().numpy()
+        ref = op.unpack(res.x, 1, 1024)
+        assert rel_l2(x, ref) < 1e-10, (pole, res.iters)
+    plan.set_fixed_iters(None)
+    x = plan.solve(12, w)
+    it, rr = plan.stats()
+    assert rr[12] <= 1e-8
+
+
+def test_vector2048_properties():
+    """2048^2 vector grid (mixed precision): homogeneous medium keeps E_y = 0 and E_x equal to the
+    scalar step; in a random medium every pole meets tol on its FP64 true residual."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp, inputs
+    N = 2048
+    wl = workload(N=N, ncomp=2, W=256, npoles=8, medium=("uniform",), w0=64.0, tol=1e-8)
+    wl["n2"] = np.ones((N, N))
+    vec = gpu_plan(wl, precision=1)
+    out_v = vec.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    vec.close()
+    wl_s = dict(wl)
+    wl_s["cfg"] = dict(wl["cfg"], ncomp=1)
+    sca = gpu_plan(wl_s, precision=1)
+    out_s = sca.step(to_gpu(wl["w"][:1].copy()), to_gpu(wl["n2"]))
+    sca.close()
+    assert float(out_v[1].abs().max()) == 0.0
+    assert rel_l2(out_v[0].cpu().numpy(), out_s[0].cpu().numpy()) < 1e-6
+    del out_v, out_s
+    cfg = inputs.CONFIGS["vector2048"]
+    wl = workload(N=N, ncomp=2, W=256, npoles=24, medium=cfg["medium"], w0=64.0, tol=1e-8)
+    plan = gpu_plan(wl, precision=1)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    it, rr = plan.stats()
+    assert np.isfinite(out.cpu().numpy()).all()
+    assert max(rr) <= 1e-8, rr
+    assert float(out[1].abs().max()) > 0.0   # cross-polarisation appears in the random medium
+
+
+@pytest.mark.parametrize("N,precision", [(192, 0), (384, 0), (768, 1)])
+def test_radix3_sizes(N, precision):
+    """3 * 2^k grids (radix-3 stage): preconditioner and one step against the oracle."""
+    torch = _cuda()
+    wl = workload(N=N, W=N // 8, npoles=8, medium=("sine", 0.02, 1.0), w0=N * 0.25 / 8, tol=1e-10)
+    g = oracle_grid(wl)
+    lam = precond.spectrum(g)
+    eps = 2.2e-16 if precision == 0 else 1.2e-7
+    plan = gpu_plan(wl, precision=precision)
+    x = inputs.random_field(N, 1, seed=8)
+    b = wl["fit"]["poles"][3]
+    y = torch.zeros_like(to_gpu(x))
+    plan.apply_preconditioner(3, to_gpu(x), y)
+    kappa = np.abs(lam - b).max() / np.abs(lam - b).min()
+    assert rel_l2(y.cpu().numpy(), precond.apply_minv(g, x, b)) < 20 * eps * kappa
+    if precision == 0:
+        ref, stats = _oracle_step(wl)
+        plan.set_fixed_iters([sum(c) for c in stats.cycle_iters])
+        out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+        assert rel_l2(out.cpu().numpy(), ref) < 1e-10
