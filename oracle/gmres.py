@@ -61,19 +61,26 @@ def _lsq(Hbar: np.ndarray, beta: complex):
 
 
 def gmres(A, Minv, b: np.ndarray, tol: float, restart: int = 30, max_cycles: int = 20,
-          schedule: list | None = None) -> GmresResult:
-    """Solve A x = b, x0 = 0, with right preconditioner Minv (both callables on flat vectors)."""
+          schedule: list | None = None, x0: np.ndarray | None = None) -> GmresResult:
+    """Solve A x = b with right preconditioner Minv (both callables on flat vectors), starting
+    from x0 (zero when None).  The iterate of a cycle started at x is x + Minv(V y), V the
+    cycle's Arnoldi basis of A Minv from r = b - A x (Saad 2003, Algorithm 9.5); the
+    stopping test stays relative to ||b||, whatever the start."""
     bnorm = np.linalg.norm(b)
-    x = np.zeros_like(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=complex)
     if bnorm == 0.0:
-        return GmresResult(x=x, iters=0, cycles=0, relres=0.0)
+        return GmresResult(x=np.zeros_like(b), iters=0, cycles=0, relres=0.0)
     total = 0
     cycle_iters = []
     relres = 1.0
+    if x0 is not None:
+        relres = float(np.linalg.norm(b - A(x)) / bnorm)
+        if schedule is None and relres <= tol:
+            return GmresResult(x=x, iters=0, cycles=0, relres=relres)
     ncycles = len(schedule) if schedule is not None else max_cycles
     for cyc in range(ncycles):
         m = schedule[cyc] if schedule is not None else restart
-        r0 = b - A(x) if cyc > 0 else b.copy()
+        r0 = b - A(x) if (cyc > 0 or x0 is not None) else b.copy()
         z = r0
         Ws = []
         H = np.zeros((m + 1, m), dtype=complex)

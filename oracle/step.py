@@ -37,23 +37,38 @@ class StepStats:
 
 
 def solve_pole(g: op.Grid, co: op.Coefficients, w: np.ndarray, b_k: complex, tol: float,
-               restart: int = 30, schedule=None, workers: int = -1):
+               restart: int = 30, schedule=None, workers: int = -1, x0: np.ndarray | None = None):
+    """(Zbar - b_k I) x = w by preconditioned GMRES; x0 (ncomp, N, N) an optional start."""
     ncomp, N = w.shape[0], g.N
     A = lambda x: op.pack(op.apply_shifted(g, co, op.unpack(x, ncomp, N), b_k))
     Minv = lambda v: op.pack(apply_minv(g, op.unpack(v, ncomp, N), b_k, workers))
-    return gmres(A, Minv, op.pack(w), tol, restart=restart, schedule=schedule)
+    return gmres(A, Minv, op.pack(w), tol, restart=restart, schedule=schedule,
+                 x0=None if x0 is None else op.pack(x0))
+
+
+def judge_guess(g: op.Grid, co: op.Coefficients, w: np.ndarray, b_k: complex, x0) -> bool:
+    """The fallback rule for an initial guess: use x0 only when its residual is below that of
+    the zero start, ||w - (Zbar - b_k I) x0|| < ||w||."""
+    if x0 is None:
+        return False
+    r0 = w - op.apply_shifted(g, co, x0, b_k)
+    return bool(np.linalg.norm(r0) < np.linalg.norm(w))
 
 
 def step(g: op.Grid, co: op.Coefficients, w: np.ndarray, pf: PFTable, dz: float, tol: float,
-         restart: int = 30, schedules=None, workers: int = -1):
-    """Advance the envelope field w (ncomp, N, N) by one step dz."""
+         restart: int = 30, schedules=None, workers: int = -1, guesses=None):
+    """Advance the envelope field w (ncomp, N, N) by one step dz.  guesses: None or one
+    initial guess (or None) per pole, each used only if judge_guess accepts it."""
     K = g.k0 * g.n0 * dz
     ncomp, N = w.shape[0], g.N
     acc = pf.r_inf * op.pack(w)
     iters, relres, cyc = [], [], []
     for k, (b_k, a_k) in enumerate(zip(pf.poles, pf.residues)):
+        x0 = None if guesses is None else guesses[k]
+        if not judge_guess(g, co, w, b_k, x0):
+            x0 = None
         res = solve_pole(g, co, w, b_k, tol, restart,
-                         schedule=None if schedules is None else schedules[k], workers=workers)
+                         schedule=None if schedules is None else schedules[k], workers=workers, x0=x0)
         acc = acc + a_k * res.x
         iters.append(res.iters)
         relres.append(res.relres)

@@ -225,6 +225,36 @@ def test_gmres_krylov_minimiser():
     assert np.linalg.norm(res.x - Kr @ coef) < 1e-9 * np.linalg.norm(res.x)
 
 
+def test_gmres_initial_guess_krylov_minimiser():
+    """From x0, k steps give the minimiser of ||b - A x|| over x0 + M^-1 K_k(A M^-1, r0),
+    r0 = b - A x0 (brute-force least squares over that affine space)."""
+    rng = np.random.default_rng(8)
+    n, k = 30, 4
+    A = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    Mi = np.diag(1.0 / (1.0 + 0.5 * rng.random(n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x0 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    res = gmres(lambda x: A @ x, lambda v: Mi @ v, b, tol=0.0, schedule=[k], x0=x0)
+    r0 = b - A @ x0
+    AM = A @ Mi
+    Kr = np.stack([np.linalg.matrix_power(AM, i) @ r0 for i in range(k)], axis=1)
+    coef, *_ = np.linalg.lstsq(AM @ Kr, r0, rcond=None)
+    assert np.linalg.norm(res.x - (x0 + Mi @ Kr @ coef)) < 1e-9 * np.linalg.norm(res.x)
+
+
+def test_gmres_exact_guess_needs_no_iteration():
+    rng = np.random.default_rng(9)
+    n = 25
+    A = 4 * np.eye(n) + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    res = gmres(lambda x: A @ x, lambda v: v, b, tol=1e-10, x0=xs)
+    assert res.iters == 0 and res.relres < 1e-13
+    # a guess of the right size but wrong: still converges to the dense solution
+    res = gmres(lambda x: A @ x, lambda v: v, b, tol=1e-12, x0=xs + 0.1 * rng.standard_normal(n))
+    assert np.linalg.norm(res.x - xs) < 1e-10 * np.linalg.norm(xs)
+
+
 # ---------------------------------------------------------------- one step (Sec. 2, eqs. Wk_define .. W_k_def)
 
 def _grid(N, W=6, eta=0.0, dx=0.25):
@@ -371,3 +401,29 @@ def test_layer_loss_profile():
     assert np.isclose(m[1, 16], np.exp(-K2PI * 0.25 / 2))
     assert np.isclose(m[16, 8], np.exp(-K2PI * 0.25 * (1 / 8) ** 2 / 2))
     assert m[16, 9] == 1.0
+
+
+def test_step_guesses_fallback_and_exact():
+    """Guesses do not change what a step computes: exact per-pole solutions as guesses give the
+    plain step's output to the solve tolerance without an Arnoldi step; guesses whose residual
+    exceeds ||w|| are rejected and the output is the plain one, bit for bit."""
+    N = 24
+    g = _grid(N, W=6, eta=0.2)
+    pf = _pf(6)
+    n2 = inputs.sine_product_n2(N, 0.25, 0.05, 2.0)
+    co = op.coefficients(g, n2, False)
+    w = inputs.random_field(N, 1, seed=11)
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    plain, _ = st.step(g, co, w, pf, 1.0, 1e-12)
+    xs = []
+    for b in pf.poles:
+        A = op.dense_zbar(g, co, 1) - b * np.eye((N - 1) ** 2)
+        xs.append(op.unpack(np.linalg.solve(A, op.pack(w)), 1, N))
+    out, stats = st.step(g, co, w, pf, 1.0, 1e-12, guesses=xs)
+    assert stats.iters == [0] * len(pf.poles)
+    assert np.linalg.norm(out - plain) < 1e-10 * np.linalg.norm(plain)
+    bad = [10.0 * inputs.random_field(N, 1, seed=20 + k) for k in range(len(pf.poles))]
+    assert not any(st.judge_guess(g, co, w, b, x) for b, x in zip(pf.poles, bad))
+    out, _ = st.step(g, co, w, pf, 1.0, 1e-12, guesses=bad)
+    assert np.array_equal(out, plain)
