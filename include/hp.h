@@ -122,6 +122,36 @@ int hp_propagate(hp_plan plan, const void* E_in, const double* n2, long n2_step_
  * poles at full size and to generate solve pairs. */
 int hp_solve(hp_plan plan, int pole, const void* rhs, void* x);
 
+/* Initial guesses.  The method is unchanged by them: every solve still ends
+ * on the same test ||w - A_k x_k|| <= tol ||w|| (A_k = Zbar - b_k I); a guess
+ * only moves the point GMRES starts from, x_k = x0 + M_k^{-1} V y (Sec. 4.2).
+ *
+ * hp_step_guess: one step like hp_step, with x0[k] (device [ncomp][ny][nx]
+ * complex128, or NULL for a zero start) the guess of pole k; x0 itself may be
+ * NULL (no guesses).  Each guess is judged by its FP64 residual
+ * r0 = w - A_k x0 (explicit stencils): it is used when ||r0|| < ||w||, else
+ * that pole starts from zero (the fallback).  accepted: host [npoles] or
+ * NULL; 1 where the guess was used.  One stream synchronisation per guess. */
+int hp_step_guess(hp_plan plan, const void* E_in, const double* n2, const void* const* x0, int* accepted,
+                  void* E_out);
+
+/* Start of every pole's GMRES in hp_step / hp_propagate: HP_GUESS_ZERO
+ * (default) or HP_GUESS_PREV, the same pole's solution of the previous step on
+ * this plan, judged as in hp_step_guess (the first step after the call starts
+ * from zero).  HP_GUESS_PREV keeps each pole's solution in the workspace after
+ * the step (one extra pass over each pole's Krylov basis). */
+enum { HP_GUESS_ZERO = 0, HP_GUESS_PREV = 1 };
+int hp_set_guess(hp_plan plan, int mode);
+
+/* x_k of the last step, guess step or solve for pole k (Sec. 2 eq. W_k_def):
+ * device [ncomp][ny][nx] complex128.  Synchronous. */
+int hp_get_solution(hp_plan plan, int pole, void* x);
+
+/* y = P x, the medium part of Zbar (eq. Z_bar_eq without the transverse
+ * Laplacian: V x, and for ncomp = 2 the psi terms), FP64, zero in the edge
+ * layer; x, y distinct device [ncomp][ny][nx] complex128. */
+int hp_apply_medium(hp_plan plan, const void* x, void* y);
+
 /* Statistics of the last step (synchronous): GMRES iterations and final
  * relative residual estimate per pole (either pointer may be NULL). */
 int hp_get_stats(hp_plan plan, int* iters_per_pole, double* final_relres);

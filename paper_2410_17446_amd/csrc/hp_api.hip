@@ -77,6 +77,9 @@ struct hp_plan_s {
   std::vector<double> relres;
   std::vector<int> iters;
   bool medium_set = false;
+  int guess_mode = HP_GUESS_ZERO;
+  bool prev_valid = false;        // X holds every pole's solution of the previous step
+  std::vector<int> accepted;      // per pole: the last step started from a guess
   // kernel timing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -350,8 +353,49 @@ int restart_pole(hp_plan p, int k) {
 // pole that finished in iteration j skips itself in iteration j+1 (its flag is
 // set on the device).  Cycle ends that need the true residual (mixed
 // precision, restarts, flag 3) are handled on the host between launches.
+// X_k += the current cycle's terms; afterwards X_k is pole k's whole solution.
 template <typename T>
-int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* noconv_out) {
+void fold(hp_plan p, int k) {
+  const size_t fn = p->fieldn;
+  launch_accum<T>(p->X + (size_t)k * fn, fld<T>(p->Z, (size_t)k * p->d.restart, fn), fn, p->st, k, p->geo,
+                  p->stream);
+  launch_mark_folded(p->st, k, 1, p->stream);
+}
+
+// Judge pole k's guess, held in X_k as S_x x0 (x0 physical, complex128, when
+// given as well): r0 = w - A_k x0 in FP64.  The guess is used when
+// ||r0|| < ||w||; the pole then starts its first cycle from r0 with X_k as the
+// solution so far.  Returns 1 when used, 0 when the pole keeps the zero start.
+template <typename T>
+int start_from_guess(hp_plan p, int k, const c128* w, const c128* x0, double beta0, bool* done, double* rel) {
+  const c128* xp = x0;
+  if (!xp) {
+    launch_row_inv<double>(p->X + (size_t)k * p->fieldn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+    xp = p->tmp1;
+  }
+  launch_apply_op(xp, w, p->tmp2, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc, p->geo, p->part_misc,
+                  p->stream);
+  HPCHK(hipMemcpyAsync(p->misc_h, p->part_misc, p->nopblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipStreamSynchronize(p->stream));
+  double s = 0.0;
+  for (int b = 0; b < p->nopblk; ++b) s += p->misc_h[b];
+  const double r0 = sqrt(s);
+  *done = false;
+  *rel = beta0 > 0 ? r0 / beta0 : 0.0;
+  if (!(r0 < beta0)) return 0;  // also rejects NaN
+  static const int one = 1;
+  HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
+  if (r0 <= p->d.tol * beta0) {  // already within tolerance: no Arnoldi step
+    *done = true;
+    return 1;
+  }
+  int rc = restart_pole<T>(p, k);
+  return rc ? rc : 1;
+}
+
+template <typename T>
+int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* noconv_out,
+              const c128* const* x0 = nullptr, bool use_prev = false) {
   const hp_plan_desc& d = p->d;
   const size_t fn = p->fieldn;
   const int K = d.npoles, M = d.restart;
@@ -401,6 +445,28 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     int slot;
     long iter;
   };
+  // initial guesses (explicit, or the previous step's solutions held in X)
+  p->accepted.assign(K, 0);
+  for (int k : subset) {
+    const c128* g = x0 ? x0[k] : nullptr;
+    if (!g && !use_prev) continue;
+    if (beta0 < 0) {
+      HPCHK(hipMemcpyAsync(p->misc_h, &p->st[subset[0]].beta0, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HPCHK(hipStreamSynchronize(p->stream));
+      beta0 = p->misc_h[0];
+    }
+    if (g)
+      launch_row_fwd<double>(g, p->X + (size_t)k * fn, p->part_misc, p->tw64_x, p->geo, p->stream, tile_width<T>());
+    bool done = false;
+    double rel = 0.0;
+    int rc = start_from_guess<T>(p, k, w, g, beta0, &done, &rel);
+    if (rc < 0) return rc;
+    p->accepted[k] = rc;
+    if (done) {
+      live[k] = 0;
+      p->relres[k] = rel;
+    }
+  }
   std::vector<Flight> q;
   long next_iter = 0;
   auto launch_iter = [&](const std::vector<int>& poles) -> int {
@@ -457,8 +523,11 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     return v;
   };
   {
-    int rc = launch_iter(live_list());
-    if (rc) return rc;
+    std::vector<int> v = live_list();
+    if (!v.empty()) {
+      int rc = launch_iter(v);
+      if (rc) return rc;
+    }
   }
   while (!q.empty()) {
     if (q.size() < 2) {
@@ -515,13 +584,14 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
 }
 
 template <typename T>
-int run_step(hp_plan p, const c128* w, c128* out) {
+int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullptr) {
   const hp_plan_desc& d = p->d;
   const int K = d.npoles;
   std::vector<int> all(K);
   for (int k = 0; k < K; ++k) all[k] = k;
   bool noconv = false;
-  int rc = run_poles<T>(p, w, all, &noconv);
+  const bool use_prev = !x0 && p->guess_mode == HP_GUESS_PREV && p->prev_valid;
+  int rc = run_poles<T>(p, w, all, &noconv, x0, use_prev);
   if (rc) return rc;
   {
     const double es = (double)sizeof(cx<T>);
@@ -533,6 +603,10 @@ int run_step(hp_plan p, const c128* w, c128* out) {
                     p->fieldn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta, d.edge_width, p->tw64_x,
                     p->geo, p->stream);
   }
+  if (p->guess_mode == HP_GUESS_PREV) {  // keep the solutions as the next step's guesses
+    for (int k = 0; k < K; ++k) fold<T>(p, k);
+    p->prev_valid = true;
+  }
   HPCHK(hipGetLastError());
   return noconv ? HP_WARN_NOCONV : HP_OK;
 }
@@ -543,13 +617,21 @@ int run_solve(hp_plan p, int k, const c128* rhs, c128* x) {
   bool noconv = false;
   int rc = run_poles<T>(p, rhs, std::vector<int>{k}, &noconv);
   if (rc) return rc;
-  const size_t fn = p->fieldn;
-  launch_accum<T>(p->X + (size_t)k * fn, fld<T>(p->Z, (size_t)k * p->d.restart, fn), fn, p->st, k, p->geo,
-                  p->stream);
-  launch_row_inv<double>(p->X + (size_t)k * fn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+  fold<T>(p, k);
+  launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
   HPCHK(hipGetLastError());
   HPCHK(hipStreamSynchronize(p->stream));
   return noconv ? HP_WARN_NOCONV : HP_OK;
+}
+
+// x_k of the last step or solve (physical complex128).
+template <typename T>
+int get_solution(hp_plan p, int k, c128* x) {
+  fold<T>(p, k);
+  launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+  HPCHK(hipGetLastError());
+  HPCHK(hipStreamSynchronize(p->stream));
+  return HP_OK;
 }
 
 template <typename T>
@@ -727,6 +809,53 @@ int hp_step(hp_plan p, const void* E_in, const double* n2, void* E_out) {
   const c128* w = reinterpret_cast<const c128*>(E_in);
   c128* out = reinterpret_cast<c128*>(E_out);
   return p->mixed ? run_step<float>(p, w, out) : run_step<double>(p, w, out);
+}
+
+int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* const* x0, int* accepted,
+                  void* E_out) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!E_in || !E_out) return fail(p, HP_EINVAL, "E_in/E_out is NULL");
+  if (n2) {
+    int rc = hp_set_medium(p, n2);
+    if (rc) return rc;
+  }
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
+  const c128* w = reinterpret_cast<const c128*>(E_in);
+  c128* out = reinterpret_cast<c128*>(E_out);
+  std::vector<const c128*> g(p->d.npoles, nullptr);
+  if (x0)
+    for (int k = 0; k < p->d.npoles; ++k) g[k] = reinterpret_cast<const c128*>(x0[k]);
+  const c128* const* gp = x0 ? g.data() : nullptr;
+  int rc = p->mixed ? run_step<float>(p, w, out, gp) : run_step<double>(p, w, out, gp);
+  if (rc >= 0 && accepted)
+    for (int k = 0; k < p->d.npoles; ++k) accepted[k] = p->accepted[k];
+  return rc;
+}
+
+int hp_set_guess(hp_plan p, int mode) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (mode != HP_GUESS_ZERO && mode != HP_GUESS_PREV) return fail(p, HP_EINVAL, "unknown guess mode");
+  p->guess_mode = mode;
+  p->prev_valid = false;
+  return HP_OK;
+}
+
+int hp_get_solution(hp_plan p, int pole, void* x) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!x) return fail(p, HP_EINVAL, "x is NULL");
+  if (pole < 0 || pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  c128* o = reinterpret_cast<c128*>(x);
+  return p->mixed ? get_solution<float>(p, pole, o) : get_solution<double>(p, pole, o);
+}
+
+int hp_apply_medium(hp_plan p, const void* x, void* y) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!x || !y || x == y) return fail(p, HP_EINVAL, "x, y must be distinct device buffers");
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
+  launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, mk(0.0, 0.0),
+                  p->sc, p->geo, nullptr, p->stream, 1);
+  HPCHK(hipGetLastError());
+  return HP_OK;
 }
 
 int hp_solve(hp_plan p, int pole, const void* rhs, void* x) {

@@ -105,12 +105,12 @@ __device__ __forceinline__ double edge_loss(int i, int j, int nx, int ny, int W,
 
 // ------------------------------------------------------------------ row forward (physical -> R-domain)
 
-template <typename T, int N>
+template <typename T, int N, int TW>
 __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
                                                            double* __restrict__ part, const cx<T>* __restrict__ tw,
                                                            int ny, size_t fsz, int nblk) {
   using RC = RowCfg<N>;
-  constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT, TW = Tile<T>::W;
+  constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT;
   __shared__ cx<T> lds[RPW * plen(N)];
   __shared__ cx<T> scr[RPW * RC::SCR];
   __shared__ double red[(WG + 63) / 64];
@@ -858,7 +858,7 @@ constexpr int OP_WG = 256;
 __global__ __launch_bounds__(OP_WG) void k_apply_op(const c128* __restrict__ x, const c128* __restrict__ rhs,
                                                     c128* __restrict__ y, const double* __restrict__ coef, c128 b,
                                                     StencilCoef sc, int nx, int ny, int ncomp, size_t fsz,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, int medium_only) {
   __shared__ double red[OP_WG / 64];
   double nrm = 0.0;
   const size_t idx = (size_t)blockIdx.x * OP_WG + threadIdx.x;
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(OP_WG) void k_apply_op(const c128* __restrict__ x, 
     }
     const double V = coef[idx];
     for (int c = 0; c < ncomp; ++c) {
-      c128 v = lap[c] + V * xc[c] - b * xc[c];
+      c128 v = medium_only ? V * xc[c] : lap[c] + V * xc[c] - b * xc[c];
       if (ncomp == 2) {
         const double px = coef[fsz + idx], py = coef[2 * fsz + idx], pxx = coef[3 * fsz + idx],
                      pyy = coef[4 * fsz + idx], pxy = coef[5 * fsz + idx];
@@ -962,6 +962,15 @@ __global__ __launch_bounds__(256) void k_coef_c(const double* __restrict__ psi, 
   coef[5 * fsz + idx] = pxy;
 }
 
+// After X_k has absorbed the cycle's Z terms: X_k is the whole solution.
+__global__ void k_mark_folded(PoleState* __restrict__ st, int first, int count) {
+  const int k = first + (int)threadIdx.x;
+  if ((int)threadIdx.x < count) {
+    st[k].has_x = 1;
+    st[k].m = 0;
+  }
+}
+
 __global__ void k_fill_zero(c128* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = mk(0.0, 0.0);
@@ -994,12 +1003,19 @@ int row_blocks(int nx) {
 }
 
 template <typename T>
-void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s) {
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s,
+                    int tile_w) {
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny - 1 + rpw - 1) / rpw;
   dim3 grid(nblk, g.ncomp);
-#define L_(NN) \
-  hipLaunchKernelGGL((k_row_fwd<T, NN>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz, nblk)
+  if (tile_w <= 0) tile_w = tile_width<T>();
+#define L_(NN)                                                                                                    \
+  if (tile_w == 8)                                                                                                \
+    hipLaunchKernelGGL((k_row_fwd<T, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,   \
+                       nblk);                                                                                     \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_row_fwd<T, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,  \
+                       nblk);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
@@ -1127,9 +1143,9 @@ void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, i
 int op_blocks(const Geo& g) { return (int)((g.fsz + OP_WG - 1) / OP_WG); }
 
 void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
-                     const Geo& g, double* part, hipStream_t s) {
+                     const Geo& g, double* part, hipStream_t s, int medium_only) {
   hipLaunchKernelGGL(k_apply_op, dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny, g.ncomp,
-                     g.fsz, part);
+                     g.fsz, part, medium_only);
 }
 
 void launch_coef(const double* n2, double* coef, double* scratch, double n0, double s_scale, int W,
@@ -1144,6 +1160,10 @@ void launch_coef(const double* n2, double* coef, double* scratch, double n0, dou
   }
 }
 
+void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark_folded, dim3(1), dim3(HP_MAXPOLES), 0, s, st, first, count);
+}
+
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, p, n);
 }
@@ -1153,7 +1173,7 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   template int row_blocks<T>(int);                                                                                   \
   template int row_apply_blocks<T>(const Geo&);                                                                      \
   template int row_apply_parts<T>(const Geo&);                                                                       \
-  template void launch_row_fwd<T>(const c128*, cx<T>*, double*, const cx<T>*, const Geo&, hipStream_t);              \
+  template void launch_row_fwd<T>(const c128*, cx<T>*, double*, const cx<T>*, const Geo&, hipStream_t, int);         \
   template void launch_row_inv<T>(const cx<T>*, c128*, const cx<T>*, const Geo&, int, hipStream_t);                  \
   template void launch_col<T>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,         \
                               const int*, int, bool, const double*, const double*, const cx<T>*, const Geo&,         \

@@ -17,9 +17,11 @@ struct Geo {
 };
 
 // Row DST-I of the unknowns of a complex128 field (physical, row-major): out
-// (R-domain, T, column-tiled) and per-block partial sums of |in|^2.
+// (R-domain, T, column-tiled with tile_w elements per tile row; 0 = the width
+// of T's own layout) and per-block partial sums of |in|^2.
 template <typename T>
-void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s);
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s,
+                    int tile_w = 0);
 template <typename T>
 int row_blocks(int nx);
 
@@ -86,14 +88,19 @@ void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, i
                   hipStream_t s);
 
 // y = rhs - (Zbar - b I) x  (rhs may be NULL: y = (Zbar - b I) x), explicit
-// 13-point stencils, complex128; partial |y|^2 per block.
+// 13-point stencils, complex128; partial |y|^2 per block.  medium_only: the
+// medium part P of Zbar alone (V x, plus the psi terms of the vector operator).
 void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
-                     const Geo& g, double* part, hipStream_t s);
+                     const Geo& g, double* part, hipStream_t s, int medium_only = 0);
 int op_blocks(const Geo& g);
 
 // Coefficient planes from n^2: V (plane 0) and, for the vector operator,
 // s psi_x, s psi_y, s psi_xx, s psi_yy, s psi_xy (planes 1..5).
 void launch_coef(const double* n2, double* coef, double* scratch, double n0, double s_scale, int W,
                  const StencilCoef& sc, const Geo& g, hipStream_t s);
+
+// Poles first..first+count-1 (count <= HP_MAXPOLES): has_x = 1, m = 0 (their
+// X accumulators now hold the whole solution).
+void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s);
 
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);

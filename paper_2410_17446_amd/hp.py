@@ -18,9 +18,11 @@ _lib = None
 
 HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
 HP_FP64, HP_MIXED = 0, 1
+HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_get_stats", "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
+           "hp_step_guess", "hp_set_guess", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_profile", "hp_profile_read", "hp_last_error", "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
 KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
@@ -58,6 +60,10 @@ def lib():
         L.hp_step.argtypes = [vp, vp, vp, vp]
         L.hp_propagate.argtypes = [vp, vp, vp, C.c_long, C.c_int, vp]
         L.hp_solve.argtypes = [vp, C.c_int, vp, vp]
+        L.hp_step_guess.argtypes = [vp, vp, vp, C.POINTER(vp), ip, vp]
+        L.hp_set_guess.argtypes = [vp, C.c_int]
+        L.hp_get_solution.argtypes = [vp, C.c_int, vp]
+        L.hp_apply_medium.argtypes = [vp, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
         L.hp_set_fixed_iters.argtypes = [vp, ip]
         L.hp_apply_operator.argtypes = [vp, C.c_int, vp, vp]
@@ -149,6 +155,36 @@ class Plan:
             x = torch.empty_like(rhs)
         self._check(self.L.hp_solve(self.handle, pole, _ptr(rhs), _ptr(x)), "hp_solve")
         return x
+
+    def step_guess(self, E_in, x0, n2=None, E_out=None):
+        """One step with per-pole initial guesses x0 (list of tensors or None); returns
+        (E_out, accepted flags)."""
+        import torch
+        if E_out is None:
+            E_out = torch.empty_like(E_in)
+        vp = C.c_void_p
+        arr = None
+        if x0 is not None:
+            if len(x0) != self.npoles:
+                raise HPError("x0 needs one entry per pole")
+            arr = (vp * self.npoles)(*[vp(_ptr(g)) if g is not None else vp() for g in x0])
+        acc = (C.c_int * self.npoles)()
+        rc = self.L.hp_step_guess(self.handle, _ptr(E_in), _ptr(n2), arr, acc, _ptr(E_out))
+        self._check(rc, "hp_step_guess")
+        return E_out, list(acc)
+
+    def set_guess(self, mode):
+        return self._check(self.L.hp_set_guess(self.handle, int(mode)), "hp_set_guess")
+
+    def solution(self, pole, x=None):
+        import torch
+        if x is None:
+            x = torch.empty(self.shape, dtype=torch.complex128, device="cuda")
+        self._check(self.L.hp_get_solution(self.handle, pole, _ptr(x)), "hp_get_solution")
+        return x
+
+    def apply_medium(self, x, y):
+        return self._check(self.L.hp_apply_medium(self.handle, _ptr(x), _ptr(y)), "hp_apply_medium")
 
     def stats(self):
         it = (C.c_int * self.npoles)()

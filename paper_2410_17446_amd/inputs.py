@@ -109,3 +109,39 @@ def batch_configs(count: int = 64, seed: int = 4) -> list[dict]:
         out.append(dict(N=N, dx=0.25, ncomp=1, W=N // 8, eta_max=0.25, dz=1.0, npoles=npoles, steps=50,
                         tol=1e-8, restart=30, medium=medium, w0=N * 0.25 / 8))
     return out
+
+
+def random_beam(N: int, dx: float, ncomp: int, seed: int) -> np.ndarray:
+    """A Gaussian beam with seeded waist (N dx / 16 .. N dx / 6), centre offset (within
+    N dx / 10 of the middle), tilt (transverse wavenumber up to 0.15 k0 per axis) and
+    curvature phase; for ncomp = 2 a seeded linear polarisation angle."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = N * dx
+    w0 = rng.uniform(L / 16, L / 6)
+    cx, cy = rng.uniform(-L / 10, L / 10, size=2)
+    kx, ky = rng.uniform(-0.15, 0.15, size=2) * K0
+    curv = rng.uniform(-0.5, 0.5) / w0 ** 2
+    x = coords(N, dx)
+    X, Y = np.meshgrid(x - cx, x - cy)
+    r2 = X ** 2 + Y ** 2
+    u = np.exp(-r2 / w0 ** 2 + 1j * (kx * X + ky * Y + curv * r2))
+    u[0, :] = 0.0
+    u[:, 0] = 0.0
+    out = np.zeros((ncomp, N, N), dtype=np.complex128)
+    if ncomp == 1:
+        out[0] = u
+    else:
+        a = rng.uniform(0, np.pi)
+        out[0], out[1] = np.cos(a) * u, np.sin(a) * u
+    return out
+
+
+def random_medium(N: int, dx: float, seed: int) -> np.ndarray:
+    """Training media: half Gaussian random fields (rms log-uniform in [1e-3, 2e-2],
+    correlation length uniform in [1, 3] lambda), half sine products (amplitude uniform
+    in [0.005, 0.03], period uniform in [1, 2] lambda)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if rng.random() < 0.5:
+        rms = float(np.exp(rng.uniform(np.log(1e-3), np.log(2e-2))))
+        return grf_n2(N, dx, rms, float(rng.uniform(1.0, 3.0)), int(rng.integers(1 << 30)))
+    return sine_product_n2(N, dx, float(rng.uniform(0.005, 0.03)), float(rng.uniform(1.0, 2.0)))

@@ -7,19 +7,34 @@ import re
 import numpy as np
 import pytest
 
-from paper_2410_17446_amd import hp
+from paper_2410_17446_amd import hp, unet
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "hp.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hp_[a-z_]+)\s*\(", src)))
+def declared_functions(header=None):
+    names = set()
+    for h in ([header] if header else sorted(os.listdir(os.path.join(ROOT, "include")))):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(hp_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_binding_symbols():
-    assert declared_functions() == sorted(hp.SYMBOLS)
+    assert declared_functions("hp.h") == sorted(hp.SYMBOLS)
+    assert declared_functions("hp_unet.h") == sorted(unet.SYMBOLS)
+    assert declared_functions() == sorted(hp.SYMBOLS + unet.SYMBOLS)
+
+
+@pytest.mark.parametrize("args", [(0, 32, 7, 2), (7, 32, 7, 2), (4, 0, 7, 2), (4, 300, 7, 2), (4, 32, 0, 2),
+                                  (4, 32, 7, 65)])
+def test_unet_create_rejects_bad_sizes_on_the_host(args):
+    L = unet.lib()
+    h = C.c_void_p()
+    assert L.hp_unet_create(*args, 0, None, C.byref(h)) == -1
+    assert h.value is None
+    assert b"levels" in L.hp_unet_last_error(None)
 
 
 def test_library_exports_every_declared_symbol():
