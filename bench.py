@@ -15,6 +15,11 @@ The dominant kernel's roofline figure comes from HIP events recorded around
 its launches inside the timed region (on the plan's stream) and the
 algorithmic bytes the library counts for them.  cpu_baseline times the CPU
 oracle on a bounded sample of the same workload.
+
+Other workloads (--config): batch64 (64 independent propagations of uneven
+sizes run concurrently) and learned (a U-Net trained on the GPU from the
+propagator's own solves supplies GMRES starting points; timed against the plain
+method and the previous-step start on scalar1024).
 """
 from __future__ import annotations
 
@@ -40,6 +45,10 @@ def parse():
     ap.add_argument("--modes", default="mixed,fp64")
     ap.add_argument("--cpu-poles", type=int, default=8, help="poles of one oracle step in the CPU sample")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (batch64 workload)")
+    ap.add_argument("--unet-base", type=int, default=32, help="U-Net base channels (learned workload)")
+    ap.add_argument("--train-n", type=int, default=256, help="training grid (learned workload)")
+    ap.add_argument("--train-draws", type=int, default=48, help="(medium, beam) draws for training")
+    ap.add_argument("--train-seconds", type=float, default=90.0, help="training time budget")
     return ap.parse_args()
 
 
@@ -83,6 +92,129 @@ def run_batch(args):
                        "sizes": sorted({p["nx"] for p in problems})},
             "gmres_iterations": int(sum(it)), "all_finite": finite,
             "busiest_problem_s": max(sec)}
+    print(json.dumps(line))
+    return 0
+
+
+def unet_forward_flops(levels, base, cin, cout, H, W):
+    """Multiply-adds x 2 of one forward pass (3x3 and 1x1 convolutions)."""
+    ch = lambda l: base << l
+    f = 2 * ch(0) * cout * H * W
+    for l in range(levels):
+        pl = (H >> l) * (W >> l)
+        f += 18 * ((cin if l == 0 else ch(l - 1)) * ch(l) + ch(l) * ch(l)) * pl
+        if l + 1 < levels:
+            f += 18 * ((ch(l + 1) + ch(l)) * ch(l) + ch(l) * ch(l)) * pl
+    return f
+
+
+def run_learned(args):
+    """Learned initial guesses on the scalar1024 workload against the plain method and the
+    previous-step start: train a U-Net on FP64 solve pairs the propagator makes at 256^2
+    (random media and beams, the same 16-pole table), then time steps of all three from the
+    same field (the plain method's field after the warmup steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, learn, tables
+    from paper_2410_17446_amd.unet import UNet
+    cfg = dict(inputs.CONFIGS["scalar1024"])
+    poles, residues, r_inf, d2, d1 = tables.plan_tables(inputs.K0 * cfg["dz"], cfg["npoles"])
+    fit = dict(poles=poles, residues=residues, r_inf=r_inf)
+    levels, base = 4, args.unet_base
+    net = UNet(levels, base, 7, 2, seed=0)
+    t0 = time.perf_counter()
+    X, T = learn.generate(net, fit, d2, d1, args.train_n, 1, count=args.train_draws, seed=1, tol=1e-10,
+                          poles_per_field=8)
+    Xv, Tv = learn.generate(net, fit, d2, d1, args.train_n, 1, count=8, seed=2, tol=1e-10, poles_per_field=8)
+    t_gen = time.perf_counter() - t0
+    print(f"# training pairs: {X.shape[0]} at {args.train_n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    learn.train(net, X, T, steps=10, batch=8, lr=1e-3)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / 10
+    nsteps = max(10, int(args.train_seconds / per))
+    net = UNet(levels, base, 7, 2, seed=0)
+    t0 = time.perf_counter()
+    losses = learn.train(net, X, T, steps=nsteps, batch=8, lr=1e-3, lr_final=1e-4, log_every=max(1, nsteps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    mse, mse0 = learn.evaluate(net, Xv, Tv)
+    print(f"# trained {nsteps} Adam steps in {t_train:.1f} s; held-out mse {mse:.3e} vs free-space {mse0:.3e}",
+          file=sys.stderr, flush=True)
+    del X, T
+    N = cfg["N"]
+    mk = lambda: hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=inputs.K0, n0=1.0, dz=cfg["dz"], ncomp=1,
+                         poles=poles, residues=residues, r_inf=r_inf, d2=d2, d1=d1, edge_width=cfg["W"],
+                         edge_eta=cfg["eta_max"], tol=cfg["tol"], restart=cfg["restart"], max_cycles=20)
+    w0 = torch.from_numpy(inputs.beam(cfg)).cuda()
+    n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
+    base_plan = mk()
+    start = base_plan.propagate(w0, args.warmup, n2=n2) if args.warmup else w0.clone()
+    base_plan.close()
+    res = {}
+    for mode in ("plain", "prev", "learned"):
+        plan = mk()
+        plan.set_medium(n2)
+        if mode == "prev":
+            plan.set_guess(hp.HP_GUESS_PREV)
+            plan.step(start)           # the first step has no previous solutions; untimed
+        lg = learn.LearnedGuess(plan, net, poles, 1.0, cfg["W"]) if mode == "learned" else None
+        if lg is not None:
+            lg.step(start, n2)         # allocate activations; untimed
+        a = start.clone()
+        b = torch.empty_like(a)
+        its, acc_total, t_guess = [], 0, 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            if lg is None:
+                plan.step(a, E_out=b)
+            else:
+                tg = time.perf_counter()
+                X0 = lg.guesses(a, n2)
+                torch.cuda.synchronize()
+                t_guess += time.perf_counter() - tg
+                _, acc = plan.step_guess(a, [X0[k] for k in range(plan.npoles)], E_out=b)
+                acc_total += sum(acc)
+            its.append(sum(plan.stats()[0]))
+            a, b = b, a
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[mode] = dict(steps_per_s=args.steps / dt, iters_per_step=float(np.mean(its)), field=a)
+        if lg is not None:
+            res[mode]["guess_ms_per_step"] = 1e3 * t_guess / args.steps
+            res[mode]["accepted_frac"] = acc_total / (args.steps * plan.npoles)
+        plan.close()
+        print(f"# {mode}: {res[mode]['steps_per_s']:.2f} steps/s, {res[mode]['iters_per_step']:.1f} iterations "
+              f"per step", file=sys.stderr, flush=True)
+    ref = res["plain"]["field"].cpu().numpy()
+    for mode in res:
+        f = res[mode].pop("field").cpu().numpy()
+        res[mode]["err_vs_plain"] = float(np.linalg.norm(f - ref) / np.linalg.norm(ref))
+    # U-Net forward throughput at the inference shape (8 poles per launch)
+    x = torch.randn(8, 7, N, N, device="cuda")
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        net.forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / 3
+    tflops = unet_forward_flops(levels, base, 7, 2, N, N) * 8 / fwd / 1e12
+    line = {"metric": "propagation steps/s (1024^2, 16 poles, tol 1e-8) with learned initial guesses",
+            "value": res["learned"]["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 / res["learned"]["steps_per_s"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c128+f32", "data": "synthetic",
+            "config": {"workload": "scalar1024", "grid": N, "poles": cfg["npoles"], "tol": cfg["tol"],
+                       "unet": {"levels": levels, "base": base, "params": net.nparam},
+                       "training": {"grid": args.train_n, "pairs": args.train_draws * 8,
+                                    "adam_steps": nsteps, "batch": 8, "seconds": t_train,
+                                    "datagen_seconds": t_gen, "final_loss": float(np.mean(losses[-20:])),
+                                    "heldout_mse": mse, "heldout_mse_free_space": mse0}},
+            "modes": res,
+            "roofline": {"bound": "alu", "kernel": "unet forward (k_conv3)", "achieved": tflops, "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": tflops / 157.3, "traffic": None}}
     print(json.dumps(line))
     return 0
 
@@ -157,6 +289,8 @@ def main():
         return 2
     if args.config == "batch64":
         return run_batch(args)
+    if args.config == "learned":
+        return run_learned(args)
     import numpy as np
     import torch
 
