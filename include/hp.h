@@ -131,7 +131,10 @@ int hp_solve(hp_plan plan, int pole, const void* rhs, void* x);
  * NULL (no guesses).  Each guess is judged by its FP64 residual
  * r0 = w - A_k x0 (explicit stencils): it is used when ||r0|| < ||w||, else
  * that pole starts from zero (the fallback).  accepted: host [npoles] or
- * NULL; 1 where the guess was used.  One stream synchronisation per guess. */
+ * NULL; 1 where the guess was used.  All guesses are judged together with one
+ * stream synchronisation; the first guess step on a plan allocates one
+ * complex128 field per pole (hipMalloc) for their residuals, freed with the
+ * plan. */
 int hp_step_guess(hp_plan plan, const void* E_in, const double* n2, const void* const* x0, int* accepted,
                   void* E_out);
 
@@ -169,12 +172,15 @@ int hp_set_fixed_iters(hp_plan plan, const int* iters);
 int hp_apply_operator(hp_plan plan, int pole, const void* x, void* y);
 int hp_apply_preconditioner(hp_plan plan, int pole, const void* x, void* y);
 
-/* Kernel timing (diagnostics).  While enabled, each launch of the step's
- * kernels is bracketed by HIP events on the plan's stream and its algorithmic
- * HBM bytes (the bytes the operation must move: fields read and written once)
- * are counted.  hp_profile_read synchronises and returns, per kernel class
- * (HP_K_*), launches, summed event milliseconds and summed algorithmic bytes
- * since the last enable; arrays have HP_K_COUNT entries (NULL to skip). */
+/* Kernel timing (diagnostics).  enable: 0 off, -1 every kernel class, else a
+ * bitmask of classes (1 << HP_K_*).  Each launch of a timed class is
+ * bracketed by HIP events on the plan's stream (an event pair costs a few
+ * microseconds of stream time, so time one class to keep the rest of the step
+ * undisturbed) and its algorithmic HBM bytes (the bytes the operation must
+ * move: fields read and written once) are counted.  hp_profile_read
+ * synchronises and returns, per kernel class (HP_K_*), launches, summed event
+ * milliseconds and summed algorithmic bytes since the last hp_profile call;
+ * arrays have HP_K_COUNT entries (NULL to skip). */
 enum { HP_K_ROW_FWD = 0, HP_K_COL = 1, HP_K_ROW_APPLY = 2, HP_K_UPDATE = 3, HP_K_SMALL = 4,
        HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_COUNT = 7 };
 int hp_profile(hp_plan plan, int enable);

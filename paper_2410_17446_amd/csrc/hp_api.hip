@@ -80,8 +80,11 @@ struct hp_plan_s {
   int guess_mode = HP_GUESS_ZERO;
   bool prev_valid = false;        // X holds every pole's solution of the previous step
   std::vector<int> accepted;      // per pole: the last step started from a guess
+  c128* guess_r = nullptr;        // per pole: residual of its guess (allocated on first use)
+  double* guess_part = nullptr;   // per pole: partial sums of |r0|^2
+  double* guess_part_h = nullptr; // pinned copy (+1 slot: ||w||)
   // kernel timing
-  bool prof = false;
+  int prof = 0;  // bit c set: launches of kernel class c are timed
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_cls;
@@ -121,8 +124,9 @@ struct Prof {
   hp_plan p;
   int cls;
   double bytes;
-  Prof(hp_plan p_, int c, double b) : p(p_), cls(c), bytes(b) {
-    if (!p->prof) return;
+  bool on;
+  Prof(hp_plan p_, int c, double b) : p(p_), cls(c), bytes(b), on(((p_->prof >> c) & 1) != 0) {
+    if (!on) return;
     if (p->ev_used + 2 > p->ev_pool.size()) {
       for (int i = 0; i < 256; ++i) {
         hipEvent_t e;
@@ -133,7 +137,7 @@ struct Prof {
     (void)hipEventRecord(p->ev_pool[p->ev_used], p->stream);
   }
   ~Prof() {
-    if (!p->prof || p->ev_used + 2 > p->ev_pool.size()) return;
+    if (!on || p->ev_used + 2 > p->ev_pool.size()) return;
     (void)hipEventRecord(p->ev_pool[p->ev_used + 1], p->stream);
     p->ev_used += 2;
     p->ev_cls.push_back(cls);
@@ -325,14 +329,15 @@ int true_residual(hp_plan p, int k, const c128* w, double* res) {
   return HP_OK;
 }
 
-// Start a new cycle for pole k from the residual in tmp2.
+// Start a new cycle for pole k from the residual r (physical complex128; tmp2 by default).
 template <typename T>
-int restart_pole(hp_plan p, int k) {
+int restart_pole(hp_plan p, int k, const c128* r = nullptr) {
   const size_t fn = p->fieldn;
   cx<T>* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
   {
     Prof pr(p, HP_K_ROW_FWD, (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
-    launch_row_fwd<T>(p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, p->stream);
+    launch_row_fwd<T>(r ? r : p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo,
+                      p->stream);
   }
   if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)u0) {
     p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
@@ -362,35 +367,68 @@ void fold(hp_plan p, int k) {
   launch_mark_folded(p->st, k, 1, p->stream);
 }
 
-// Judge pole k's guess, held in X_k as S_x x0 (x0 physical, complex128, when
-// given as well): r0 = w - A_k x0 in FP64.  The guess is used when
-// ||r0|| < ||w||; the pole then starts its first cycle from r0 with X_k as the
-// solution so far.  Returns 1 when used, 0 when the pole keeps the zero start.
+// Guess residuals for several poles at once: one buffer and one set of
+// partial sums per pole (allocated on first use, freed with the plan).
+int ensure_guess_buffers(hp_plan p) {
+  if (p->guess_r) return HP_OK;
+  const int K = p->d.npoles;
+  HPCHK(hipMalloc(&p->guess_r, (size_t)K * p->fieldn * sizeof(c128)));
+  HPCHK(hipMalloc(&p->guess_part, (size_t)K * p->nopblk * sizeof(double)));
+  HPCHK(hipHostMalloc(&p->guess_part_h, ((size_t)K * p->nopblk + 1) * sizeof(double)));
+  return HP_OK;
+}
+
+// Judge the guesses of the poles in cand: pole cand[j]'s guess is held in its
+// X accumulator as S_x x0 (x0[j], physical complex128, given as well, or NULL:
+// X then comes from the previous step).  r0 = w - A_k x0 in FP64 for all of
+// them, one synchronisation, then every pole with ||r0|| < ||w|| starts its
+// first cycle from r0 with X_k as the solution so far (done[j]: already within
+// tol, no Arnoldi step); the others keep the zero start.  acc[j] = 1 when used.
 template <typename T>
-int start_from_guess(hp_plan p, int k, const c128* w, const c128* x0, double beta0, bool* done, double* rel) {
-  const c128* xp = x0;
-  if (!xp) {
-    launch_row_inv<double>(p->X + (size_t)k * p->fieldn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
-    xp = p->tmp1;
+int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, const c128* const* x0,
+                       const int* st_first, std::vector<int>& acc, std::vector<char>& done,
+                       std::vector<double>& rel) {
+  int rc = ensure_guess_buffers(p);
+  if (rc) return rc;
+  const size_t fn = p->fieldn;
+  const int nc = (int)cand.size();
+  for (int j = 0; j < nc; ++j) {
+    const int k = cand[j];
+    const c128* xp = x0 ? x0[j] : nullptr;
+    if (!xp) {
+      launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+      xp = p->tmp1;
+    }
+    launch_apply_op(xp, w, p->guess_r + (size_t)j * fn, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc,
+                    p->geo, p->guess_part + (size_t)j * p->nopblk, p->stream);
   }
-  launch_apply_op(xp, w, p->tmp2, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc, p->geo, p->part_misc,
-                  p->stream);
-  HPCHK(hipMemcpyAsync(p->misc_h, p->part_misc, p->nopblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipMemcpyAsync(p->guess_part_h, p->guess_part, (size_t)nc * p->nopblk * sizeof(double),
+                       hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipMemcpyAsync(p->guess_part_h + (size_t)nc * p->nopblk, &p->st[*st_first].beta0, sizeof(double),
+                       hipMemcpyDeviceToHost, p->stream));
   HPCHK(hipStreamSynchronize(p->stream));
-  double s = 0.0;
-  for (int b = 0; b < p->nopblk; ++b) s += p->misc_h[b];
-  const double r0 = sqrt(s);
-  *done = false;
-  *rel = beta0 > 0 ? r0 / beta0 : 0.0;
-  if (!(r0 < beta0)) return 0;  // also rejects NaN
+  const double beta0 = p->guess_part_h[(size_t)nc * p->nopblk];
   static const int one = 1;
-  HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  if (r0 <= p->d.tol * beta0) {  // already within tolerance: no Arnoldi step
-    *done = true;
-    return 1;
+  acc.assign(nc, 0);
+  done.assign(nc, 0);
+  rel.assign(nc, 0.0);
+  for (int j = 0; j < nc; ++j) {
+    const int k = cand[j];
+    double s2 = 0.0;
+    for (int b = 0; b < p->nopblk; ++b) s2 += p->guess_part_h[(size_t)j * p->nopblk + b];
+    const double r0 = sqrt(s2);
+    rel[j] = beta0 > 0 ? r0 / beta0 : 0.0;
+    if (!(r0 < beta0)) continue;  // also rejects NaN
+    acc[j] = 1;
+    HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
+    if (r0 <= p->d.tol * beta0) {
+      done[j] = 1;
+      continue;
+    }
+    rc = restart_pole<T>(p, k, p->guess_r + (size_t)j * fn);
+    if (rc) return rc;
   }
-  int rc = restart_pole<T>(p, k);
-  return rc ? rc : 1;
+  return HP_OK;
 }
 
 template <typename T>
@@ -447,24 +485,31 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   };
   // initial guesses (explicit, or the previous step's solutions held in X)
   p->accepted.assign(K, 0);
-  for (int k : subset) {
-    const c128* g = x0 ? x0[k] : nullptr;
-    if (!g && !use_prev) continue;
-    if (beta0 < 0) {
-      HPCHK(hipMemcpyAsync(p->misc_h, &p->st[subset[0]].beta0, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-      HPCHK(hipStreamSynchronize(p->stream));
-      beta0 = p->misc_h[0];
+  {
+    std::vector<int> cand;
+    std::vector<const c128*> gx;
+    for (int k : subset) {
+      const c128* g = x0 ? x0[k] : nullptr;
+      if (!g && !use_prev) continue;
+      if (g)
+        launch_row_fwd<double>(g, p->X + (size_t)k * fn, p->part_misc, p->tw64_x, p->geo, p->stream,
+                               tile_width<T>());
+      cand.push_back(k);
+      gx.push_back(g);
     }
-    if (g)
-      launch_row_fwd<double>(g, p->X + (size_t)k * fn, p->part_misc, p->tw64_x, p->geo, p->stream, tile_width<T>());
-    bool done = false;
-    double rel = 0.0;
-    int rc = start_from_guess<T>(p, k, w, g, beta0, &done, &rel);
-    if (rc < 0) return rc;
-    p->accepted[k] = rc;
-    if (done) {
-      live[k] = 0;
-      p->relres[k] = rel;
+    if (!cand.empty()) {
+      std::vector<int> acc;
+      std::vector<char> done;
+      std::vector<double> rel;
+      int rc = start_from_guesses<T>(p, cand, w, gx.data(), &subset[0], acc, done, rel);
+      if (rc) return rc;
+      for (size_t j = 0; j < cand.size(); ++j) {
+        p->accepted[cand[j]] = acc[j];
+        if (done[j]) {
+          live[cand[j]] = 0;
+          p->relres[cand[j]] = rel[j];
+        }
+      }
     }
   }
   std::vector<Flight> q;
@@ -941,7 +986,7 @@ int hp_apply_preconditioner(hp_plan p, int pole, const void* x, void* y) {
 int hp_profile(hp_plan p, int enable) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
   HPCHK(hipStreamSynchronize(p->stream));
-  p->prof = enable != 0;
+  p->prof = enable < 0 ? (1 << HP_K_COUNT) - 1 : enable & ((1 << HP_K_COUNT) - 1);
   p->ev_used = 0;
   p->ev_cls.clear();
   p->ev_bytes.clear();
@@ -986,6 +1031,9 @@ void hp_plan_destroy(hp_plan p) {
   if (p->est_h) (void)hipHostFree(p->est_h);
   if (p->active_h) (void)hipHostFree(p->active_h);
   if (p->misc_h) (void)hipHostFree(p->misc_h);
+  if (p->guess_r) (void)hipFree(p->guess_r);
+  if (p->guess_part) (void)hipFree(p->guess_part);
+  if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->iter_ev)
     if (e) (void)hipEventDestroy(e);

@@ -84,13 +84,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin; map consecutive tiles onto
-// one XCD so neighbouring column tiles share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nb) {
-  if (nb % 8) return bid;
-  return (bid % 8) * (nb / 8) + bid / 8;
-}
-
 template <typename T>
 __device__ __forceinline__ cx<T> czero() {
   return mk<T>((T)0, (T)0);
@@ -182,10 +175,22 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restri
 
 // ------------------------------------------------------------------ column pass (preconditioner)
 //
-// One workgroup per tile of TW columns (a tile row is one 128-byte line).  The
-// columns go through LDS GC at a time; the GC-column slices of a line that one
-// group reads are followed by the rest of that line in the next groups of the
-// same workgroup, so the line comes from HBM once and from L2 after.
+// One workgroup per group of GC columns of a tile (a tile row is one 128-byte
+// line, TW columns).  Workgroups are dealt to the 8 XCDs round-robin; the
+// TW/GC sibling groups of a tile get block indices with the same value mod 8,
+// consecutive in dispatch order: they run at the
+// same time on one XCD, so each line comes from HBM once and from that XCD's
+// L2 for the siblings (one workgroup walking the groups in turn lost the
+// lines from L2 between groups and read the tile about three times).
+__device__ __forceinline__ void col_block(int bid, int ntiles, int S, int& tile, int& sub) {
+  if (ntiles % 8 == 0) {
+    tile = (bid / (8 * S)) * 8 + bid % 8;
+    sub = (bid / 8) % S;
+  } else {
+    tile = bid / S;
+    sub = bid % S;
+  }
+}
 
 template <typename T, int N, int NC>
 __global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
@@ -194,13 +199,15 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
     const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw, size_t fsz,
     StencilCoef sc) {
   using CC = ColCfg<T, N>;
-  constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG;
+  constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
   constexpr int PL = plen(N);
   constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
   __shared__ cx<T> lds[GC * PL];
   __shared__ cx<T> scr[GC * CC::SCR];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int tile, sub;
+  col_block(blockIdx.x, gridDim.x / S, S, tile, sub);
   const int col0 = tile * TW;
+  const int c0 = sub * GC;
   const int comp = blockIdx.y % NC;
   const int tid = threadIdx.x;
   const int g = tid / NT, t = tid % NT;
@@ -214,9 +221,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
   const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
   cx<T>* z = zbase + k * zsp + m * zsi + tbase;
   cx<T>* dz = (NC == 2) ? dzbase + k * dzsp + tbase : nullptr;
-#pragma unroll 1
-  for (int c0 = 0; c0 < TW; c0 += GC) {
-    __syncthreads();
+  {
     for (int e = tid; e < NE; e += WG) {
       const int r = 1 + e / GC, c = e % GC;
       lds[c * PL + pidx(r)] = u[(size_t)r * TW + c0 + c];
@@ -1041,7 +1046,7 @@ void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, 
   (void)shared;
 #define L_(NN)                                                                                                 \
   {                                                                                                            \
-    dim3 grid(g.nx / ColCfg<T, NN>::TW, g.ncomp * nactive);                                                    \
+    dim3 grid(g.nx / ColCfg<T, NN>::GC, g.ncomp * nactive);                                                    \
     if (g.ncomp == 1)                                                                                          \
       hipLaunchKernelGGL((k_col<T, NN, 1>), grid, dim3(ColCfg<T, NN>::WG), 0, s, uptr, zbase, zsp, zsi, dzbase, \
                          dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                         \

@@ -203,8 +203,12 @@ class Plan:
         return self._check(self.L.hp_apply_preconditioner(self.handle, pole, _ptr(x), _ptr(y)),
                            "hp_apply_preconditioner")
 
-    def profile(self, enable: bool):
-        return self._check(self.L.hp_profile(self.handle, int(enable)), "hp_profile")
+    def profile(self, enable: bool, classes=None):
+        """Time the launches of the given kernel classes (names of KERNEL_CLASSES; all when None)."""
+        mask = 0
+        if enable:
+            mask = -1 if classes is None else sum(1 << KERNEL_CLASSES.index(c) for c in classes)
+        return self._check(self.L.hp_profile(self.handle, mask), "hp_profile")
 
     def profile_read(self):
         """{kernel class: (launches, total ms, total algorithmic bytes)}."""
