@@ -95,8 +95,20 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
     if constexpr (NS > 1) {
       const int k = j % NS;
       constexpr int STEP = L / (NS * R);
+      if constexpr (sizeof(T) == 8 && R > 2) {
+        // complex128: powers of one table twiddle (fewer live registers; the
+        // products add a few ulps, far below the FP64 step tolerance)
+        const cx<T> w1 = tw[k * STEP];
+        cx<T> wr = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[q][r] = v[q][r] * tw[r * k * STEP];
+        for (int r = 1; r < R; ++r) {
+          v[q][r] = v[q][r] * wr;
+          if (r + 1 < R) wr = wr * w1;
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = v[q][r] * tw[r * k * STEP];
+      }
     }
     dft<T, R>(v[q]);
   }

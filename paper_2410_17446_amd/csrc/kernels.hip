@@ -36,6 +36,25 @@ __device__ __forceinline__ size_t tix(int i, int q, int ny) {
   return ((size_t)(q / TW) * ny + i) * TW + (q % TW);
 }
 
+// Tiled offsets of the points q = t + s * NT (s = 0, 1, ...) of row i: when NT
+// is a multiple of TW they step by a uniform stride (kept in a scalar
+// register instead of one address per point).
+template <int TW, int NT>
+struct RowWalk {
+  size_t o0, step;
+  int i, t, ny;
+  __device__ __forceinline__ RowWalk(size_t base, int i_, int t_, int ny_) : i(i_), t(t_), ny(ny_) {
+    o0 = base + tix<TW>(i_, t_, ny_);
+    step = (size_t)(NT / TW) * ny_ * TW;
+  }
+  __device__ __forceinline__ size_t at(int s) const {
+    if constexpr (NT % TW == 0)
+      return o0 + (size_t)s * step;
+    else
+      return o0 - tix<TW>(i, t, ny) + tix<TW>(i, t + s * NT, ny);
+  }
+};
+
 template <int N>
 struct RowCfg {
   static constexpr int NT = N / 8;                           // threads per transform
@@ -192,8 +211,16 @@ __device__ __forceinline__ void col_block(int bid, int ntiles, int S, int& tile,
   }
 }
 
+// Waves per SIMD for the column pass (as for the row pass: the most that
+// compile without spilling).
+template <typename T, int N>
+struct ColWaves {
+  static constexpr bool POW2 = (N & (N - 1)) == 0;
+  static constexpr int V = (N <= 1024 && POW2) ? 4 : 2;
+};
+
 template <typename T, int N, int NC>
-__global__ __launch_bounds__((ColCfg<T, N>::WG)) void k_col(
+__global__ __launch_bounds__((ColCfg<T, N>::WG), (ColWaves<T, N>::V)) void k_col(
     const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
     cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const int* __restrict__ active,
     const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw, size_t fsz,
@@ -270,8 +297,19 @@ struct ApplyCfg {
   static constexpr int SCR = ScanScratch<NT>::SIZE;
 };
 
+// Waves per SIMD the register allocation must allow, the most that compile
+// without spilling: scalar complex64 four (128 VGPRs; three for 3 * 2^k and
+// 2048), scalar complex128 three (two at 2048); vector fields as many as their
+// registers allow (complex64 one, complex128 two).
 template <typename T, int N, int NC>
-__global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
+struct ApplyWaves {
+  static constexpr bool POW2 = (N & (N - 1)) == 0;
+  static constexpr int V = NC == 2 ? (sizeof(T) == 4 ? 1 : 2)
+                                   : (sizeof(T) == 4 ? (N <= 1024 && POW2 ? 4 : 3) : (N >= 2048 ? 2 : 3));
+};
+
+template <typename T, int N, int NC>
+__global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
     cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const double* __restrict__ coef,
     const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
@@ -294,15 +332,13 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
   const T scale = (T)sqrt(2.0 / N);
   const size_t cbase = comp * fsz;
   const size_t ci0 = (size_t)row * N;  // physical row offset
-  size_t toff[PT];                     // tiled offsets of the thread's points
-#pragma unroll
-  for (int s = 0; s < PT; ++s) toff[s] = cbase + tix<TW>(valid ? row : 0, t + s * NT, ny);
+  const RowWalk<TW, NT> toff(cbase, valid ? row : 0, t, ny);  // tiled offsets of the thread's points
 
   const cx<T>* z = zbase + k * zsp + m * zsi;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    buf[pidx(j)] = (valid && j > 0) ? z[toff[s]] : czero<T>();
+    buf[pidx(j)] = (valid && j > 0) ? z[toff.at(s)] : czero<T>();
   }
   __syncthreads();
   dst1<T, N>(buf, tw, sg, t);
@@ -336,7 +372,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      buf[pidx(j)] = (valid && j > 0) ? dz[toff[s]] : czero<T>();
+      buf[pidx(j)] = (valid && j > 0) ? dz[toff.at(s)] : czero<T>();
     }
     __syncthreads();
     dst1<T, N>(buf, tw, sg, t);
@@ -388,7 +424,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
     pv[s] = (j == 0 || !valid) ? czero<T>() : dst_val(buf, j, scale);
-    if (valid) p[toff[s]] = pv[s];
+    if (valid) p[toff.at(s)] = pv[s];
   }
   // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
   // the reorthogonalisation of the provisional u_m, from the same reads of the
@@ -397,7 +433,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
   {
     const cx<T>* u = uptr[k * (HP_MAXM + 1) + m];
 #pragma unroll
-    for (int s = 0; s < PT; ++s) um[s] = valid ? u[toff[s]] : czero<T>();
+    for (int s = 0; s < PT; ++s) um[s] = valid ? u[toff.at(s)] : czero<T>();
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int slot = blockIdx.x * AC::WAVES + wave;
@@ -407,7 +443,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG)) void k_row_apply(
     if (valid) {
 #pragma unroll
       for (int s = 0; s < PT; ++s) {
-        const cx<double> a = cvt<double>(i == m ? um[s] : u[toff[s]]);
+        const cx<double> a = cvt<double>(i == m ? um[s] : u[toff.at(s)]);
         const cx<double> bp = cvt<double>(pv[s]);
         const cx<double> bq = cvt<double>(um[s]);
         pr += a.re * bp.re + a.im * bp.im;
@@ -781,9 +817,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
   const bool valid = row > 0 && row < ny;
   c128* buf = lds + g * plen(N);
   const size_t roff = comp * fsz + (size_t)row * N;
-  size_t toff[PT];
-#pragma unroll
-  for (int s = 0; s < PT; ++s) toff[s] = comp * fsz + tix<TW>(valid ? row : 0, t + s * NT, ny);
+  const RowWalk<TW, NT> toff(comp * fsz, valid ? row : 0, t, ny);
   c128 acc[PT];
 #pragma unroll
   for (int s = 0; s < PT; ++s) acc[s] = mk(0.0, 0.0);
@@ -793,7 +827,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
       if (st[k].has_x) {
         const c128* xk = xacc + k * xsp;
 #pragma unroll
-        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + ak * xk[toff[s]];
+        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + ak * xk[toff.at(s)];
       }
       const int mk_ = st[k].m;
       const cx<T>* zk = zbase + k * zsp;
@@ -801,7 +835,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
         const c128 cf = ak * st[k].y[i];
         const cx<T>* zi = zk + i * zsi;
 #pragma unroll
-        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + cf * cvt<double>(zi[toff[s]]);
+        for (int s = 0; s < PT; ++s) acc[s] = acc[s] + cf * cvt<double>(zi[toff.at(s)]);
       }
     }
   }
