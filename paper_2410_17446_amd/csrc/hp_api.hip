@@ -464,6 +464,8 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   const int ns = (int)subset.size();
   for (int a = 0; a < ns; ++a) act0[a] = subset[a];
   HPCHK(hipMemcpyAsync(p->active_d, act0, ns * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  // device copies of the iteration lists (slot 0 shares its storage with the initial list)
+  std::vector<int> uploaded[2] = {subset, {}};
   launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
                     p->mixed ? kInnerRtolMixed : 0.0, p->stream);
   std::vector<char> live(K, 0);
@@ -522,12 +524,15 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     int maxm = 0;
     double sum_m = 0.0;
     for (int a = 0; a < na; ++a) {
-      ah[a] = poles[a];
       const int mk_ = (int)std::min<long>(next_iter - since[poles[a]], M - 1);
       maxm = std::max(maxm, mk_);
       sum_m += mk_;
     }
-    HPCHK(hipMemcpyAsync(ad, ah, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    if (uploaded[slot] != poles) {  // the slot's device list changes only when poles finish
+      for (int a = 0; a < na; ++a) ah[a] = poles[a];
+      HPCHK(hipMemcpyAsync(ad, ah, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
+      uploaded[slot] = poles;
+    }
     {
       const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
       Prof pr(p, HP_K_COL, U1 * es * (na + outs));

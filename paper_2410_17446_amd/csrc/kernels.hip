@@ -467,6 +467,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
 // ------------------------------------------------------------------ Gram-Schmidt update
 
 constexpr int UPD_WG = 256;
+constexpr int UPD_E = 4;
 
 // u_{m+1} = cu_{m+1} p + sum_{i<=m} cu_i u_i, and (delayed reorthogonalisation)
 // u_m <- sum_{i<=m} cv_i u_i in place; partial |u_{m+1}|^2.
@@ -493,18 +494,41 @@ __global__ __launch_bounds__(UPD_WG) void k_update(const cx<T>* __restrict__ pba
   cx<T>* out = up[m + 1];
   cx<T>* um = up[m];
   double nrm = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * UPD_WG + threadIdx.x; idx < total; idx += (size_t)gridDim.x * UPD_WG) {
-    cx<double> v = cf[m + 1] * cvt<double>(p[idx]);
-    cx<double> c = mk(0.0, 0.0);
-    for (int i = 0; i <= m; ++i) {
-      const cx<double> ui = cvt<double>(up[i][idx]);
-      v = v + cf[i] * ui;
-      c = c + cv[i] * ui;
+  // UPD_E elements per thread, UPD_WG apart, so that each basis vector's
+  // loads are in flight together
+  const size_t chunk = (size_t)UPD_WG * UPD_E;
+  for (size_t base = (size_t)blockIdx.x * chunk + threadIdx.x; base < total; base += (size_t)gridDim.x * chunk) {
+    cx<double> v[UPD_E], c[UPD_E];
+#pragma unroll
+    for (int e = 0; e < UPD_E; ++e) {
+      const size_t idx = base + (size_t)e * UPD_WG;
+      v[e] = (idx < total) ? cf[m + 1] * cvt<double>(p[idx]) : mk(0.0, 0.0);
+      c[e] = mk(0.0, 0.0);
     }
-    const cx<T> r = cvt<T>(v);
-    out[idx] = r;
-    if (corr) um[idx] = cvt<T>(c);
-    nrm += abs2(cvt<double>(r));
+    for (int i = 0; i <= m; ++i) {
+      const cx<T>* ui = up[i];
+      cx<double> a[UPD_E];
+#pragma unroll
+      for (int e = 0; e < UPD_E; ++e) {
+        const size_t idx = base + (size_t)e * UPD_WG;
+        a[e] = (idx < total) ? cvt<double>(ui[idx]) : mk(0.0, 0.0);
+      }
+      const c128 fi = cf[i], gi = cv[i];
+#pragma unroll
+      for (int e = 0; e < UPD_E; ++e) {
+        v[e] = v[e] + fi * a[e];
+        c[e] = c[e] + gi * a[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < UPD_E; ++e) {
+      const size_t idx = base + (size_t)e * UPD_WG;
+      if (idx >= total) continue;
+      const cx<T> r = cvt<T>(v[e]);
+      out[idx] = r;
+      if (corr) um[idx] = cvt<T>(c[e]);
+      nrm += abs2(cvt<double>(r));
+    }
   }
   double s = block_sum<UPD_WG>(nrm, red);
   if (threadIdx.x == 0) part[(size_t)k * nblk + blockIdx.x] = s;
@@ -533,9 +557,26 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double2* __restrict_
   if (i > m) return;
   const double2* src = part + (((size_t)k * (HP_MAXM + 1) + i) * 2 + slot) * nparts;
   double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 256) {
-    re += src[b].x;
-    im += src[b].y;
+  {
+    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    int b = threadIdx.x;
+    for (; b + 3 * 256 < nparts; b += 4 * 256) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 v = src[b + u * 256];
+        ar[u] += v.x;
+        ai[u] += v.y;
+      }
+    }
+    for (; b < nparts; b += 256) {
+      ar[0] += src[b].x;
+      ai[0] += src[b].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      re += ar[u];
+      im += ai[u];
+    }
   }
   re = block_sum<256>(re, red);
   im = block_sum<256>(im, red);
@@ -663,12 +704,29 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
   const int k = active[blockIdx.x];
   if (st[k].flag) return;
   const int tid = threadIdx.x;
-  double s = 0.0;
-  for (int b = tid; b < nblk; b += 64) s += part[(size_t)k * nblk + b];
-  s = wave_sum(s);
   PoleState& S = st[k];
   constexpr int LD = HP_MAXM + 1;
   const int m = S.m;
+  // scalars thread 0 needs, loaded up front so their latency overlaps the reduction
+  const c128 gpre_m1 = (tid == 0 && m >= 1) ? S.gpre[m - 1] : mk(0.0, 0.0);
+  const c128 g_m = (tid == 0) ? S.g[m] : mk(0.0, 0.0);
+  const int fixed = S.fixed, total = S.total;
+  const double tol = S.tol;
+  double s = 0.0;
+  {
+    // eight independent accumulators keep eight loads in flight per thread
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double* src = part + (size_t)k * nblk;
+    int b = tid;
+    for (; b + 7 * 64 < nblk; b += 8 * 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += src[b + u * 64];
+    }
+    for (; b < nblk; b += 64) acc[0] += src[b];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += acc[u];
+  }
+  s = wave_sum(s);
   for (int i = tid; i <= m; i += 64) {
     c2[i] = S.Hraw[i + m * LD];
     if (m >= 1) c1[i] = S.Hraw[i + (m - 1) * LD];
@@ -679,6 +737,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
   }
   __syncthreads();
   if (tid == 0) {
+    c128 gm_rot = mk(0.0, 0.0);
     const double h = sqrt(s);
     S.Hraw[m + 1 + m * LD] = mk(h, 0.0);
     c2[m + 1] = mk(h, 0.0);
@@ -696,8 +755,9 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
       sn[m - 1] = snn;
       c1[m - 1] = r;
       c1[m] = mk(0.0, 0.0);
-      S.g[m - 1] = c * S.gpre[m - 1];
-      S.g[m] = -1.0 * cmulc(snn, S.gpre[m - 1]);
+      S.g[m - 1] = c * gpre_m1;
+      gm_rot = -1.0 * cmulc(snn, gpre_m1);
+      S.g[m] = gm_rot;
     }
     for (int i = 0; i < m; ++i) {
       const c128 a = c2[i], b = c2[i + 1];
@@ -711,19 +771,22 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
     sn[m] = snn;
     c2[m] = r;
     c2[m + 1] = mk(0.0, 0.0);
-    S.gpre[m] = S.g[m];
-    S.g[m + 1] = -1.0 * cmulc(snn, S.g[m]);
-    S.g[m] = c * S.g[m];
+    const c128 gm = (m >= 1) ? gm_rot : g_m;  // g[m] as it stands after column m-1
+    const c128 gnext = -1.0 * cmulc(snn, gm);
+    const double est = sqrt(abs2(gnext));
+    S.gpre[m] = gm;
+    S.g[m + 1] = gnext;
+    S.g[m] = c * gm;
     S.sigma[m + 1] = (h > 0.0) ? 1.0 / h : 0.0;
-    S.est = sqrt(abs2(S.g[m + 1]));
+    S.est = est;
     S.m = m + 1;
-    S.total += 1;
+    S.total = total + 1;
     int flag = 0;
-    if (S.fixed > 0) {
-      if (S.m >= S.fixed) flag = 1;
-    } else if (S.est <= S.tol || h == 0.0) {
+    if (fixed > 0) {
+      if (m + 1 >= fixed) flag = 1;
+    } else if (est <= tol || h == 0.0) {
       flag = 1;
-    } else if (S.m >= restart) {
+    } else if (m + 1 >= restart) {
       flag = 2;
     }
     flag_s = flag;
@@ -757,7 +820,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
     // The estimate measures the split operator I + P M~^-1; it differs from
     // A M~^-1 by about eps kappa(M_k) ||y|| (||y|| = ||M x||).  When that is not
     // well below tol, the true residual decides.
-    if (tid == 0 && flag == 1 && S.fixed == 0) {
+    if (tid == 0 && flag == 1 && fixed == 0) {
       double yn = 0.0;
       for (int i = 0; i < n; ++i) yn += abs2(rhs[i]);
       if (S.incons * sqrt(yn) > 0.1 * S.tol) flag = 3;
@@ -1136,7 +1199,7 @@ void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int*
 }
 
 int update_blocks(size_t total) {
-  size_t b = (total + UPD_WG * 4 - 1) / (UPD_WG * 4);
+  size_t b = (total + UPD_WG * UPD_E - 1) / (UPD_WG * UPD_E);
   if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   return (int)b;
