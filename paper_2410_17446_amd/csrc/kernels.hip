@@ -679,20 +679,27 @@ __device__ __forceinline__ void givens(c128 a, double b, double& c, c128& sn, c1
   r = c * a + b * sn;
 }
 
-// Back substitution R x = rhs (R upper triangular, column-major with leading
-// dimension HP_MAXM + 1), column by column with the 64 threads of the block.
-__device__ void upper_solve(const c128* __restrict__ R, c128* rhs, c128* x, int n) {
-  constexpr int LD = HP_MAXM + 1;
+// Upper triangle of an n x n matrix packed by columns: (r, c), r <= c.
+__device__ __forceinline__ int pk(int r, int c) { return c * (c + 1) / 2 + r; }
+
+// Back substitution R x = rhs (R packed upper triangular, n <= 64) by the one
+// wave of the block: lane l keeps rhs[l] in a register, x[i] is broadcast by a
+// shuffle; x is written to LDS.  rhs is not modified.
+__device__ void upper_solve(const c128* __restrict__ R, const c128* rhs, c128* x, int n) {
+  const int l = threadIdx.x;
+  c128 r = (l < n) ? rhs[l] : mk(0.0, 0.0);
   for (int i = n - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) {
-      const c128 d = R[i + i * LD];
-      x[i] = (abs2(d) > 0.0) ? cdiv(rhs[i], d) : mk(0.0, 0.0);
+    c128 xi = mk(0.0, 0.0);
+    if (l == i) {
+      const c128 d = R[pk(i, i)];
+      xi = (abs2(d) > 0.0) ? cdiv(r, d) : mk(0.0, 0.0);
+      x[i] = xi;
     }
-    __syncthreads();
-    const c128 xi = x[i];
-    for (int l = threadIdx.x; l < i; l += 64) rhs[l] = rhs[l] - R[l + i * LD] * xi;
-    __syncthreads();
+    xi.re = __shfl(xi.re, i, 64);
+    xi.im = __shfl(xi.im, i, 64);
+    if (l < i) r = r - R[pk(l, i)] * xi;
   }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, const int* __restrict__ active,
@@ -806,20 +813,25 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
   }
   int flag = flag_s;
   if (flag) {
-    // least squares R y = g, then y~ = Rc^{-1} y (the coefficients of the stored Z~)
+    // least squares R y = g, then y~ = Rc^{-1} y (the coefficients of the stored Z~);
+    // both triangles go through LDS, packed (one parallel load each)
+    __shared__ c128 tri[HP_MAXM * (HP_MAXM + 1) / 2];
     const int n = m + 1;
-    __threadfence_block();
-    __syncthreads();
+    for (int c = 0; c < n; ++c)
+      for (int r = tid; r <= c; r += 64)
+        tri[pk(r, c)] = (c == m) ? c2[r] : (c == m - 1 ? c1[r] : S.H[r + c * LD]);
     for (int i = tid; i < n; i += 64) rhs[i] = S.g[i];
     __syncthreads();
-    upper_solve(S.H, rhs, y, n);
-    for (int i = tid; i < n; i += 64) rhs[i] = y[i];
+    upper_solve(tri, rhs, y, n);
+    for (int c = 0; c < n; ++c)
+      for (int r = tid; r <= c; r += 64) tri[pk(r, c)] = S.Rc[r + c * LD];
+    for (int i = tid; i < n; i += 64) rhs[i] = y[i];  // the least-squares solution
     __syncthreads();
-    upper_solve(S.Rc, rhs, y, n);
+    upper_solve(tri, rhs, y, n);
     for (int i = tid; i < n; i += 64) S.y[i] = y[i];
     // The estimate measures the split operator I + P M~^-1; it differs from
-    // A M~^-1 by about eps kappa(M_k) ||y|| (||y|| = ||M x||).  When that is not
-    // well below tol, the true residual decides.
+    // A M~^-1 by about eps kappa(M_k) ||y|| (y the least-squares solution, so
+    // ||y|| = ||M x||).  When that is not well below tol, the true residual decides.
     if (tid == 0 && flag == 1 && fixed == 0) {
       double yn = 0.0;
       for (int i = 0; i < n; ++i) yn += abs2(rhs[i]);
