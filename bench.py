@@ -35,6 +35,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "cplx.hpp", "state.hpp", "kernels.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "row_apply_scalar1024_fp64_hbm_counters.md")
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary, or None
+    when there is none for it or the kernel sources changed since it was taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_17446_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(COUNTERS) as fh:
+            kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != h.hexdigest() or kv.get("traffic_kernel", "").strip() != kernel:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -370,7 +390,9 @@ def main():
         "modes": {m: {"steps_per_s": args.steps / res[m]["seconds"], "last_step_iters": res[m]["iters"]}
                   for m in res},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(dom) if best == "fp64" else None,
+                     "algorithmic_bytes_per_launch": by / max(n_l, 1),
                      "launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1)},
         "inner_loop_roofline": {"kernels": ["col", "row_apply"], "steps": "warmup",
                                 "achieved": inner_b / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else 0.0,
