@@ -53,6 +53,15 @@ typedef struct hp_unet_s* hp_unet;
 int hp_unet_create(int levels, int base, int cin, int cout, unsigned long long seed, void* stream, hp_unet* out);
 long hp_unet_num_params(hp_unet net);
 
+/* Arithmetic of the 3x3 convolutions (forward and data gradient):
+ * HP_UNET_F32 (default): float32 direct convolution on the vector ALUs;
+ * HP_UNET_BF16: implicit GEMM on the matrix cores (v_mfma_f32_16x16x32_bf16),
+ * activations and weights rounded to bf16 as they are staged, float32
+ * accumulation.  Parameters, the other layers, the weight gradients and Adam
+ * stay float32 in both. */
+enum { HP_UNET_F32 = 0, HP_UNET_BF16 = 1 };
+int hp_unet_set_precision(hp_unet net, int precision);
+
 /* Host copies (each pointer may be NULL; arrays of hp_unet_num_params floats).
  * Synchronous.  get: parameters, gradients of the last hp_unet_grad, Adam
  * moments and step count; set: parameters and the Adam state (NULL moments

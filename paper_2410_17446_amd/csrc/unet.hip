@@ -84,6 +84,143 @@ __global__ __launch_bounds__(256) void k_conv3(const float* __restrict__ x, cons
   }
 }
 
+// ---------------------------------------------------------------- BF16 MFMA 3x3 convolution
+//
+// The same convolution as an implicit GEMM on the matrix cores:
+// D[co][pixel] = sum over (tap, ci) of W(co, ci, tap) X[ci](pixel + d_tap), the
+// reduction taken 32 input channels at a time per tap by
+// v_mfma_f32_16x16x32_bf16 (bf16 operands, float32 accumulation).  Lane l of a
+// wave holds, for A (16 x 32), row l % 16 and reduction indices 8 (l / 16) ..
+// + 7; for B (32 x 16), column l % 16 and the same reduction indices; the 16 x
+// 16 float result has column l % 16 and rows 4 (l / 16) .. + 3.
+//
+// Operands are prepared once per convolution: the input as bf16 in channel
+// chunks of 32, channel-innermost ([b][chunk][y][x][32], 64 bytes a pixel), and
+// the weights as bf16 A fragments in lane order ([co tile][chunk][tap][block]
+// [lane][8]), so a wave reads each fragment as one contiguous 1 KB block.
+//
+// A workgroup (4 waves) computes 64 output channels x an 8 x 16 pixel tile:
+// wave w takes the channel blocks 2 (w % 2), + 1 and the pixel rows 4 (w / 2)
+// .. + 3 (one 16-pixel row per MFMA column block): 8 accumulators, 2 A and 4 B
+// fragments per tap.  The halo patch (10 x 18 pixels) of each chunk goes
+// through LDS with 40-element pixel rows (80 bytes: the 16 lanes of one
+// reduction group read disjoint banks).
+namespace mf {
+constexpr int TH = 8, TWD = 16;           // pixel tile
+constexpr int CO = 64, CK = 32, CS = 40;  // channels per tile, per chunk, LDS pixel stride
+constexpr int CB = CO / 16;               // 16-channel blocks per tile
+constexpr int HX = TH + 2, HY = TWD + 2;  // halo rows, columns
+}  // namespace mf
+
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_b8 __attribute__((ext_vector_type(8)));
+
+// x [B][C][H][W] float -> xb [B][ceil(C/32)][H][W][32] bf16 (channels past C are 0)
+__global__ void k_to_bf16c(const float* __restrict__ x, __bf16* __restrict__ xb, int B, int C, int H, int W) {
+  const int nch = (C + mf::CK - 1) / mf::CK;
+  const size_t plane = (size_t)H * W;
+  const size_t n = (size_t)B * nch * plane;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = e % plane;
+    const int ch = (int)((e / plane) % nch), b = (int)(e / (plane * nch));
+    mf_b8 v[4];
+#pragma unroll
+    for (int c = 0; c < mf::CK; ++c) {
+      const int ci = ch * mf::CK + c;
+      v[c / 8][c % 8] = (__bf16)(ci < C ? x[((size_t)b * C + ci) * plane + p] : 0.f);
+    }
+    mf_b8* o = reinterpret_cast<mf_b8*>(xb + e * mf::CK);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = v[q];
+  }
+}
+
+// A fragments of the weights: wp[(((ct * nch + ch) * 9 + tap) * CB + blk) * 64 + lane][j] =
+// w(co, ci, tap) with co = 64 ct + 16 blk + lane % 16, ci = 32 ch + 8 (lane / 16) + j, the
+// weight of (co, ci, tap) read at co * wso + ci * wsi + (flip ? 8 - tap : tap); 0 outside.
+__global__ void k_pack_w(const float* __restrict__ w, __bf16* __restrict__ wp, int cin, int cout, int wso, int wsi,
+                         int flip) {
+  const int nch = (cin + mf::CK - 1) / mf::CK, nct = (cout + mf::CO - 1) / mf::CO;
+  const size_t n = (size_t)nct * nch * 9 * mf::CB * 64 * 8;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % 8), lane = (int)((e / 8) % 64), blk = (int)((e / 512) % mf::CB);
+    const size_t r = e / (512 * mf::CB);
+    const int tap = (int)(r % 9), ch = (int)((r / 9) % nch), ct = (int)(r / (9 * (size_t)nch));
+    const int co = ct * mf::CO + blk * 16 + lane % 16, ci = ch * mf::CK + (lane / 16) * 8 + j;
+    float v = 0.f;
+    if (co < cout && ci < cin) v = w[(size_t)co * wso + (size_t)ci * wsi + (flip ? 8 - tap : tap)];
+    wp[e] = (__bf16)v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_conv3_mfma(const __bf16* __restrict__ xb, const __bf16* __restrict__ wp,
+                                                    const float* __restrict__ bias, float* __restrict__ y, int cin,
+                                                    int cout, int H, int W, int relu) {
+  using namespace mf;
+  __shared__ __attribute__((aligned(16))) __bf16 xs[HX * HY * CS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ntx = (W + TWD - 1) / TWD;
+  const int x0 = (blockIdx.x % ntx) * TWD, y0 = (blockIdx.x / ntx) * TH;
+  const int ct = blockIdx.y, b = blockIdx.z;
+  const int nch = (cin + CK - 1) / CK;
+  const size_t plane = (size_t)H * W;
+  const int cb0 = (wave & 1) * 2;  // first channel block of this wave
+  const int r0 = (wave >> 1) * 4;  // first pixel row of this wave
+  const int col = lane & 15, kg = lane >> 4;
+  mf_f4 acc[2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[c][r] = mf_f4{0.f, 0.f, 0.f, 0.f};
+  const mf_b8* wf = reinterpret_cast<const mf_b8*>(wp) + (size_t)ct * nch * 9 * CB * 64;
+  for (int ch = 0; ch < nch; ++ch) {
+    __syncthreads();
+    // halo patch of this chunk: 4 x 16 bytes per pixel
+    const mf_b8* src = reinterpret_cast<const mf_b8*>(xb) + ((size_t)b * nch + ch) * plane * 4;
+    for (int e = tid; e < HX * HY * 4; e += 256) {
+      const int q = e & 3, r = e >> 2;
+      const int gy = y0 + r / HY - 1, gx = x0 + r % HY - 1;
+      mf_b8 v;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = src[((size_t)gy * W + gx) * 4 + q];
+      else
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+      *reinterpret_cast<mf_b8*>(&xs[r * CS + q * 8]) = v;
+    }
+    __syncthreads();
+    const mf_b8* wc = wf + (size_t)ch * 9 * CB * 64;
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
+      const mf_b8 a0 = wc[(tap * CB + cb0) * 64 + lane];
+      const mf_b8 a1 = wc[(tap * CB + cb0 + 1) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const mf_b8 bv = *reinterpret_cast<const mf_b8*>(&xs[((r0 + r + dy) * HY + col + dx) * CS + kg * 8]);
+        acc[0][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[0][r], 0, 0, 0);
+        acc[1][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[1][r], 0, 0, 0);
+      }
+    }
+  }
+  // D: column = pixel x0 + col of row y0 + r0 + r; rows = channels 16 (cb0 + c) + 4 kg + i
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int oy = y0 + r0 + r, ox = x0 + col;
+    if (oy >= H || ox >= W) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = ct * CO + (cb0 + c) * 16 + kg * 4 + i;
+        if (co >= cout) continue;
+        float v = acc[c][r][i] + (bias ? bias[co] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        y[((size_t)b * cout + co) * plane + (size_t)oy * W + ox] = v;
+      }
+  }
+}
+
 // dW[co][ci][k] = sum_b sum_p dy[b][co](p) x[b][ci](p + d_k): one workgroup per (co, ci).
 __global__ __launch_bounds__(256) void k_conv3_wgrad(const float* __restrict__ x, const float* __restrict__ dy,
                                                      float* __restrict__ dw, int B, int cin, int cout, int H, int W) {
@@ -406,6 +543,7 @@ int eblocks(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192); }
 
 struct hp_unet_s {
   int levels = 4, base = 32, cin = 7, cout = 2;
+  bool bf16 = false;  // 3x3 convolutions (forward, data gradient) on bf16 matrix cores
   struct Conv {
     int ci, co, k;  // k = 3 or 1
     size_t w, b;    // offsets (floats) of weights [co][ci][k][k] and bias [co]
@@ -419,6 +557,8 @@ struct hp_unet_s {
   int B = 0, H = 0, W = 0;
   std::vector<float*> enc1, enc2, pool, up, dec1, dec2, dskip;
   float *y = nullptr, *dy = nullptr, *ga = nullptr, *gb = nullptr;
+  __bf16* xb = nullptr;   // bf16 channel-chunked copy of a convolution's input
+  __bf16* wpk = nullptr;  // bf16 weight fragments of one convolution
   std::vector<float*> owned;
   double* part = nullptr;    // device partial sums (loss)
   double* part_h = nullptr;  // pinned
@@ -466,6 +606,7 @@ void free_acts(hp_unet n) {
   n->owned.clear();
   for (auto* v : {&n->enc1, &n->enc2, &n->pool, &n->up, &n->dec1, &n->dec2, &n->dskip}) v->clear();
   n->y = n->dy = n->ga = n->gb = nullptr;
+  n->xb = n->wpk = nullptr;
   n->B = n->H = n->W = 0;
 }
 
@@ -504,6 +645,20 @@ int ensure_acts(hp_unet n, int B, int H, int W) {
   n->dy = dalloc(n, (size_t)B * n->cout * pl0, &ok);
   n->ga = dalloc(n, g, &ok);
   n->gb = dalloc(n, g, &ok);
+  // bf16 operand buffers: every convolution input (forward or data gradient)
+  // has at most 3 base channels at full resolution (or cin / cout)
+  {
+    const int cmax = std::max({3 * n->base, n->cin, n->base << (L - 1)});
+    const size_t ch32 = (size_t)((cmax + mf::CK - 1) / mf::CK) * mf::CK;
+    n->xb = reinterpret_cast<__bf16*>(dalloc(n, (size_t)B * pl0 * ch32 / 2 + 8, &ok));
+    size_t wmax = 0;
+    auto wsz = [&](int ci, int co) {
+      return (size_t)((co + mf::CO - 1) / mf::CO) * ((ci + mf::CK - 1) / mf::CK) * 9 * mf::CB * 64 * 8;
+    };
+    for (auto* v : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
+      for (auto& c : *v) wmax = std::max({wmax, wsz(c.ci, c.co), wsz(c.co, c.ci)});
+    n->wpk = reinterpret_cast<__bf16*>(dalloc(n, wmax / 2 + 8, &ok));
+  }
   if (!ok) {
     free_acts(n);
     return ufail(n, HP_ENOMEM, "activation allocation failed");
@@ -514,20 +669,31 @@ int ensure_acts(hp_unet n, int B, int H, int W) {
   return HP_OK;
 }
 
+// y = conv(x) with weights addressed as in k_conv3; float32 or bf16 matrix cores
+void conv3_any(hp_unet n, const float* x, const float* w, const float* bias, float* y, int cin, int cout, int B,
+               int H, int W, int wso, int wsi, int flip, int relu) {
+  if (n->bf16) {
+    const int nch = (cin + mf::CK - 1) / mf::CK, nct = (cout + mf::CO - 1) / mf::CO;
+    const size_t xn = (size_t)B * nch * H * W, wn = (size_t)nct * nch * 9 * mf::CB * 64 * 8;
+    hipLaunchKernelGGL(k_to_bf16c, dim3(eblocks(xn)), dim3(256), 0, n->stream, x, n->xb, B, cin, H, W);
+    hipLaunchKernelGGL(k_pack_w, dim3(eblocks(wn)), dim3(256), 0, n->stream, w, n->wpk, cin, cout, wso, wsi, flip);
+    dim3 grid(((W + mf::TWD - 1) / mf::TWD) * ((H + mf::TH - 1) / mf::TH), nct, B);
+    hipLaunchKernelGGL(k_conv3_mfma, grid, dim3(256), 0, n->stream, n->xb, n->wpk, bias, y, cin, cout, H, W, relu);
+  } else {
+    dim3 grid(((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE), (cout + COB - 1) / COB, B);
+    hipLaunchKernelGGL(k_conv3, grid, dim3(256), 0, n->stream, x, w, bias, y, cin, cout, H, W, wso, wsi, flip,
+                       relu);
+  }
+}
+
 void conv3(hp_unet n, const float* x, const hp_unet_s::Conv& c, float* y, int B, int H, int W, int relu) {
-  dim3 grid(((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE), (c.co + COB - 1) / COB, B);
-  hipLaunchKernelGGL(k_conv3, grid, dim3(256), 0, n->stream, x, n->P + c.w, n->P + c.b, y, c.ci, c.co, H, W,
-                     c.ci * 9, 9, 0, relu);
+  conv3_any(n, x, n->P + c.w, n->P + c.b, y, c.ci, c.co, B, H, W, c.ci * 9, 9, 0, relu);
 }
 
 // Gradients of one 3x3 convolution: dW, db into G; dx (when wanted) from dy.
 void conv3_bwd(hp_unet n, const float* x, const float* dy, const hp_unet_s::Conv& c, float* dx, int B, int H,
                int W) {
-  if (dx) {
-    dim3 grid(((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE), (c.ci + COB - 1) / COB, B);
-    hipLaunchKernelGGL(k_conv3, grid, dim3(256), 0, n->stream, dy, n->P + c.w, nullptr, dx, c.co, c.ci, H, W, 9,
-                       c.ci * 9, 1, 0);
-  }
+  if (dx) conv3_any(n, dy, n->P + c.w, nullptr, dx, c.co, c.ci, B, H, W, 9, c.ci * 9, 1, 0);
   hipLaunchKernelGGL(k_conv3_wgrad, dim3(c.co * c.ci), dim3(256), 0, n->stream, x, dy, n->G + c.w, B, c.ci, c.co, H,
                      W);
   hipLaunchKernelGGL(k_bias_grad, dim3(c.co), dim3(256), 0, n->stream, dy, n->G + c.b, B, c.co, (size_t)H * W);
@@ -691,6 +857,13 @@ int hp_unet_create(int levels, int base, int cin, int cout, unsigned long long s
 }
 
 long hp_unet_num_params(hp_unet n) { return n ? (long)n->nparam : 0; }
+
+int hp_unet_set_precision(hp_unet n, int precision) {
+  if (!n) return ufail(nullptr, HP_EINVAL, "net is NULL");
+  if (precision != HP_UNET_F32 && precision != HP_UNET_BF16) return ufail(n, HP_EINVAL, "unknown precision");
+  n->bf16 = precision == HP_UNET_BF16;
+  return HP_OK;
+}
 
 int hp_unet_get_params(hp_unet n, float* params, float* grads, float* adam_m, float* adam_v, long* adam_step) {
   if (!n) return ufail(nullptr, HP_EINVAL, "net is NULL");

@@ -13,11 +13,12 @@ import numpy as np
 
 from . import hp
 
-SYMBOLS = ("hp_unet_create", "hp_unet_num_params", "hp_unet_get_params", "hp_unet_set_params",
+SYMBOLS = ("hp_unet_create", "hp_unet_num_params", "hp_unet_set_precision", "hp_unet_get_params", "hp_unet_set_params",
            "hp_unet_forward", "hp_unet_grad", "hp_unet_adam", "hp_guess_stats", "hp_guess_pack",
            "hp_guess_unpack", "hp_guess_target", "hp_unet_last_error", "hp_unet_destroy")
 
 _ready = False
+HP_UNET_F32, HP_UNET_BF16 = 0, 1
 
 
 def lib():
@@ -28,6 +29,7 @@ def lib():
         L.hp_unet_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_ulonglong, vp, C.POINTER(vp)]
         L.hp_unet_num_params.argtypes = [vp]
         L.hp_unet_num_params.restype = C.c_long
+        L.hp_unet_set_precision.argtypes = [vp, C.c_int]
         L.hp_unet_get_params.argtypes = [vp, fp, fp, fp, fp, lp]
         L.hp_unet_set_params.argtypes = [vp, fp, fp, fp, C.c_long]
         L.hp_unet_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, vp]
@@ -55,7 +57,7 @@ def _fptr(a):
 class UNet:
     """hp_unet: levels, base channels, input and output channels; float32 parameters."""
 
-    def __init__(self, levels=4, base=32, cin=7, cout=2, seed=0, stream=None):
+    def __init__(self, levels=4, base=32, cin=7, cout=2, seed=0, stream=None, precision=HP_UNET_F32):
         import torch
         self.L = lib()
         self.levels, self.base, self.cin, self.cout = levels, base, cin, cout
@@ -66,6 +68,12 @@ class UNet:
         if rc < 0:
             raise hp.HPError(f"hp_unet_create: {rc}: {self.L.hp_unet_last_error(None).decode()}")
         self.nparam = int(self.L.hp_unet_num_params(self.handle))
+        self.set_precision(precision)
+
+    def set_precision(self, precision):
+        """HP_UNET_F32 (float32 convolutions) or HP_UNET_BF16 (bf16 matrix cores)."""
+        self._check(self.L.hp_unet_set_precision(self.handle, int(precision)), "hp_unet_set_precision")
+        self.precision = precision
 
     def _check(self, rc, what):
         if rc < 0:

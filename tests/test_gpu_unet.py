@@ -5,7 +5,10 @@ learned guess end to end.
 Tolerances: float32 weights, activations and accumulation against float64:
 forward 1e-5 relative L2, gradients 1e-4 (a ReLU whose input rounds to the
 other side of 0 changes a few terms), Adam 1e-5; guess planes 1e-6 (float32
-rounding of planes computed in FP64).
+rounding of planes computed in FP64).  The bf16 matrix-core convolutions
+(8 significant bits per operand, float32 accumulation): forward 2e-2,
+gradients 5e-2, and bit-exact against float32 where every operand and sum is
+exact.
 """
 import numpy as np
 import pytest
@@ -60,6 +63,43 @@ def test_gradients_match_oracle(levels):
     rloss, rg = ref.loss_and_grad(x.astype(np.float64), t.astype(np.float64))
     assert abs(loss - rloss) <= 1e-6 * rloss
     assert rel_l2(s["grads"], rg) < 1e-4
+
+
+def test_bf16_convolutions_exact_on_small_integers():
+    """Integer weights and inputs small enough that every bf16 operand and every float32 sum is
+    exact: the matrix-core convolutions (cin 7 and 48: one and two channel chunks; cout 48: a
+    partial channel tile; 40 x 24 pixels: partial pixel tiles) equal the float32 ones bit for bit."""
+    torch = _cuda()
+    from paper_2410_17446_amd.unet import HP_UNET_BF16, UNet
+    rng = np.random.default_rng(3)
+    a = UNet(1, 48, 7, 2, seed=0)
+    p = rng.integers(-1, 2, size=a.nparam).astype(np.float32)
+    a.load_state(p)
+    b = UNet(1, 48, 7, 2, seed=0, precision=HP_UNET_BF16)
+    b.load_state(p)
+    x = to_gpu(rng.integers(-2, 3, size=(2, 7, 40, 24)).astype(np.float32))
+    ya, yb = a.forward(x).cpu().numpy(), b.forward(x).cpu().numpy()
+    assert np.abs(ya).max() > 10
+    assert np.array_equal(ya, yb)
+
+
+@pytest.mark.parametrize("levels", [1, 3])
+def test_bf16_forward_and_gradients_near_oracle(levels):
+    """bf16 operands (8 significant bits), float32 accumulation: forward within 2e-2 and the
+    gradient (whose data-gradient convolutions also run on the matrix cores) within 5e-2
+    relative L2 of the FP64 reference."""
+    torch = _cuda()
+    from paper_2410_17446_amd.unet import HP_UNET_BF16
+    net = _net(levels, 8)
+    net.set_precision(HP_UNET_BF16)
+    x, t = _data()
+    y = net.forward(to_gpu(x)).cpu().numpy()
+    ref = ounet.UNet(levels, 8, 7, 2, net.state()["params"].astype(np.float64))
+    ry, _ = ref.forward(x.astype(np.float64))
+    assert rel_l2(y, ry) < 2e-2
+    net.grad(to_gpu(x), to_gpu(t))
+    _, rg = ref.loss_and_grad(x.astype(np.float64), t.astype(np.float64))
+    assert rel_l2(net.state()["grads"], rg) < 5e-2
 
 
 def test_adam_matches_oracle_and_checkpoint_resumes_exactly():
