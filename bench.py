@@ -379,7 +379,8 @@ def main():
     inner_ms = brk["col"][1] + brk["row_apply"][1]
     inner_b = brk["col"][2] + brk["row_apply"][2]
     line = {
-        "metric": "propagation steps/s (1024^2, 16 poles, err<=1e-6 vs FP64), plain GPU method",
+        "metric": (f"propagation steps/s ({cfg['N']}^2{' vector' if cfg['ncomp'] == 2 else ''}, {cfg['npoles']} poles, "
+                   f"err<=1e-6 vs FP64), plain GPU method"),
         "value": value,
         "unit": "steps/s",
         "n_gpus": 1,
