@@ -55,6 +55,7 @@ struct hp_plan_s {
   void *tw_x = nullptr, *tw_y = nullptr;
   c128* tw64_x = nullptr;
   double *coef = nullptr, *coef_scratch = nullptr;
+  float* coef_f = nullptr;  // float copy of the coefficient planes (mixed precision)
   void *U = nullptr, *Z = nullptr, *P = nullptr, *DZ = nullptr, *bR = nullptr, *tmpR = nullptr;
   c128 *X = nullptr, *tmp1 = nullptr, *tmp2 = nullptr;
   PoleState* st = nullptr;
@@ -185,6 +186,7 @@ void layout(hp_plan p, Ws& w) {
   p->tw64_x = w.take<c128>(d.nx + d.nx / 2 + 1);
   p->coef = w.take<double>((d.ncomp == 2 ? 6 : 1) * p->geo.fsz);
   p->coef_scratch = w.take<double>((d.ncomp == 2 ? 2 : 1) * p->geo.fsz);
+  p->coef_f = w.take<float>(p->mixed ? (d.ncomp == 2 ? 6 : 1) * p->geo.fsz : 1);
   p->U = w.take<char>((size_t)K * (M + 1) * fn * es);
   p->Z = w.take<char>((size_t)K * M * fn * es);
   p->P = w.take<char>((size_t)K * fn * es);
@@ -288,6 +290,18 @@ int upload_state(hp_plan p) {
   }
   HPCHK(hipMemcpyAsync(p->st, h.data(), h.size() * sizeof(PoleState), hipMemcpyHostToDevice, p->stream));
   return HP_OK;
+}
+
+// coefficient planes in the working precision
+template <typename T>
+const T* coef_as(hp_plan p);
+template <>
+const double* coef_as<double>(hp_plan p) {
+  return p->coef;
+}
+template <>
+const float* coef_as<float>(hp_plan p) {
+  return p->coef_f;
 }
 
 template <typename T>
@@ -542,7 +556,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     {
       const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
       Prof pr(p, HP_K_ROW_APPLY, U1 * es * per_pole + (U1 / d.ncomp) * 8.0 * planes);
-      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, p->coef, p->st, ad, na, p->part_dots, twx, p->geo,
+      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<T>(p), p->st, ad, na, p->part_dots, twx, p->geo,
                           p->sc, p->stream);
     }
     {
@@ -843,6 +857,7 @@ int hp_set_medium(hp_plan p, const double* n2) {
   if (!n2) return fail(p, HP_EINVAL, "n2 is NULL");
   const double s = 1.0 / ((p->d.k0 * p->d.n0) * (p->d.k0 * p->d.n0));
   launch_coef(n2, p->coef, p->coef_scratch, p->d.n0, s, p->d.edge_width, p->sc, p->geo, p->stream);
+  if (p->mixed) launch_to_float(p->coef, p->coef_f, (p->d.ncomp == 2 ? 6 : 1) * p->geo.fsz, p->stream);
   HPCHK(hipGetLastError());
   p->medium_set = true;
   return HP_OK;

@@ -311,7 +311,7 @@ struct ApplyWaves {
 template <typename T, int N, int NC>
 __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
-    cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const double* __restrict__ coef,
+    cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const T* __restrict__ coef,
     const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
     const cx<T>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
   using AC = ApplyCfg<N, NC>;
@@ -348,7 +348,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
       const cx<T> zj = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
-      const T v = valid ? (T)coef[ci0 + j] : (T)0;
+      const T v = valid ? coef[ci0 + j] : (T)0;
       pz[s] = v * zj;
     }
   } else {
@@ -400,8 +400,8 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
         continue;
       }
       const size_t ci = ci0 + j;
-      const T v = (T)coef[ci], px = (T)coef[fsz + ci], py = (T)coef[2 * fsz + ci];
-      const T pxx = (T)coef[3 * fsz + ci], pyy = (T)coef[4 * fsz + ci], pxy = (T)coef[5 * fsz + ci];
+      const T v = coef[ci], px = coef[fsz + ci], py = coef[2 * fsz + ci];
+      const T pxx = coef[3 * fsz + ci], pyy = coef[4 * fsz + ci], pxy = coef[5 * fsz + ci];
       const cx<T> zo = other[pidx(j)], dzo = other2[pidx(j)];
       if (comp == 0)
         pz[s] = pxx * zc[s] + px * dxz[s] + pxy * zo + py * dzo + v * zc[s];
@@ -1187,7 +1187,7 @@ int row_apply_parts(const Geo& g) {
 
 template <typename T>
 void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
-                      size_t psp, const cx<T>* const* uptr, const double* coef, const PoleState* st,
+                      size_t psp, const cx<T>* const* uptr, const T* coef, const PoleState* st,
                       const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
                       const StencilCoef& sc, hipStream_t s) {
   const int nblk = row_apply_blocks<T>(g);
@@ -1278,6 +1278,15 @@ void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_mark_folded, dim3(1), dim3(HP_MAXPOLES), 0, s, st, first, count);
 }
 
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+void launch_to_float(const double* a, float* b, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_float, dim3(2048), dim3(256), 0, s, a, b, n);
+}
+
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, p, n);
 }
@@ -1293,7 +1302,7 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
                               const int*, int, bool, const double*, const double*, const cx<T>*, const Geo&,         \
                               const StencilCoef&, hipStream_t);                                                      \
   template void launch_row_apply<T>(const cx<T>*, size_t, size_t, const cx<T>*, size_t, cx<T>*, size_t,              \
-                                    const cx<T>* const*, const double*, const PoleState*, const int*, int, double2*, \
+                                    const cx<T>* const*, const T*, const PoleState*, const int*, int, double2*, \
                                     const cx<T>*, const Geo&, const StencilCoef&, hipStream_t);                      \
   template void launch_update<T>(const cx<T>*, size_t, cx<T>* const*, const PoleState*, const int*, int, double*,    \
                                  int, const Geo&, hipStream_t);                                                      \

@@ -39,10 +39,11 @@ void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, 
                 const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s);
 
 // Row pass: p = S_x (P (S_x z_m)) with P the medium part of Zbar, plus the
-// partial inner products <u_i, p>, i = 0..m.
+// partial inner products <u_i, p>, i = 0..m.  coef: the coefficient planes in
+// the working precision.
 template <typename T>
 void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
-                      size_t psp, const cx<T>* const* uptr, const double* coef, const PoleState* st,
+                      size_t psp, const cx<T>* const* uptr, const T* coef, const PoleState* st,
                       const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
                       const StencilCoef& sc, hipStream_t s);
 template <typename T>
@@ -104,3 +105,4 @@ void launch_coef(const double* n2, double* coef, double* scratch, double n0, dou
 void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s);
 
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);
+void launch_to_float(const double* a, float* b, size_t n, hipStream_t s);
