@@ -79,6 +79,11 @@ struct ColCfg {
   static_assert(TW % GC == 0, "column groups tile the 128-byte row");
   static constexpr int WG = GC * NT;
   static constexpr int SCR = ScanScratch<NT>::SIZE;
+  // LDS stride between the GC column buffers: plen(N) (a multiple of 256 bytes
+  // for the sizes used) plus 256/GC bytes, so that neighbouring threads, which
+  // alternate columns in the load, divide and store loops, hit different banks
+  static constexpr int SHIFT = (256 / GC) / (int)sizeof(cx<T>) > 0 ? (256 / GC) / (int)sizeof(cx<T>) : 1;
+  static constexpr int PLC = plen(N) + SHIFT;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -227,7 +232,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG), (ColWaves<T, N>::V)) void k_col
     StencilCoef sc) {
   using CC = ColCfg<T, N>;
   constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
-  constexpr int PL = plen(N);
+  constexpr int PL = CC::PLC;  // padded per-column stride
   constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
   __shared__ cx<T> lds[GC * PL];
   __shared__ cx<T> scr[GC * CC::SCR];
