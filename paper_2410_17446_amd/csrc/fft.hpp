@@ -15,7 +15,7 @@
 // so the odd outputs are a prefix sum (a shuffle scan here).  This holds for
 // complex x because every step is linear with real coefficients.
 //
-// FFT: self-sorting Stockham radix-8/4/2 with the data in LDS, one group of
+// FFT: self-sorting Stockham radix-16/8/4/2 (and 3) with the data in LDS, one group of
 // NT = L/8 threads per transform, each thread holding R values of a stage in
 // registers.  Twiddles come from a table tw[m] = exp(-2 pi i m / L).
 //
@@ -57,6 +57,40 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     v[1] = t - v[1];
   } else if constexpr (R == 4) {
     dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 16) {
+    // 16 = 4 x 4: length-4 DFTs over n1 (n = 4 n1 + n2), twiddles W16^(n2 k1),
+    // length-4 DFTs over n2; output k = k1 + 4 k2
+    const T c1 = (T)0.923879532511286756128183189396788933;  // cos(pi/8)
+    const T s1 = (T)0.382683432365089771728459984030398866;  // sin(pi/8)
+    const T h = (T)0.707106781186547524400844362104849039;
+    cx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      a[n2][0] = v[n2];
+      a[n2][1] = v[4 + n2];
+      a[n2][2] = v[8 + n2];
+      a[n2][3] = v[12 + n2];
+      dft4(a[n2][0], a[n2][1], a[n2][2], a[n2][3]);
+    }
+    // W16^m = cos(m pi/8) - i sin(m pi/8), m = n2 k1 in {1, 2, 3, 4, 6, 9}
+    a[1][1] = a[1][1] * mk<T>(c1, -s1);
+    a[1][2] = a[1][2] * mk<T>(h, -h);
+    a[1][3] = a[1][3] * mk<T>(s1, -c1);
+    a[2][1] = a[2][1] * mk<T>(h, -h);
+    a[2][2] = mul_mi(a[2][2]);
+    a[2][3] = a[2][3] * mk<T>(-h, -h);
+    a[3][1] = a[3][1] * mk<T>(s1, -c1);
+    a[3][2] = a[3][2] * mk<T>(-h, -h);
+    a[3][3] = a[3][3] * mk<T>(-c1, s1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+      dft4(b0, b1, b2, b3);
+      v[k1] = b0;
+      v[k1 + 4] = b1;
+      v[k1 + 8] = b2;
+      v[k1 + 12] = b3;
+    }
   } else {
     static_assert(R == 8, "radix");
     cx<T> a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6];
@@ -128,7 +162,10 @@ template <typename T, int L, int NS, int NT>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int t) {
   if constexpr (NS < L) {
     constexpr int REM = L / NS;
-    constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3));
+    // radix 8 where it leaves no radix-2 stage; 16 for remainders 16 and 256
+    // (so 1024 = 8 8 16 and 2048 = 8 16 16: three passes through LDS, not four)
+    constexpr int R = (REM == 16 || REM == 256) ? 16
+                                                : ((REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3)));
     static_assert(REM % R == 0, "lengths are 2^k or 3 * 2^k");
     fft_stage<T, L, R, NS, NT>(buf, tw, t);
     fft_stages<T, L, NS * R, NT>(buf, tw, t);

@@ -303,14 +303,14 @@ struct ApplyCfg {
 };
 
 // Waves per SIMD the register allocation must allow, the most that compile
-// without spilling: scalar complex64 four (128 VGPRs; three for 3 * 2^k and
-// 2048), scalar complex128 three (two at 2048); vector fields as many as their
-// registers allow (complex64 one, complex128 two).
+// without spilling: scalar fields four (128 VGPRs) for 2^k up to 1024, else
+// three (complex128 at 2048: two); vector fields as many as their registers
+// allow (complex64 one, complex128 two).
 template <typename T, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
   static constexpr int V = NC == 2 ? (sizeof(T) == 4 ? 1 : 2)
-                                   : (sizeof(T) == 4 ? (N <= 1024 && POW2 ? 4 : 3) : (N >= 2048 ? 2 : 3));
+                                   : ((N <= 1024 && POW2) ? 4 : (sizeof(T) == 4 || N < 2048 ? 3 : 2));
 };
 
 template <typename T, int N, int NC>
