@@ -973,41 +973,59 @@ __device__ __forceinline__ c128 ld_odd(const c128* __restrict__ x, int i, int j,
 }
 
 constexpr int OP_WG = 256;
+constexpr int OP_TX = 64, OP_TY = 16, OP_H = 6;  // output tile, stencil half-width
+constexpr int OP_LX = OP_TX + 2 * OP_H, OP_LY = OP_TY + 2 * OP_H;
 
+// The explicit FP64 operator on LDS tiles: each workgroup stages a 64 x 16
+// tile of every component with a 6-node halo (odd reflection about the
+// Dirichlet nodes applied while staging), then each thread evaluates four
+// pixels of a column of the tile.
+template <int NC>
 __global__ __launch_bounds__(OP_WG) void k_apply_op(const c128* __restrict__ x, const c128* __restrict__ rhs,
                                                     c128* __restrict__ y, const double* __restrict__ coef, c128 b,
-                                                    StencilCoef sc, int nx, int ny, int ncomp, size_t fsz,
+                                                    StencilCoef sc, int nx, int ny, size_t fsz,
                                                     double* __restrict__ part, int medium_only) {
+  __shared__ c128 tile[NC][OP_LY * OP_LX];
   __shared__ double red[OP_WG / 64];
+  const int ntx = (nx + OP_TX - 1) / OP_TX;
+  const int x0 = (blockIdx.x % ntx) * OP_TX, y0 = (blockIdx.x / ntx) * OP_TY;
+  for (int c = 0; c < NC; ++c)
+    for (int e = threadIdx.x; e < OP_LY * OP_LX; e += OP_WG)
+      tile[c][e] = ld_odd(x + c * fsz, y0 + e / OP_LX - OP_H, x0 + e % OP_LX - OP_H, nx, ny);
+  __syncthreads();
   double nrm = 0.0;
-  const size_t idx = (size_t)blockIdx.x * OP_WG + threadIdx.x;
-  if (idx < fsz) {
-    const int i = (int)(idx / nx), j = (int)(idx % nx);
+  const int tx = threadIdx.x % OP_TX, tq = threadIdx.x / OP_TX;
+#pragma unroll
+  for (int q = 0; q < OP_TY / (OP_WG / OP_TX); ++q) {
+    const int ty = tq + q * (OP_WG / OP_TX);
+    const int i = y0 + ty, j = x0 + tx;
+    if (i >= ny || j >= nx) continue;
+    const size_t idx = (size_t)i * nx + j;
     const bool inner = i > 0 && j > 0;
-    c128 lap[2], d1x[2], d1y[2], xc[2];
-    for (int c = 0; c < ncomp; ++c) {
-      const c128* xc_ = x + c * fsz;
-      c128 l = mk(0.0, 0.0), ax = mk(0.0, 0.0), ay = mk(0.0, 0.0);
-      const c128 x0 = inner ? xc_[idx] : mk(0.0, 0.0);
-      if (inner) {
-        l = (sc.c2x[0] + sc.c2y[0]) * x0;
-        for (int mm = 1; mm <= 6; ++mm) {
-          const c128 xp = ld_odd(xc_, i, j + mm, nx, ny), xm = ld_odd(xc_, i, j - mm, nx, ny);
-          const c128 yp = ld_odd(xc_, i + mm, j, nx, ny), ym = ld_odd(xc_, i - mm, j, nx, ny);
-          l = l + sc.c2x[mm] * (xp + xm) + sc.c2y[mm] * (yp + ym);
-          ax = ax + sc.d1x[mm - 1] * (xp - xm);
-          ay = ay + sc.d1y[mm - 1] * (yp - ym);
-        }
+    const int lc = (ty + OP_H) * OP_LX + tx + OP_H;
+    c128 lap[NC], d1x[NC], d1y[NC], xc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const c128* t = tile[c];
+      const c128 x0c = t[lc];
+      c128 l = (sc.c2x[0] + sc.c2y[0]) * x0c, ax = mk(0.0, 0.0), ay = mk(0.0, 0.0);
+#pragma unroll
+      for (int mm = 1; mm <= 6; ++mm) {
+        const c128 xp = t[lc + mm], xm = t[lc - mm], yp = t[lc + mm * OP_LX], ym = t[lc - mm * OP_LX];
+        l = l + sc.c2x[mm] * (xp + xm) + sc.c2y[mm] * (yp + ym);
+        ax = ax + sc.d1x[mm - 1] * (xp - xm);
+        ay = ay + sc.d1y[mm - 1] * (yp - ym);
       }
       lap[c] = l;
       d1x[c] = ax;
       d1y[c] = ay;
-      xc[c] = x0;
+      xc[c] = x0c;
     }
     const double V = coef[idx];
-    for (int c = 0; c < ncomp; ++c) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
       c128 v = medium_only ? V * xc[c] : lap[c] + V * xc[c] - b * xc[c];
-      if (ncomp == 2) {
+      if constexpr (NC == 2) {
         const double px = coef[fsz + idx], py = coef[2 * fsz + idx], pxx = coef[3 * fsz + idx],
                      pyy = coef[4 * fsz + idx], pxy = coef[5 * fsz + idx];
         if (c == 0)
@@ -1259,12 +1277,16 @@ void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, i
   hipLaunchKernelGGL((k_accum<T>), dim3(update_blocks(total)), dim3(256), 0, s, xacc, z, zsi, st, pole, total);
 }
 
-int op_blocks(const Geo& g) { return (int)((g.fsz + OP_WG - 1) / OP_WG); }
+int op_blocks(const Geo& g) { return ((g.nx + OP_TX - 1) / OP_TX) * ((g.ny + OP_TY - 1) / OP_TY); }
 
 void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
                      const Geo& g, double* part, hipStream_t s, int medium_only) {
-  hipLaunchKernelGGL(k_apply_op, dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny, g.ncomp,
-                     g.fsz, part, medium_only);
+  if (g.ncomp == 2)
+    hipLaunchKernelGGL((k_apply_op<2>), dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny,
+                       g.fsz, part, medium_only);
+  else
+    hipLaunchKernelGGL((k_apply_op<1>), dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny,
+                       g.fsz, part, medium_only);
 }
 
 void launch_coef(const double* n2, double* coef, double* scratch, double n0, double s_scale, int W,
