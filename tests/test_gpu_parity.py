@@ -282,3 +282,44 @@ def test_radix3_sizes(N, precision):
         plan.set_fixed_iters([sum(c) for c in stats.cycle_iters])
         out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
         assert rel_l2(out.cpu().numpy(), ref) < 1e-10
+
+
+def test_zero_field_steps_to_zero():
+    """Degenerate input: w = 0 gives x_k = 0 for every pole (no division by the zero norm), an
+    all-zero output and zero iterations' worth of error."""
+    torch = _cuda()
+    wl = workload(N=64, W=8)
+    plan = gpu_plan(wl)
+    w = torch.zeros((1, 64, 64), dtype=torch.complex128, device="cuda")
+    out = plan.step(w, to_gpu(wl["n2"]))
+    assert bool(torch.isfinite(torch.view_as_real(out)).all())
+    assert float(out.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("npoles,restart", [(1, 30), (4, 2), (8, 4)])
+def test_single_pole_and_short_restarts(npoles, restart):
+    """One pole, and GMRES(2) / GMRES(4) with up to nine restarts: the true residual of every
+    solve still meets tol and the field matches the oracle (same fit, same tol) to ~tol."""
+    torch = _cuda()
+    wl = workload(N=64, W=8, npoles=npoles, tol=1e-9, restart=restart)
+    ref, stats = _oracle_step(wl)
+    plan = gpu_plan(wl, restart=restart)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    _, rr = plan.stats()
+    assert max(rr) <= 1e-9
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-7
+
+
+def test_largest_pole_count():
+    """24 poles, the largest table the workloads use; at dz = lambda the fits of this interval
+    with more poles start to place poles above the real axis.  Every solve meets tol and the
+    step matches the oracle's step with the same fit."""
+    torch = _cuda()
+    wl = workload(N=64, W=8, npoles=24, tol=1e-10)
+    assert np.all(wl["fit"]["poles"].imag < 0)
+    ref, _ = _oracle_step(wl)
+    plan = gpu_plan(wl)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    _, rr = plan.stats()
+    assert max(rr) <= 1e-10
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-8
