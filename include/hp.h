@@ -66,7 +66,18 @@ enum {
   HP_ESTATE = -4
 };
 
-enum { HP_FP64 = 0, HP_MIXED = 1 };
+/* Precision of the GMRES inner loop (Sec. 4.2).  In every mode the Arnoldi
+ * coefficients, Givens rotations, least squares, the solution accumulator,
+ * the true residual and the residue-weighted sum are FP64.
+ *   HP_FP64:    complex128 Krylov vectors and transforms.
+ *   HP_MIXED:   complex64 Krylov vectors and complex64 transforms; each
+ *               complex64 cycle stops at 1e-5 of its starting residual and the
+ *               FP64 true residual restarts it (iterative refinement).
+ *   HP_MIXED64: complex64 Krylov vectors (half the HBM traffic), transforms in
+ *               FP64 arithmetic; a cycle runs to tol and the FP64 true
+ *               residual decides, restarting the solve if the rounding of the
+ *               stored vectors kept it above tol. */
+enum { HP_FP64 = 0, HP_MIXED = 1, HP_MIXED64 = 2 };
 
 typedef struct {
   int nx, ny;                 /* cells per axis = array dims; 2^k or 3 * 2^k, 64 <= n <= 2048 */
@@ -84,7 +95,7 @@ typedef struct {
   double tol;                 /* relative residual ||w - A x|| / ||w|| per solve */
   int restart;                /* GMRES(m) restart length, 1..64 */
   int max_cycles;             /* restarts before HP_WARN_NOCONV, >= 1 */
-  int precision;              /* HP_FP64 (complex128 everywhere) or HP_MIXED */
+  int precision;              /* HP_FP64, HP_MIXED or HP_MIXED64 */
 } hp_plan_desc;
 
 /* Device bytes a plan needs; 0 if desc is invalid. */

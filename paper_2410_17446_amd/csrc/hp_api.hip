@@ -47,7 +47,8 @@ struct hp_plan_s {
   size_t ws_bytes = 0;
   Geo geo{};
   StencilCoef sc{};
-  bool mixed = false;
+  bool mixed = false;     // complex64 storage of the R-domain fields
+  bool mixed64 = false;   // ... with FP64 transforms (HP_MIXED64)
   int nrowblk = 0, napplyblk = 0, nupdblk = 0, nopblk = 0;
   size_t fieldn = 0;  // ncomp * nx * ny
   // device
@@ -158,7 +159,8 @@ std::string validate(const hp_plan_desc* d) {
   if (!d) return "desc is NULL";
   if (!fft_size(d->nx) || !fft_size(d->ny)) return "nx, ny must be 2^k or 3 * 2^k in [64, 2048]";
   if (d->ncomp != 1 && d->ncomp != 2) return "ncomp must be 1 or 2";
-  if (d->precision != HP_FP64 && d->precision != HP_MIXED) return "precision must be HP_FP64 or HP_MIXED";
+  if (d->precision != HP_FP64 && d->precision != HP_MIXED && d->precision != HP_MIXED64)
+    return "precision must be HP_FP64, HP_MIXED or HP_MIXED64";
   if (d->ncomp == 2 && d->precision == HP_FP64 && d->nx > 1024) return "FP64 vector plans support n <= 1024";
   if (!(d->dx > 0) || !(d->dy > 0) || !(d->k0 > 0) || !(d->n0 > 0) || !(d->dz > 0)) return "dx, dy, k0, n0, dz must be > 0";
   if (d->npoles < 1 || d->npoles > HP_MAXPOLES - 4) return "npoles must be in [1, 60]";
@@ -177,16 +179,17 @@ std::string validate(const hp_plan_desc* d) {
 void layout(hp_plan p, Ws& w) {
   const hp_plan_desc& d = p->d;
   const size_t es = p->mixed ? sizeof(c64) : sizeof(c128);
+  const size_t cs = (p->mixed && !p->mixed64) ? sizeof(c64) : sizeof(c128);  // transform arithmetic
   const size_t fn = p->fieldn;
   const int K = d.npoles, M = d.restart;
   p->mu_x = w.take<double>(d.nx);
   p->mu_y = w.take<double>(d.ny);
-  p->tw_x = w.take<char>((d.nx + d.nx / 2 + 1) * es);
-  p->tw_y = w.take<char>((d.ny + d.ny / 2 + 1) * es);
+  p->tw_x = w.take<char>((d.nx + d.nx / 2 + 1) * cs);
+  p->tw_y = w.take<char>((d.ny + d.ny / 2 + 1) * cs);
   p->tw64_x = w.take<c128>(d.nx + d.nx / 2 + 1);
   p->coef = w.take<double>((d.ncomp == 2 ? 6 : 1) * p->geo.fsz);
   p->coef_scratch = w.take<double>((d.ncomp == 2 ? 2 : 1) * p->geo.fsz);
-  p->coef_f = w.take<float>(p->mixed ? (d.ncomp == 2 ? 6 : 1) * p->geo.fsz : 1);
+  p->coef_f = w.take<float>((p->mixed && !p->mixed64) ? (d.ncomp == 2 ? 6 : 1) * p->geo.fsz : 1);
   p->U = w.take<char>((size_t)K * (M + 1) * fn * es);
   p->Z = w.take<char>((size_t)K * M * fn * es);
   p->P = w.take<char>((size_t)K * fn * es);
@@ -210,7 +213,8 @@ void layout(hp_plan p, Ws& w) {
 
 void derive(hp_plan p) {
   const hp_plan_desc& d = p->d;
-  p->mixed = d.precision == HP_MIXED;
+  p->mixed = d.precision == HP_MIXED || d.precision == HP_MIXED64;
+  p->mixed64 = d.precision == HP_MIXED64;
   p->geo.nx = d.nx;
   p->geo.ny = d.ny;
   p->geo.ncomp = d.ncomp;
@@ -264,17 +268,17 @@ std::complex<double> rat(hp_plan p, double z) {
   return r;
 }
 
-template <typename T>
+template <typename C>
 int upload_tables(hp_plan p) {
   const hp_plan_desc& d = p->d;
   const double s = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
   auto mx = mu_table(d.nx, d.dx, p->c2, s), my = mu_table(d.ny, d.dy, p->c2, s);
   HPCHK(hipMemcpy(p->mu_x, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->mu_y, my.data(), my.size() * sizeof(double), hipMemcpyHostToDevice));
-  auto tx = twiddles<T>(d.nx), ty = twiddles<T>(d.ny);
+  auto tx = twiddles<C>(d.nx), ty = twiddles<C>(d.ny);
   auto t64 = twiddles<double>(d.nx);
-  HPCHK(hipMemcpy(p->tw_x, tx.data(), tx.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
-  HPCHK(hipMemcpy(p->tw_y, ty.data(), ty.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->tw_x, tx.data(), tx.size() * sizeof(cx<C>), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->tw_y, ty.data(), ty.size() * sizeof(cx<C>), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->tw64_x, t64.data(), t64.size() * sizeof(c128), hipMemcpyHostToDevice));
   return HP_OK;
 }
@@ -343,14 +347,24 @@ int true_residual(hp_plan p, int k, const c128* w, double* res) {
   return HP_OK;
 }
 
+// Cycle tolerance relative to the cycle's starting residual: complex64
+// transforms stop each cycle at 1e-5 (the FP64 true residual then restarts
+// the solve); with FP64 transforms a cycle runs to tol like FP64 mode.
+double inner_rtol(hp_plan p) { return (p->mixed && !p->mixed64) ? kInnerRtolMixed : 0.0; }
+
+// Call fn<storage, compute> for the plan's precision.
+#define HP_BY_PRECISION(p, fn, ...)                                                                   \
+  ((p)->mixed ? ((p)->mixed64 ? fn<float, double>(__VA_ARGS__) : fn<float, float>(__VA_ARGS__)) \
+              : fn<double, double>(__VA_ARGS__))
+
 // Start a new cycle for pole k from the residual r (physical complex128; tmp2 by default).
-template <typename T>
+template <typename T, typename C>
 int restart_pole(hp_plan p, int k, const c128* r = nullptr) {
   const size_t fn = p->fieldn;
   cx<T>* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
   {
     Prof pr(p, HP_K_ROW_FWD, (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
-    launch_row_fwd<T>(r ? r : p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo,
+    launch_row_fwd<T, C>(r ? r : p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo,
                       p->stream);
   }
   if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)u0) {
@@ -362,8 +376,8 @@ int restart_pole(hp_plan p, int k, const c128* r = nullptr) {
   int* slot_d = p->active_d + 3 * HP_MAXPOLES - 1;
   *slot_h = k;
   HPCHK(hipMemcpyAsync(slot_d, slot_h, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, slot_d, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol,
-                    p->mixed ? kInnerRtolMixed : 0.0, p->stream);
+  launch_cycle_init(p->st, slot_d, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol, inner_rtol(p),
+                    p->stream);
   return HP_OK;
 }
 
@@ -398,7 +412,7 @@ int ensure_guess_buffers(hp_plan p) {
 // them, one synchronisation, then every pole with ||r0|| < ||w|| starts its
 // first cycle from r0 with X_k as the solution so far (done[j]: already within
 // tol, no Arnoldi step); the others keep the zero start.  acc[j] = 1 when used.
-template <typename T>
+template <typename T, typename C>
 int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, const c128* const* x0,
                        const int* st_first, std::vector<int>& acc, std::vector<char>& done,
                        std::vector<double>& rel) {
@@ -439,20 +453,20 @@ int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, c
       done[j] = 1;
       continue;
     }
-    rc = restart_pole<T>(p, k, p->guess_r + (size_t)j * fn);
+    rc = restart_pole<T, C>(p, k, p->guess_r + (size_t)j * fn);
     if (rc) return rc;
   }
   return HP_OK;
 }
 
-template <typename T>
+template <typename T, typename C>
 int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* noconv_out,
               const c128* const* x0 = nullptr, bool use_prev = false) {
   const hp_plan_desc& d = p->d;
   const size_t fn = p->fieldn;
   const int K = d.npoles, M = d.restart;
-  const cx<T>* twx = reinterpret_cast<const cx<T>*>(p->tw_x);
-  const cx<T>* twy = reinterpret_cast<const cx<T>*>(p->tw_y);
+  const cx<C>* twx = reinterpret_cast<const cx<C>*>(p->tw_x);
+  const cx<C>* twy = reinterpret_cast<const cx<C>*>(p->tw_y);
   cx<T>* bR = reinterpret_cast<cx<T>*>(p->bR);
   const double es = (double)sizeof(cx<T>);
   const double U1 = (double)(d.nx - 1) * (d.ny - 1) * d.ncomp;  // unknowns of one field
@@ -461,7 +475,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   // shared first Krylov vector: S_x w (every pole's right-hand side is w)
   {
     Prof pr(p, HP_K_ROW_FWD, U1 * (16.0 + es));
-    launch_row_fwd<T>(w, bR, p->part_misc, twx, p->geo, p->stream);
+    launch_row_fwd<T, C>(w, bR, p->part_misc, twx, p->geo, p->stream);
   }
   bool changed = false;
   for (int k : subset) {
@@ -480,8 +494,8 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   HPCHK(hipMemcpyAsync(p->active_d, act0, ns * sizeof(int), hipMemcpyHostToDevice, p->stream));
   // device copies of the iteration lists (slot 0 shares its storage with the initial list)
   std::vector<int> uploaded[2] = {subset, {}};
-  launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol,
-                    p->mixed ? kInnerRtolMixed : 0.0, p->stream);
+  launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol, inner_rtol(p),
+                    p->stream);
   std::vector<char> live(K, 0);
   for (int k : subset) live[k] = 1;
   std::vector<long> since(K, 0);  // iteration at which the pole's current cycle started
@@ -517,7 +531,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       std::vector<int> acc;
       std::vector<char> done;
       std::vector<double> rel;
-      int rc = start_from_guesses<T>(p, cand, w, gx.data(), &subset[0], acc, done, rel);
+      int rc = start_from_guesses<T, C>(p, cand, w, gx.data(), &subset[0], acc, done, rel);
       if (rc) return rc;
       for (size_t j = 0; j < cand.size(); ++j) {
         p->accepted[cand[j]] = acc[j];
@@ -550,13 +564,14 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     {
       const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
       Prof pr(p, HP_K_COL, U1 * es * (na + outs));
-      launch_col<T>(up, Zb, zsp, zsi, DZb, dzsp, p->st, ad, na, false, p->mu_x, p->mu_y, twy, p->geo, p->sc,
+      launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, ad, na, false, p->mu_x, p->mu_y, twy, p->geo, p->sc,
                     p->stream);
     }
     {
       const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
       Prof pr(p, HP_K_ROW_APPLY, U1 * es * per_pole + (U1 / d.ncomp) * 8.0 * planes);
-      launch_row_apply<T>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<T>(p), p->st, ad, na, p->part_dots, twx, p->geo,
+      launch_row_apply<T, C>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<C>(p), p->st, ad, na, p->part_dots, twx,
+                             p->geo,
                           p->sc, p->stream);
     }
     {
@@ -635,7 +650,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
         noconv = true;
         continue;
       }
-      rc = restart_pole<T>(p, k);
+      rc = restart_pole<T, C>(p, k);
       if (rc) return rc;
       live[k] = 1;
       since[k] = next_iter;
@@ -647,7 +662,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   return HP_OK;
 }
 
-template <typename T>
+template <typename T, typename C>
 int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullptr) {
   const hp_plan_desc& d = p->d;
   const int K = d.npoles;
@@ -655,7 +670,7 @@ int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullpt
   for (int k = 0; k < K; ++k) all[k] = k;
   bool noconv = false;
   const bool use_prev = !x0 && p->guess_mode == HP_GUESS_PREV && p->prev_valid;
-  int rc = run_poles<T>(p, w, all, &noconv, x0, use_prev);
+  int rc = run_poles<T, C>(p, w, all, &noconv, x0, use_prev);
   if (rc) return rc;
   {
     const double es = (double)sizeof(cx<T>);
@@ -676,10 +691,10 @@ int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullpt
 }
 
 // One shifted solve (Zbar - b_k I) x = rhs; x physical complex128.
-template <typename T>
+template <typename T, typename C>
 int run_solve(hp_plan p, int k, const c128* rhs, c128* x) {
   bool noconv = false;
-  int rc = run_poles<T>(p, rhs, std::vector<int>{k}, &noconv);
+  int rc = run_poles<T, C>(p, rhs, std::vector<int>{k}, &noconv);
   if (rc) return rc;
   fold<T>(p, k);
   launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
@@ -698,7 +713,7 @@ int get_solution(hp_plan p, int k, c128* x) {
   return HP_OK;
 }
 
-template <typename T>
+template <typename T, typename C>
 int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
   PoleState h;
   memset(&h, 0, sizeof(h));
@@ -710,14 +725,14 @@ int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
   HPCHK(hipMemcpyAsync(p->st_scratch, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(p->uptr_scratch, tbl, sizeof(tbl), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(p->active_d + 3 * HP_MAXPOLES - 2, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_row_fwd<T>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<T>*>(p->tw_x),
+  launch_row_fwd<T, C>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<C>*>(p->tw_x),
                     p->geo, p->stream);
   // the first basis slot of pole 0 in Z serves as output; the DZ slot as scratch
   cx<T>* zout = reinterpret_cast<cx<T>*>(p->P);
-  launch_col<T>(reinterpret_cast<const cx<T>* const*>(p->uptr_scratch), zout, 0, 0, reinterpret_cast<cx<T>*>(p->DZ), 0,
+  launch_col<T, C>(reinterpret_cast<const cx<T>* const*>(p->uptr_scratch), zout, 0, 0, reinterpret_cast<cx<T>*>(p->DZ), 0,
                 p->st_scratch, p->active_d + 3 * HP_MAXPOLES - 2, 1, false, p->mu_x, p->mu_y,
-                reinterpret_cast<const cx<T>*>(p->tw_y), p->geo, p->sc, p->stream);
-  launch_row_inv<T>(zout, y, reinterpret_cast<const cx<T>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
+                reinterpret_cast<const cx<C>*>(p->tw_y), p->geo, p->sc, p->stream);
+  launch_row_inv<T, C>(zout, y, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
   HPCHK(hipStreamSynchronize(p->stream));
   return HP_OK;
 }
@@ -776,7 +791,7 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
     }
   }
   // kappa(M_k) <= max |lambda - b_k| / dist(b_k, [lo, hi]) over the free-space spectrum
-  const double eps = desc->precision == HP_MIXED ? 6e-8 : 1.1e-16;
+  const double eps = desc->precision != HP_FP64 ? 6e-8 : 1.1e-16;  // complex64 storage rounds every vector
   p->incons.assign(desc->npoles, 0.0);
   for (int k = 0; k < desc->npoles; ++k) {
     const std::complex<double> b(p->poles[k].re, p->poles[k].im);
@@ -821,7 +836,7 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
     hp_plan_destroy(p);
     return fail(nullptr, HP_ENOMEM, "pinned host allocation failed");
   }
-  int rc = p->mixed ? upload_tables<float>(p) : upload_tables<double>(p);
+  int rc = (p->mixed && !p->mixed64) ? upload_tables<float>(p) : upload_tables<double>(p);
   if (rc) {
     g_thread_error = p->err;
     hp_plan_destroy(p);
@@ -857,7 +872,8 @@ int hp_set_medium(hp_plan p, const double* n2) {
   if (!n2) return fail(p, HP_EINVAL, "n2 is NULL");
   const double s = 1.0 / ((p->d.k0 * p->d.n0) * (p->d.k0 * p->d.n0));
   launch_coef(n2, p->coef, p->coef_scratch, p->d.n0, s, p->d.edge_width, p->sc, p->geo, p->stream);
-  if (p->mixed) launch_to_float(p->coef, p->coef_f, (p->d.ncomp == 2 ? 6 : 1) * p->geo.fsz, p->stream);
+  if (p->mixed && !p->mixed64)
+    launch_to_float(p->coef, p->coef_f, (p->d.ncomp == 2 ? 6 : 1) * p->geo.fsz, p->stream);
   HPCHK(hipGetLastError());
   p->medium_set = true;
   return HP_OK;
@@ -873,7 +889,7 @@ int hp_step(hp_plan p, const void* E_in, const double* n2, void* E_out) {
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
   const c128* w = reinterpret_cast<const c128*>(E_in);
   c128* out = reinterpret_cast<c128*>(E_out);
-  return p->mixed ? run_step<float>(p, w, out) : run_step<double>(p, w, out);
+  return HP_BY_PRECISION(p, run_step, p, w, out);
 }
 
 int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* const* x0, int* accepted,
@@ -891,7 +907,7 @@ int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* con
   if (x0)
     for (int k = 0; k < p->d.npoles; ++k) g[k] = reinterpret_cast<const c128*>(x0[k]);
   const c128* const* gp = x0 ? g.data() : nullptr;
-  int rc = p->mixed ? run_step<float>(p, w, out, gp) : run_step<double>(p, w, out, gp);
+  int rc = HP_BY_PRECISION(p, run_step, p, w, out, gp);
   if (rc >= 0 && accepted)
     for (int k = 0; k < p->d.npoles; ++k) accepted[k] = p->accepted[k];
   return rc;
@@ -930,7 +946,7 @@ int hp_solve(hp_plan p, int pole, const void* rhs, void* x) {
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
   const c128* r = reinterpret_cast<const c128*>(rhs);
   c128* o = reinterpret_cast<c128*>(x);
-  return p->mixed ? run_solve<float>(p, pole, r, o) : run_solve<double>(p, pole, r, o);
+  return HP_BY_PRECISION(p, run_solve, p, pole, r, o);
 }
 
 int hp_propagate(hp_plan p, const void* E_in, const double* n2, long n2_step_stride, int nsteps, void* E_out) {
@@ -1000,7 +1016,7 @@ int hp_apply_preconditioner(hp_plan p, int pole, const void* x, void* y) {
   if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
   const c128* xx = reinterpret_cast<const c128*>(x);
   c128* yy = reinterpret_cast<c128*>(y);
-  return p->mixed ? apply_prec<float>(p, pole, xx, yy) : apply_prec<double>(p, pole, xx, yy);
+  return HP_BY_PRECISION(p, apply_prec, p, pole, xx, yy);
 }
 
 int hp_profile(hp_plan p, int enable) {

@@ -66,11 +66,11 @@ struct RowCfg {
 
 constexpr int kColLdsBytes = 40960;  // several column workgroups per CU
 
-template <typename T, int N>
+template <typename T, typename C, int N>
 struct ColCfg {
   static constexpr int TW = Tile<T>::W;
   static constexpr int NT = N / 8;
-  static constexpr int PB = plen(N) * (int)sizeof(cx<T>);
+  static constexpr int PB = plen(N) * (int)sizeof(cx<C>);
   static constexpr int G0 = kColLdsBytes / PB;
   static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
   static constexpr int G2 = (G1 * NT > 1024) ? 1024 / NT : G1;
@@ -82,7 +82,7 @@ struct ColCfg {
   // LDS stride between the GC column buffers: plen(N) (a multiple of 256 bytes
   // for the sizes used) plus 256/GC bytes, so that neighbouring threads, which
   // alternate columns in the load, divide and store loops, hit different banks
-  static constexpr int SHIFT = (256 / GC) / (int)sizeof(cx<T>) > 0 ? (256 / GC) / (int)sizeof(cx<T>) : 1;
+  static constexpr int SHIFT = (256 / GC) / (int)sizeof(cx<C>) > 0 ? (256 / GC) / (int)sizeof(cx<C>) : 1;
   static constexpr int PLC = plen(N) + SHIFT;
 };
 
@@ -122,42 +122,42 @@ __device__ __forceinline__ double edge_loss(int i, int j, int nx, int ny, int W,
 
 // ------------------------------------------------------------------ row forward (physical -> R-domain)
 
-template <typename T, int N, int TW>
+template <typename T, typename C, int N, int TW>
 __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
-                                                           double* __restrict__ part, const cx<T>* __restrict__ tw,
+                                                           double* __restrict__ part, const cx<C>* __restrict__ tw,
                                                            int ny, size_t fsz, int nblk) {
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT;
-  __shared__ cx<T> lds[RPW * plen(N)];
-  __shared__ cx<T> scr[RPW * RC::SCR];
+  __shared__ cx<C> lds[RPW * plen(N)];
+  __shared__ cx<C> scr[RPW * RC::SCR];
   __shared__ double red[(WG + 63) / 64];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = 1 + blockIdx.x * RPW + g;
   const int comp = blockIdx.y;
   const bool valid = row < ny;
-  cx<T>* buf = lds + g * plen(N);
+  cx<C>* buf = lds + g * plen(N);
   const c128* src = in + comp * fsz + (size_t)row * N;
   double nrm = 0.0;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int m = t + s * NT;
-    cx<T> v = czero<T>();
+    cx<C> v = czero<C>();
     if (valid && m > 0) {
       const c128 a = src[m];
       nrm += abs2(a);
-      v = cvt<T>(a);
+      v = cvt<C>(a);
     }
     buf[pidx(m)] = v;
   }
   __syncthreads();
-  dst1<T, N>(buf, tw, scr + g * RC::SCR, t);
-  const T scale = (T)sqrt(2.0 / N);
+  dst1<C, N>(buf, tw, scr + g * RC::SCR, t);
+  const C scale = (C)sqrt(2.0 / N);
   if (valid) {
     cx<T>* dst = out + comp * fsz;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int p = t + s * NT;
-      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : dst_val(buf, p, scale);
+      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : cvt<T>(dst_val(buf, p, scale));
     }
   }
   double sum = block_sum<WG>(nrm, red);
@@ -166,27 +166,27 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restric
 
 // ------------------------------------------------------------------ row inverse (R-domain -> physical complex128)
 
-template <typename T, int N, int TW>
+template <typename T, typename C, int N, int TW>
 __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restrict__ in, c128* __restrict__ out,
-                                                           const cx<T>* __restrict__ tw, int ny, size_t fsz) {
+                                                           const cx<C>* __restrict__ tw, int ny, size_t fsz) {
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT;
-  __shared__ cx<T> lds[RPW * plen(N)];
-  __shared__ cx<T> scr[RPW * RC::SCR];
+  __shared__ cx<C> lds[RPW * plen(N)];
+  __shared__ cx<C> scr[RPW * RC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // all rows, row 0 -> zeros
   const int comp = blockIdx.y;
   const bool valid = row < ny && row > 0;
-  cx<T>* buf = lds + g * plen(N);
+  cx<C>* buf = lds + g * plen(N);
   const cx<T>* src = in + comp * fsz;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int m = t + s * NT;
-    buf[pidx(m)] = (valid && m > 0) ? src[tix<TW>(row, m, ny)] : czero<T>();
+    buf[pidx(m)] = (valid && m > 0) ? cvt<C>(src[tix<TW>(row, m, ny)]) : czero<C>();
   }
   __syncthreads();
-  dst1<T, N>(buf, tw, scr + g * RC::SCR, t);
-  const T scale = (T)sqrt(2.0 / N);
+  dst1<C, N>(buf, tw, scr + g * RC::SCR, t);
+  const C scale = (C)sqrt(2.0 / N);
   if (row < ny) {
     c128* dst = out + comp * fsz + (size_t)row * N;
 #pragma unroll
@@ -218,24 +218,24 @@ __device__ __forceinline__ void col_block(int bid, int ntiles, int S, int& tile,
 
 // Waves per SIMD for the column pass (as for the row pass: the most that
 // compile without spilling).
-template <typename T, int N>
+template <typename C, int N>
 struct ColWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
   static constexpr int V = (N <= 1024 && POW2) ? 4 : 2;
 };
 
-template <typename T, int N, int NC>
-__global__ __launch_bounds__((ColCfg<T, N>::WG), (ColWaves<T, N>::V)) void k_col(
+template <typename T, typename C, int N, int NC>
+__global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_col(
     const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
     cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const int* __restrict__ active,
-    const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<T>* __restrict__ tw, size_t fsz,
+    const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<C>* __restrict__ tw, size_t fsz,
     StencilCoef sc) {
-  using CC = ColCfg<T, N>;
+  using CC = ColCfg<T, C, N>;
   constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
   constexpr int PL = CC::PLC;  // padded per-column stride
   constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
-  __shared__ cx<T> lds[GC * PL];
-  __shared__ cx<T> scr[GC * CC::SCR];
+  __shared__ cx<C> lds[GC * PL];
+  __shared__ cx<C> scr[GC * CC::SCR];
   int tile, sub;
   col_block(blockIdx.x, gridDim.x / S, S, tile, sub);
   const int col0 = tile * TW;
@@ -243,12 +243,12 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG), (ColWaves<T, N>::V)) void k_col
   const int comp = blockIdx.y % NC;
   const int tid = threadIdx.x;
   const int g = tid / NT, t = tid % NT;
-  const T scale = (T)sqrt(2.0 / N);
+  const C scale = (C)sqrt(2.0 / N);
   const int k = active[blockIdx.y / NC];
   if (st[k].flag) return;
   const int m = st[k].m;
   const c128 b = st[k].bk;
-  const T sc2 = (T)st[k].sigma[m] * scale;
+  const C sc2 = (C)st[k].sigma[m] * scale;
   const size_t tbase = comp * fsz + (size_t)tile * N * TW;  // this tile, component comp (ny == N)
   const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
   cx<T>* z = zbase + k * zsp + m * zsi + tbase;
@@ -256,34 +256,34 @@ __global__ __launch_bounds__((ColCfg<T, N>::WG), (ColWaves<T, N>::V)) void k_col
   {
     for (int e = tid; e < NE; e += WG) {
       const int r = 1 + e / GC, c = e % GC;
-      lds[c * PL + pidx(r)] = u[(size_t)r * TW + c0 + c];
+      lds[c * PL + pidx(r)] = cvt<C>(u[(size_t)r * TW + c0 + c]);
     }
-    if (tid < GC) lds[tid * PL + pidx(0)] = czero<T>();
+    if (tid < GC) lds[tid * PL + pidx(0)] = czero<C>();
     __syncthreads();
-    dst1<T, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
     // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
     for (int e = tid; e < NE; e += WG) {
       const int p = 1 + e / GC, c = e % GC, q = col0 + c0 + c;
-      cx<T>* bc = lds + c * PL;
-      const cx<T> X = dst_val(bc, p, scale);
+      cx<C>* bc = lds + c * PL;
+      const cx<C> X = dst_val(bc, p, scale);
       const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
       const double den = lr * lr + li * li;
-      bc[pidx(p)] = X * mk<T>((T)(lr / den), (T)(-li / den));
+      bc[pidx(p)] = X * mk<C>((C)(lr / den), (C)(-li / den));
     }
-    if (tid < GC) lds[tid * PL + pidx(0)] = czero<T>();
+    if (tid < GC) lds[tid * PL + pidx(0)] = czero<C>();
     __syncthreads();
-    dst1<T, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
     for (int e = tid; e < NE; e += WG) {
       const int p = 1 + e / GC, c = e % GC;
-      const cx<T>* bc = lds + c * PL;
-      z[(size_t)p * TW + c0 + c] = sc2 * bc[pidx(p)];
+      const cx<C>* bc = lds + c * PL;
+      z[(size_t)p * TW + c0 + c] = cvt<T>(sc2 * bc[pidx(p)]);
       if constexpr (NC == 2) {
         // D1y of the column, physical in y (odd reflection about rows 0 and N)
         cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
         for (int mm = 1; mm <= 6; ++mm)
           acc = acc + sc.d1y[mm - 1] * cvt<double>(odd_at(bc, N, p + mm) - odd_at(bc, N, p - mm));
-        dz[(size_t)p * TW + c0 + c] = sc2 * cvt<T>(acc);
+        dz[(size_t)p * TW + c0 + c] = cvt<T>(sc2 * cvt<C>(acc));
       }
     }
   }
@@ -306,25 +306,25 @@ struct ApplyCfg {
 // without spilling: scalar fields four (128 VGPRs) for 2^k up to 1024, else
 // three (complex128 at 2048: two); vector fields as many as their registers
 // allow (complex64 one, complex128 two).
-template <typename T, int N, int NC>
+template <typename C, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
-  static constexpr int V = NC == 2 ? (sizeof(T) == 4 ? 1 : 2)
-                                   : ((N <= 1024 && POW2) ? 4 : (sizeof(T) == 4 || N < 2048 ? 3 : 2));
+  static constexpr int V = NC == 2 ? (sizeof(C) == 4 ? 1 : 2)
+                                   : ((N <= 1024 && POW2) ? 4 : (sizeof(C) == 4 || N < 2048 ? 3 : 2));
 };
 
-template <typename T, int N, int NC>
-__global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) void k_row_apply(
+template <typename T, typename C, int N, int NC>
+__global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
-    cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const T* __restrict__ coef,
+    cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const C* __restrict__ coef,
     const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
-    const cx<T>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
+    const cx<C>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
   using AC = ApplyCfg<N, NC>;
   constexpr int NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
   constexpr int PT = N / NT;  // values per thread per row
   constexpr int PL = plen(N);
-  __shared__ cx<T> lds[GROUPS * PL * NC];
-  __shared__ cx<T> scr[GROUPS * AC::SCR];
+  __shared__ cx<C> lds[GROUPS * PL * NC];
+  __shared__ cx<C> scr[GROUPS * AC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int comp = g % NC;
   const int row = 1 + blockIdx.x * ROWS + g / NC;
@@ -332,9 +332,9 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
   const int k = active[blockIdx.y];
   if (st[k].flag) return;
   const int m = st[k].m;
-  cx<T>* buf = lds + g * PL;
-  cx<T>* sg = scr + g * AC::SCR;
-  const T scale = (T)sqrt(2.0 / N);
+  cx<C>* buf = lds + g * PL;
+  cx<C>* sg = scr + g * AC::SCR;
+  const C scale = (C)sqrt(2.0 / N);
   const size_t cbase = comp * fsz;
   const size_t ci0 = (size_t)row * N;  // physical row offset
   const RowWalk<TW, NT> toff(cbase, valid ? row : 0, t, ny);  // tiled offsets of the thread's points
@@ -343,48 +343,48 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    buf[pidx(j)] = (valid && j > 0) ? z[toff.at(s)] : czero<T>();
+    buf[pidx(j)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
   }
   __syncthreads();
-  dst1<T, N>(buf, tw, sg, t);
-  cx<T> pz[PT];  // P z at the thread's points j = t + s * NT
+  dst1<C, N>(buf, tw, sg, t);
+  cx<C> pz[PT];  // P z at the thread's points j = t + s * NT
   if constexpr (NC == 1) {
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      const cx<T> zj = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
-      const T v = valid ? coef[ci0 + j] : (T)0;
+      const cx<C> zj = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
+      const C v = valid ? coef[ci0 + j] : (C)0;
       pz[s] = v * zj;
     }
   } else {
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
-    cx<T>* buf2 = lds + (GROUPS + g) * PL;
-    cx<T> zc[PT], dxz[PT], dyz[PT];
+    cx<C>* buf2 = lds + (GROUPS + g) * PL;
+    cx<C> zc[PT], dxz[PT], dyz[PT];
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      zc[s] = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
+      zc[s] = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
       cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
       for (int mm = 1; mm <= 6; ++mm)
         acc = acc + sc.d1x[mm - 1] * cvt<double>(odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
-      dxz[s] = (j == 0) ? czero<T>() : scale * cvt<T>(acc);
+      dxz[s] = (j == 0) ? czero<C>() : scale * cvt<C>(acc);
     }
     __syncthreads();
     const cx<T>* dz = dzbase + k * dzsp;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      buf[pidx(j)] = (valid && j > 0) ? dz[toff.at(s)] : czero<T>();
+      buf[pidx(j)] = (valid && j > 0) ? cvt<C>(dz[toff.at(s)]) : czero<C>();
     }
     __syncthreads();
-    dst1<T, N>(buf, tw, sg, t);
+    dst1<C, N>(buf, tw, sg, t);
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      dyz[s] = (j == 0) ? czero<T>() : dst_val(buf, j, scale);
+      dyz[s] = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
     }
     __syncthreads();
     // exchange: component 0 needs w2 and D1x w2, component 1 needs w1 and D1y w1
@@ -395,19 +395,19 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
       buf2[pidx(j)] = (comp == 0) ? dyz[s] : dxz[s];
     }
     __syncthreads();
-    const cx<T>* other = lds + (g ^ 1) * PL;
-    const cx<T>* other2 = lds + (GROUPS + (g ^ 1)) * PL;
+    const cx<C>* other = lds + (g ^ 1) * PL;
+    const cx<C>* other2 = lds + (GROUPS + (g ^ 1)) * PL;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
       if (!valid) {
-        pz[s] = czero<T>();
+        pz[s] = czero<C>();
         continue;
       }
       const size_t ci = ci0 + j;
-      const T v = coef[ci], px = coef[fsz + ci], py = coef[2 * fsz + ci];
-      const T pxx = coef[3 * fsz + ci], pyy = coef[4 * fsz + ci], pxy = coef[5 * fsz + ci];
-      const cx<T> zo = other[pidx(j)], dzo = other2[pidx(j)];
+      const C v = coef[ci], px = coef[fsz + ci], py = coef[2 * fsz + ci];
+      const C pxx = coef[3 * fsz + ci], pyy = coef[4 * fsz + ci], pxy = coef[5 * fsz + ci];
+      const cx<C> zo = other[pidx(j)], dzo = other2[pidx(j)];
       if (comp == 0)
         pz[s] = pxx * zc[s] + px * dxz[s] + pxy * zo + py * dzo + v * zc[s];
       else
@@ -419,16 +419,16 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<T, N, NC>::V)) v
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    buf[pidx(j)] = (j == 0) ? czero<T>() : pz[s];
+    buf[pidx(j)] = (j == 0) ? czero<C>() : pz[s];
   }
   __syncthreads();
-  dst1<T, N>(buf, tw, sg, t);
-  cx<T> pv[PT];
+  dst1<C, N>(buf, tw, sg, t);
+  cx<T> pv[PT];  // p as stored: the inner products use exactly what the update reads
   cx<T>* p = pbase + k * psp;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    pv[s] = (j == 0 || !valid) ? czero<T>() : dst_val(buf, j, scale);
+    pv[s] = (j == 0 || !valid) ? czero<T>() : cvt<T>(dst_val(buf, j, scale));
     if (valid) p[toff.at(s)] = pv[s];
   }
   // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
@@ -1139,8 +1139,8 @@ int row_blocks(int nx) {
   return (256 / NT) > 0 ? 256 / NT : 1;  // rows per workgroup
 }
 
-template <typename T>
-void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s,
+template <typename T, typename C>
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<C>* tw, const Geo& g, hipStream_t s,
                     int tile_w) {
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny - 1 + rpw - 1) / rpw;
@@ -1148,43 +1148,43 @@ void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, c
   if (tile_w <= 0) tile_w = tile_width<T>();
 #define L_(NN)                                                                                                    \
   if (tile_w == 8)                                                                                                \
-    hipLaunchKernelGGL((k_row_fwd<T, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,   \
+    hipLaunchKernelGGL((k_row_fwd<T, C, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,   \
                        nblk);                                                                                     \
   else                                                                                                            \
-    hipLaunchKernelGGL((k_row_fwd<T, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,  \
+    hipLaunchKernelGGL((k_row_fwd<T, C, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,  \
                        nblk);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
-template <typename T>
-void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, int tile_w, hipStream_t s) {
+template <typename T, typename C>
+void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s) {
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny + rpw - 1) / rpw;
   dim3 grid(nblk, g.ncomp);
 #define L_(NN)                                                                                                  \
   if (tile_w == 8)                                                                                              \
-    hipLaunchKernelGGL((k_row_inv<T, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
+    hipLaunchKernelGGL((k_row_inv<T, C, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
   else                                                                                                          \
-    hipLaunchKernelGGL((k_row_inv<T, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);
+    hipLaunchKernelGGL((k_row_inv<T, C, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
                 const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
-                const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s) {
+                const double* mu_y, const cx<C>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s) {
   (void)shared;
 #define L_(NN)                                                                                                 \
   {                                                                                                            \
-    dim3 grid(g.nx / ColCfg<T, NN>::GC, g.ncomp * nactive);                                                    \
+    dim3 grid(g.nx / ColCfg<T, C, NN>::GC, g.ncomp * nactive);                                                 \
     if (g.ncomp == 1)                                                                                          \
-      hipLaunchKernelGGL((k_col<T, NN, 1>), grid, dim3(ColCfg<T, NN>::WG), 0, s, uptr, zbase, zsp, zsi, dzbase, \
-                         dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                         \
+      hipLaunchKernelGGL((k_col<T, C, NN, 1>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
+                         dzbase, dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                 \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_col<T, NN, 2>), grid, dim3(ColCfg<T, NN>::WG), 0, s, uptr, zbase, zsp, zsi, dzbase, \
-                         dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                         \
+      hipLaunchKernelGGL((k_col<T, C, NN, 2>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
+                         dzbase, dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                 \
   }
   HP_DISPATCH_N(g.ny, L_)
 #undef L_
@@ -1208,20 +1208,20 @@ int row_apply_parts(const Geo& g) {
   return row_apply_blocks<T>(g) * ((apply_groups(g) * (g.nx / 8) + 63) / 64);
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
-                      size_t psp, const cx<T>* const* uptr, const T* coef, const PoleState* st,
-                      const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
+                      size_t psp, const cx<T>* const* uptr, const C* coef, const PoleState* st,
+                      const int* active, int nactive, double2* part, const cx<C>* tw, const Geo& g,
                       const StencilCoef& sc, hipStream_t s) {
   const int nblk = row_apply_blocks<T>(g);
   const int nparts = row_apply_parts<T>(g);
   dim3 grid(nblk, nactive);
 #define L_(NN)                                                                                                  \
   if (g.ncomp == 1)                                                                                             \
-    hipLaunchKernelGGL((k_row_apply<T, NN, 1>), grid, dim3(ApplyCfg<NN, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
+    hipLaunchKernelGGL((k_row_apply<T, C, NN, 1>), grid, dim3(ApplyCfg<NN, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
                        dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);            \
   else                                                                                                          \
-    hipLaunchKernelGGL((k_row_apply<T, NN, 2>), grid, dim3(ApplyCfg<NN, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
+    hipLaunchKernelGGL((k_row_apply<T, C, NN, 2>), grid, dim3(ApplyCfg<NN, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
                        dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
@@ -1323,14 +1323,6 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   template int row_blocks<T>(int);                                                                                   \
   template int row_apply_blocks<T>(const Geo&);                                                                      \
   template int row_apply_parts<T>(const Geo&);                                                                       \
-  template void launch_row_fwd<T>(const c128*, cx<T>*, double*, const cx<T>*, const Geo&, hipStream_t, int);         \
-  template void launch_row_inv<T>(const cx<T>*, c128*, const cx<T>*, const Geo&, int, hipStream_t);                  \
-  template void launch_col<T>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,         \
-                              const int*, int, bool, const double*, const double*, const cx<T>*, const Geo&,         \
-                              const StencilCoef&, hipStream_t);                                                      \
-  template void launch_row_apply<T>(const cx<T>*, size_t, size_t, const cx<T>*, size_t, cx<T>*, size_t,              \
-                                    const cx<T>* const*, const T*, const PoleState*, const int*, int, double2*, \
-                                    const cx<T>*, const Geo&, const StencilCoef&, hipStream_t);                      \
   template void launch_update<T>(const cx<T>*, size_t, cx<T>* const*, const PoleState*, const int*, int, double*,    \
                                  int, const Geo&, hipStream_t);                                                      \
   template void launch_final<T>(const c128*, c128*, const cx<T>*, size_t, size_t, const c128*, size_t,               \
@@ -1338,5 +1330,19 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
                                 hipStream_t);                                                                        \
   template void launch_accum<T>(c128*, const cx<T>*, size_t, const PoleState*, int, const Geo&, hipStream_t);
 
+// storage type T, compute type C of the transforms
+#define HP_INST2(T, C)                                                                                               \
+  template void launch_row_fwd<T, C>(const c128*, cx<T>*, double*, const cx<C>*, const Geo&, hipStream_t, int);      \
+  template void launch_row_inv<T, C>(const cx<T>*, c128*, const cx<C>*, const Geo&, int, hipStream_t);               \
+  template void launch_col<T, C>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,      \
+                                 const int*, int, bool, const double*, const double*, const cx<C>*, const Geo&,      \
+                                 const StencilCoef&, hipStream_t);                                                   \
+  template void launch_row_apply<T, C>(const cx<T>*, size_t, size_t, const cx<T>*, size_t, cx<T>*, size_t,           \
+                                       const cx<T>* const*, const C*, const PoleState*, const int*, int, double2*,   \
+                                       const cx<C>*, const Geo&, const StencilCoef&, hipStream_t);
+
 HP_INST(double)
 HP_INST(float)
+HP_INST2(double, double)
+HP_INST2(float, float)
+HP_INST2(float, double)

@@ -1,5 +1,7 @@
 // Launch wrappers of the HIP kernels (host side).  Every wrapper only enqueues
-// work on `s`; sizes are validated by the caller (the plan).
+// work on `s`; sizes are validated by the caller (the plan).  T is the storage
+// type of R-domain fields; C (default T) the arithmetic type of the transforms
+// (complex64 storage with FP64 transforms: T = float, C = double).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -19,32 +21,32 @@ struct Geo {
 // Row DST-I of the unknowns of a complex128 field (physical, row-major): out
 // (R-domain, T, column-tiled with tile_w elements per tile row; 0 = the width
 // of T's own layout) and per-block partial sums of |in|^2.
-template <typename T>
-void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<T>* tw, const Geo& g, hipStream_t s,
+template <typename T, typename C = T>
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<C>* tw, const Geo& g, hipStream_t s,
                     int tile_w = 0);
 template <typename T>
 int row_blocks(int nx);
 
 // Row DST-I back to complex128 (out = S_x in); in is column-tiled with tile_w
 // elements per tile row.
-template <typename T>
-void launch_row_inv(const cx<T>* in, c128* out, const cx<T>* tw, const Geo& g, int tile_w, hipStream_t s);
+template <typename T, typename C = T>
+void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s);
 
 // Column pass: z = sigma_m * S_y diag(1/(mu_y + mu_x - b_k)) S_y u_m for the
 // active poles.  shared: every pole reads the same u (the step's S_x w).
 // Vector fields also get dz = D1y z (the y derivative the row pass needs).
-template <typename T>
+template <typename T, typename C = T>
 void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
                 const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
-                const double* mu_y, const cx<T>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s);
+                const double* mu_y, const cx<C>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s);
 
 // Row pass: p = S_x (P (S_x z_m)) with P the medium part of Zbar, plus the
 // partial inner products <u_i, p>, i = 0..m.  coef: the coefficient planes in
 // the working precision.
-template <typename T>
+template <typename T, typename C = T>
 void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* dzbase, size_t dzsp, cx<T>* pbase,
-                      size_t psp, const cx<T>* const* uptr, const T* coef, const PoleState* st,
-                      const int* active, int nactive, double2* part, const cx<T>* tw, const Geo& g,
+                      size_t psp, const cx<T>* const* uptr, const C* coef, const PoleState* st,
+                      const int* active, int nactive, double2* part, const cx<C>* tw, const Geo& g,
                       const StencilCoef& sc, hipStream_t s);
 template <typename T>
 int row_apply_blocks(const Geo& g);

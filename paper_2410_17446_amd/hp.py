@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhp.so")
 _lib = None
 
 HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
-HP_FP64, HP_MIXED = 0, 1
+HP_FP64, HP_MIXED, HP_MIXED64 = 0, 1, 2
 HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",

@@ -45,7 +45,7 @@ def test_operator_matches_oracle(ncomp, pole):
     assert rel_l2(y.cpu().numpy(), ref) < 1e-13
 
 
-@pytest.mark.parametrize("N,precision", [(64, 0), (128, 0), (512, 0), (64, 1), (256, 1)])
+@pytest.mark.parametrize("N,precision", [(64, 0), (128, 0), (512, 0), (64, 1), (256, 1), (64, 2), (256, 2)])
 def test_preconditioner_matches_oracle(N, precision):
     """M_k^-1 by DST-I: rounding is amplified by kappa_k = max|mu - b_k| / min|mu - b_k|, so the
     bound is 20 eps kappa_k (eps of the working precision)."""
@@ -167,6 +167,22 @@ def test_mixed_precision_step():
     _, rr = plan.stats()
     assert max(rr) <= 1e-8
     assert rel_l2(out.cpu().numpy(), ref) < 1e-6
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_mixed64_step(ncomp):
+    """complex64 storage, FP64 transforms: every solve meets tol by the FP64 true residual and
+    the field agrees with the oracle to ~tol (1e-7)."""
+    torch = _cuda()
+    wl = workload(N=128, ncomp=ncomp, W=16, tol=1e-9, npoles=12, medium=("sine", 0.02, 1.0), w0=8.0)
+    if ncomp == 2:
+        wl["n2"] = inputs.grf_n2(128, 0.25, 0.01, 2.0, seed=9)
+    ref, _ = _oracle_step(wl)
+    plan = gpu_plan(wl, precision=2)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    _, rr = plan.stats()
+    assert max(rr) <= 1e-9
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-7
 
 
 def test_non_square_grid():
