@@ -304,12 +304,13 @@ struct ApplyCfg {
 
 // Waves per SIMD the register allocation must allow, the most that compile
 // without spilling: scalar fields four (128 VGPRs) for 2^k up to 1024, else
-// three (complex128 at 2048: two); vector fields as many as their registers
-// allow (complex64 one, complex128 two).
+// three (complex128 at 2048: two); vector fields complex128 two, complex64
+// three, and four at 2048, where a workgroup is 512 threads and only four
+// waves per SIMD fit two of them per CU (at the cost of a 24-byte spill).
 template <typename C, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
-  static constexpr int V = NC == 2 ? (sizeof(C) == 4 ? 1 : 2)
+  static constexpr int V = NC == 2 ? (sizeof(C) == 4 ? (N >= 2048 ? 4 : 3) : 2)
                                    : ((N <= 1024 && POW2) ? 4 : (sizeof(C) == 4 || N < 2048 ? 3 : 2));
 };
 
@@ -360,19 +361,40 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
-    cx<C>* buf2 = lds + (GROUPS + g) * PL;
-    cx<C> zc[PT], dxz[PT], dyz[PT];
+    // Component 0 needs w2 and D1x w2 from its partner, component 1 needs w1
+    // and D1y w1; each group reads the partner's transform buffer directly, so
+    // only P z stays in registers.  D1x w2 goes through the exchange buffer.
+    cx<C>* xb = lds + (GROUPS + g) * PL;
+    const cx<C>* ob = lds + (g ^ 1) * PL;
+    const cx<C>* oxb = lds + (GROUPS + (g ^ 1)) * PL;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      zc[s] = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
-      cx<double> acc = mk(0.0, 0.0);
+      pz[s] = czero<C>();
+      if (!valid || j == 0) continue;
+      const size_t ci = ci0 + j;
+      const cx<C> zc = dst_val(buf, j, scale), zo = dst_val(ob, j, scale);
+      cx<C> acc = czero<C>();
 #pragma unroll
-      for (int mm = 1; mm <= 6; ++mm)
-        acc = acc + sc.d1x[mm - 1] * cvt<double>(odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
-      dxz[s] = (j == 0) ? czero<C>() : scale * cvt<C>(acc);
+      for (int mm = 1; mm <= 6; ++mm) acc = acc + (C)sc.d1x[mm - 1] * (odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
+      const cx<C> dx = scale * acc;
+      const C v = coef[ci], pxy = coef[5 * fsz + ci];
+      if (comp == 0) {
+        pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * dx + pxy * zo;
+      } else {
+        pz[s] = (coef[4 * fsz + ci] + v) * zc + pxy * zo;
+        xb[pidx(j)] = dx;
+      }
     }
     __syncthreads();
+    if (comp == 0 && valid) {
+#pragma unroll
+      for (int s = 0; s < PT; ++s) {
+        const int j = t + s * NT;
+        if (j > 0) pz[s] = pz[s] + coef[2 * fsz + ci0 + j] * oxb[pidx(j)];
+      }
+    }
+    // D1y of both components (the column pass's second output), row-transformed
     const cx<T>* dz = dzbase + k * dzsp;
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
@@ -381,37 +403,14 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     }
     __syncthreads();
     dst1<C, N>(buf, tw, sg, t);
+    if (comp == 1 && valid) {
 #pragma unroll
-    for (int s = 0; s < PT; ++s) {
-      const int j = t + s * NT;
-      dyz[s] = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
-    }
-    __syncthreads();
-    // exchange: component 0 needs w2 and D1x w2, component 1 needs w1 and D1y w1
-#pragma unroll
-    for (int s = 0; s < PT; ++s) {
-      const int j = t + s * NT;
-      buf[pidx(j)] = zc[s];
-      buf2[pidx(j)] = (comp == 0) ? dyz[s] : dxz[s];
-    }
-    __syncthreads();
-    const cx<C>* other = lds + (g ^ 1) * PL;
-    const cx<C>* other2 = lds + (GROUPS + (g ^ 1)) * PL;
-#pragma unroll
-    for (int s = 0; s < PT; ++s) {
-      const int j = t + s * NT;
-      if (!valid) {
-        pz[s] = czero<C>();
-        continue;
+      for (int s = 0; s < PT; ++s) {
+        const int j = t + s * NT;
+        if (j == 0) continue;
+        const size_t ci = ci0 + j;
+        pz[s] = pz[s] + coef[2 * fsz + ci] * dst_val(buf, j, scale) + coef[fsz + ci] * dst_val(ob, j, scale);
       }
-      const size_t ci = ci0 + j;
-      const C v = coef[ci], px = coef[fsz + ci], py = coef[2 * fsz + ci];
-      const C pxx = coef[3 * fsz + ci], pyy = coef[4 * fsz + ci], pxy = coef[5 * fsz + ci];
-      const cx<C> zo = other[pidx(j)], dzo = other2[pidx(j)];
-      if (comp == 0)
-        pz[s] = pxx * zc[s] + px * dxz[s] + pxy * zo + py * dzo + v * zc[s];
-      else
-        pz[s] = pxy * zo + px * dzo + pyy * zc[s] + py * dyz[s] + v * zc[s];
     }
     __syncthreads();
   }
