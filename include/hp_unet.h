@@ -53,12 +53,14 @@ typedef struct hp_unet_s* hp_unet;
 int hp_unet_create(int levels, int base, int cin, int cout, unsigned long long seed, void* stream, hp_unet* out);
 long hp_unet_num_params(hp_unet net);
 
-/* Arithmetic of the 3x3 convolutions (forward and data gradient):
- * HP_UNET_F32 (default): float32 direct convolution on the vector ALUs;
- * HP_UNET_BF16: implicit GEMM on the matrix cores (v_mfma_f32_16x16x32_bf16),
- * activations and weights rounded to bf16 as they are staged, float32
- * accumulation.  Parameters, the other layers, the weight gradients and Adam
- * stay float32 in both. */
+/* Arithmetic of the 3x3 convolutions (forward, data gradient and weight
+ * gradient): HP_UNET_F32 (default): float32 direct convolution on the vector
+ * ALUs; HP_UNET_BF16: implicit GEMMs on the matrix cores
+ * (v_mfma_f32_16x16x32_bf16) with operands rounded to bf16 as they are staged
+ * and float32 accumulation (the weight gradient contracts over pixels in
+ * fixed splits summed in a fixed order, so repeated calls give identical
+ * results).  Parameters, the 1x1 output layer, bias gradients and Adam stay
+ * float32 in both. */
 enum { HP_UNET_F32 = 0, HP_UNET_BF16 = 1 };
 int hp_unet_set_precision(hp_unet net, int precision);
 

@@ -256,6 +256,169 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const float* __restrict__ x
   }
 }
 
+// Weight gradient on the matrix cores.  The contraction runs over pixels: one
+// v_mfma_f32_16x16x32_bf16 takes 32 pixels of one image row (lane group kg
+// holds the 8 consecutive pixels 8 kg .. 8 kg + 7 of the segment) for 16 output
+// channels (A = dy, row = lane % 16) against 16 input channels (B = x moved by
+// the tap, column = lane % 16).  A workgroup owns 32 output x 16 input
+// channels and a contiguous share of the row segments; its four waves take
+// every fourth segment (the next one's operands loaded while the current one
+// is multiplied), sum through LDS in wave order, and the workgroup writes
+// part[split][co][ci][tap]; workgroups of the first input-channel block also
+// sum dy for the bias gradient into part[split][cout * cin * 9 + co].
+// k_wgrad_sum adds the splits in a fixed order, so the result does not depend
+// on scheduling.
+namespace wgm {
+constexpr int CO = 32, CI = 16, SEG = 32;
+constexpr int SUM_WAVES = 16;  // waves per output chunk in k_wgrad_sum
+}
+
+// v[j] = p[j] for j < valid, else 0; vec: p is 16-byte aligned (two float4 loads when valid >= 8)
+__device__ __forceinline__ void ld8(const float* __restrict__ p, int vec, int valid, float* v) {
+  if (vec && valid >= 8) {
+    const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < valid ? p[j] : 0.f;
+  }
+}
+
+// Operands of one row segment as loaded: dy of the lane's two output channels
+// (8 pixels each) and x of its input channel on the three rows around, pixels
+// px - 1 .. px + 8.
+struct WgSeg {
+  float a[2][8];
+  float b[3][10];
+};
+
+__device__ __forceinline__ void wg_load(WgSeg& g, const float* __restrict__ x, const float* __restrict__ dy, long q,
+                                        int ws, int B, int cin, int cout, int H, int W, int co0, int ci, int l16, int kg,
+                                        int vec) {
+  const size_t plane = (size_t)H * W;
+  const int xs = (int)(q % ws);
+  const long r = q / ws;
+  const int yy = (int)(r % H), b = (int)(r / H);
+  const int px = xs * wgm::SEG + kg * 8;
+  const int nv = W - px;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int co = co0 + 16 * c + l16;
+    const bool cv = co < cout;
+    ld8(dy + ((size_t)b * cout + (cv ? co : 0)) * plane + (size_t)yy * W + px, vec, cv ? nv : 0, g.a[c]);
+  }
+#pragma unroll
+  for (int ky = 0; ky < 3; ++ky) {
+    const int sy = yy + ky - 1;
+    const bool rv = ci < cin && sy >= 0 && sy < H;
+    const float* s = x + ((size_t)b * cin + (rv ? ci : 0)) * plane + (size_t)(rv ? sy : 0) * W;
+    ld8(s + px, vec, rv ? nv : 0, g.b[ky] + 1);
+    g.b[ky][0] = (rv && px >= 1 && px - 1 < W) ? s[px - 1] : 0.f;
+    g.b[ky][9] = (rv && px + 8 < W) ? s[px + 8] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_conv3_wgrad_mfma(const float* __restrict__ x, const float* __restrict__ dy,
+                                                          float* __restrict__ part, int B, int cin, int cout, int H,
+                                                          int W, int nsplit, int vec) {
+  __shared__ float red[2 * 9 * 256];
+  __shared__ float bred[4][2][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int co0 = blockIdx.x * wgm::CO, ci0 = blockIdx.y * wgm::CI, split = blockIdx.z;
+  const int ws = (W + wgm::SEG - 1) / wgm::SEG;
+  const long nseg = (long)B * H * ws;
+  const long q0 = nseg * split / nsplit, q1 = nseg * (split + 1) / nsplit;
+  const int ci = ci0 + l16;
+  const size_t stride = (size_t)cout * cin * 9 + cout;  // floats per split
+  mf_f4 acc[2][9];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[c][t] = mf_f4{0.f, 0.f, 0.f, 0.f};
+  float bs[2] = {0.f, 0.f};
+  WgSeg cur;
+  long q = q0 + wave;
+  if (q < q1) wg_load(cur, x, dy, q, ws, B, cin, cout, H, W, co0, ci, l16, kg, vec);
+  for (; q < q1; q += 4) {
+    WgSeg nxt;
+    if (q + 4 < q1) wg_load(nxt, x, dy, q + 4, ws, B, cin, cout, H, W, co0, ci, l16, kg, vec);
+    mf_b8 a[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a[c][j] = (__bf16)cur.a[c][j];
+        bs[c] += cur.a[c][j];
+      }
+    }
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        mf_b8 bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bv[j] = (__bf16)cur.b[ky][j + kx];
+        acc[0][ky * 3 + kx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bv, acc[0][ky * 3 + kx], 0, 0, 0);
+        acc[1][ky * 3 + kx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bv, acc[1][ky * 3 + kx], 0, 0, 0);
+      }
+    cur = nxt;
+  }
+  // D lane layout: column (input channel) lane % 16, rows (output channels) 4 kg + i
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float& d = red[((c * 9 + t) * 16 + kg * 4 + i) * 16 + l16];
+            d = (w == 0 ? 0.f : d) + acc[c][t][i];
+          }
+    }
+    __syncthreads();
+  }
+  float* out = part + (size_t)split * stride;
+  for (int e = threadIdx.x; e < 2 * 9 * 256; e += 256) {
+    const int cil = e & 15, col = (e >> 4) & 15, t = (e >> 8) % 9, c = e / (9 * 256);
+    const int co = co0 + 16 * c + col, cc = ci0 + cil;
+    if (co < cout && cc < cin) out[((size_t)co * cin + cc) * 9 + t] = red[e];
+  }
+  if (blockIdx.y == 0) {
+    bred[wave][0][lane] = bs[0];
+    bred[wave][1][lane] = bs[1];
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      const int c = threadIdx.x >> 4, col = threadIdx.x & 15, co = co0 + threadIdx.x;
+      float a = 0.f;
+      for (int w = 0; w < 4; ++w)
+        for (int g = 0; g < 4; ++g) a += bred[w][c][g * 16 + col];
+      if (co < cout) out[(size_t)cout * cin * 9 + co] = a;
+    }
+  }
+}
+
+// dw[e] = sum over splits of part[s][e], e < n: a workgroup per 64 outputs,
+// wave w sums the splits w, w + SUM_WAVES, ... in order, then the waves' sums
+// are added in wave order.
+__global__ __launch_bounds__(64 * wgm::SUM_WAVES) void k_wgrad_sum(const float* __restrict__ part,
+                                                                  float* __restrict__ dw, size_t n, int nsplit) {
+  __shared__ float red[wgm::SUM_WAVES][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t e = (size_t)blockIdx.x * 64 + lane;
+  float a = 0.f;
+  if (e < n)
+    for (int s = wave; s < nsplit; s += wgm::SUM_WAVES) a += part[(size_t)s * n + e];
+  red[wave][lane] = a;
+  __syncthreads();
+  if (wave == 0 && e < n) {
+    float t = 0.f;
+    for (int w = 0; w < wgm::SUM_WAVES; ++w) t += red[w][lane];
+    dw[e] = t;
+  }
+}
+
 // db[c] = sum_b sum_p dy[b][c](p)
 __global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dy, float* __restrict__ db, int B, int C,
                                                    size_t plane) {
@@ -291,21 +454,31 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ x, cons
   }
 }
 
-// dW1[co][ci] = sum_b sum_p dy[b][co](p) x[b][ci](p)
-__global__ __launch_bounds__(256) void k_conv1_wgrad(const float* __restrict__ x, const float* __restrict__ dy,
-                                                     float* __restrict__ dw, int B, int cin, int cout, size_t plane) {
+// Split form of the 1x1 weight and bias gradients: output e < cout * cin is
+// dW1[e / cin][e % cin], e = cout * cin + co is db[co]; split s sums the pixels
+// i = (b, p) of its contiguous share of B * plane into part[s][e] (summed over
+// the splits by k_wgrad_sum).
+__global__ __launch_bounds__(256) void k_conv1_wgrad_split(const float* __restrict__ x, const float* __restrict__ dy,
+                                                           float* __restrict__ part, int B, int cin, int cout,
+                                                           unsigned plane, int nsplit) {
   __shared__ float red[4];
-  const int co = blockIdx.x / cin, ci = blockIdx.x % cin;
+  const int e = blockIdx.x, s = blockIdx.y;
+  const int n = cout * (cin + 1);
+  const bool bias = e >= cout * cin;
+  const int co = bias ? e - cout * cin : e / cin, ci = bias ? 0 : e % cin;
+  const unsigned total = (unsigned)B * plane;
+  const unsigned i0 = (unsigned)((unsigned long long)total * s / nsplit);
+  const unsigned i1 = (unsigned)((unsigned long long)total * (s + 1) / nsplit);
   float acc = 0.f;
-  for (int b = 0; b < B; ++b) {
-    const float* d = dy + ((size_t)b * cout + co) * plane;
-    const float* xp = x + ((size_t)b * cin + ci) * plane;
-    for (size_t p = threadIdx.x; p < plane; p += 256) acc += d[p] * xp[p];
+  for (unsigned i = i0 + threadIdx.x; i < i1; i += 256) {
+    const unsigned b = i / plane, p = i - b * plane;
+    const float d = dy[((size_t)b * cout + co) * plane + p];
+    acc += bias ? d : d * x[((size_t)b * cin + ci) * plane + p];
   }
   acc = wsumf(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) dw[(size_t)co * cin + ci] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) part[(size_t)s * n + e] = red[0] + red[1] + red[2] + red[3];
 }
 
 // dy = 0 where the ReLU output y is 0 (the derivative at 0 is taken as 0)
@@ -559,6 +732,7 @@ struct hp_unet_s {
   float *y = nullptr, *dy = nullptr, *ga = nullptr, *gb = nullptr;
   __bf16* xb = nullptr;   // bf16 channel-chunked copy of a convolution's input
   __bf16* wpk = nullptr;  // bf16 weight fragments of one convolution
+  float* wgpart = nullptr;  // per-split partial weight gradients (matrix-core path)
   std::vector<float*> owned;
   double* part = nullptr;    // device partial sums (loss)
   double* part_h = nullptr;  // pinned
@@ -578,6 +752,21 @@ int ufail(hp_unet n, int code, const std::string& msg) {
 }
 
 int ch(const hp_unet_s* n, int l) { return n->base << l; }
+
+// Splits of the pixel contraction in the matrix-core weight gradient: about
+// 1024 workgroups in all, each with at least 16 row segments (four per wave).
+int wgrad_splits(int B, int H, int W, int cin, int cout) {
+  const long nseg = (long)B * H * ((W + wgm::SEG - 1) / wgm::SEG);
+  const long blocks = (long)((cout + wgm::CO - 1) / wgm::CO) * ((cin + wgm::CI - 1) / wgm::CI);
+  return (int)std::max(1L, std::min(nseg / 16, 1024 / blocks));
+}
+
+// Splits of the 1x1 weight and bias gradients: about 1024 workgroups, each
+// with at least 4096 pixels.
+int conv1_splits(int B, int H, int W, int cin, int cout) {
+  const long pix = (long)B * H * W;
+  return (int)std::max(1L, std::min(pix / 4096, 1024L / ((long)cout * (cin + 1))));
+}
 
 void unet_layout(hp_unet n) {
   size_t off = 0;
@@ -607,6 +796,7 @@ void free_acts(hp_unet n) {
   for (auto* v : {&n->enc1, &n->enc2, &n->pool, &n->up, &n->dec1, &n->dec2, &n->dskip}) v->clear();
   n->y = n->dy = n->ga = n->gb = nullptr;
   n->xb = n->wpk = nullptr;
+  n->wgpart = nullptr;
   n->B = n->H = n->W = 0;
 }
 
@@ -658,6 +848,20 @@ int ensure_acts(hp_unet n, int B, int H, int W) {
     for (auto* v : {&n->enc_a, &n->enc_b, &n->dec_a, &n->dec_b})
       for (auto& c : *v) wmax = std::max({wmax, wsz(c.ci, c.co), wsz(c.co, c.ci)});
     n->wpk = reinterpret_cast<__bf16*>(dalloc(n, wmax / 2 + 8, &ok));
+    size_t pmax = 0;
+    for (int l = 0; l < L; ++l) {
+      auto part = [&](const hp_unet_s::Conv& c) {
+        pmax = std::max(pmax, (size_t)wgrad_splits(B, H >> l, W >> l, c.ci, c.co) * (c.ci * 9 + 1) * c.co);
+      };
+      part(n->enc_a[l]);
+      part(n->enc_b[l]);
+      if (l + 1 < L) {
+        part(n->dec_a[l]);
+        part(n->dec_b[l]);
+      }
+    }
+    pmax = std::max(pmax, (size_t)conv1_splits(B, H, W, n->out.ci, n->out.co) * n->out.co * (n->out.ci + 1));
+    n->wgpart = dalloc(n, pmax, &ok);
   }
   if (!ok) {
     free_acts(n);
@@ -694,9 +898,21 @@ void conv3(hp_unet n, const float* x, const hp_unet_s::Conv& c, float* y, int B,
 void conv3_bwd(hp_unet n, const float* x, const float* dy, const hp_unet_s::Conv& c, float* dx, int B, int H,
                int W) {
   if (dx) conv3_any(n, dy, n->P + c.w, nullptr, dx, c.co, c.ci, B, H, W, 9, c.ci * 9, 1, 0);
-  hipLaunchKernelGGL(k_conv3_wgrad, dim3(c.co * c.ci), dim3(256), 0, n->stream, x, dy, n->G + c.w, B, c.ci, c.co, H,
-                     W);
-  hipLaunchKernelGGL(k_bias_grad, dim3(c.co), dim3(256), 0, n->stream, dy, n->G + c.b, B, c.co, (size_t)H * W);
+  if (n->bf16) {
+    const int ns = wgrad_splits(B, H, W, c.ci, c.co);
+    const int vec = (W % 8 == 0) && ((uintptr_t)x % 16 == 0) && ((uintptr_t)dy % 16 == 0);
+    const dim3 grid((c.co + wgm::CO - 1) / wgm::CO, (c.ci + wgm::CI - 1) / wgm::CI, ns);
+    hipLaunchKernelGGL(k_conv3_wgrad_mfma, grid, dim3(256), 0, n->stream, x, dy, n->wgpart, B, c.ci, c.co, H, W, ns,
+                       vec);
+    // weights then bias: contiguous in the parameter layout
+    const size_t nw = (size_t)c.co * c.ci * 9 + c.co;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((nw + 63) / 64)), dim3(64 * wgm::SUM_WAVES), 0, n->stream,
+                       n->wgpart, n->G + c.w, nw, ns);
+  } else {
+    hipLaunchKernelGGL(k_conv3_wgrad, dim3(c.co * c.ci), dim3(256), 0, n->stream, x, dy, n->G + c.w, B, c.ci, c.co,
+                       H, W);
+    hipLaunchKernelGGL(k_bias_grad, dim3(c.co), dim3(256), 0, n->stream, dy, n->G + c.b, B, c.co, (size_t)H * W);
+  }
 }
 
 void relu_bwd(hp_unet n, const float* y, float* dy, size_t count) {
@@ -744,10 +960,15 @@ void backward(hp_unet n, const float* x) {
   const float* top = (L > 1) ? n->dec2[0] : n->enc2[0];
   float* ga = n->ga;
   float* gb = n->gb;
-  hipLaunchKernelGGL(k_conv1_wgrad, dim3(n->out.co * n->out.ci), dim3(256), 0, n->stream, top, n->dy,
-                     n->G + n->out.w, B, n->out.ci, n->out.co, pl0);
-  hipLaunchKernelGGL(k_bias_grad, dim3(n->out.co), dim3(256), 0, n->stream, n->dy, n->G + n->out.b, B, n->out.co,
-                     pl0);
+  {
+    // output layer: weights then bias, contiguous in the parameter layout
+    const int ns = conv1_splits(B, H, W, n->out.ci, n->out.co);
+    const int ne = n->out.co * (n->out.ci + 1);
+    hipLaunchKernelGGL(k_conv1_wgrad_split, dim3(ne, ns), dim3(256), 0, n->stream, top, n->dy, n->wgpart, B,
+                       n->out.ci, n->out.co, (unsigned)pl0, ns);
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((ne + 63) / 64)), dim3(64 * wgm::SUM_WAVES), 0, n->stream,
+                       n->wgpart, n->G + n->out.w, (size_t)ne, ns);
+  }
   hipLaunchKernelGGL(k_conv1, dim3(eblocks((size_t)B * pl0)), dim3(256), 0, n->stream, n->dy, n->P + n->out.w,
                      nullptr, ga, B, n->out.co, n->out.ci, pl0, 1);
   // decoder, top level first: ga = gradient w.r.t. dec2[l]

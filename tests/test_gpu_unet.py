@@ -83,6 +83,31 @@ def test_bf16_convolutions_exact_on_small_integers():
     assert np.array_equal(ya, yb)
 
 
+@pytest.mark.parametrize("H,W", [(32, 16), (128, 4)])
+def test_bf16_gradients_exact_on_small_integers(H, W):
+    """The same with the reverse pass: sparse integer weights, integer inputs, and a target that
+    differs from the output by small integers, over B * cout * H * W = 2^11 outputs, so that every
+    gradient the matrix cores see is a small integer times 2^-10 and every sum is exact.  The
+    gradients (matrix-core weight gradients summed over pixel-segment splits, and data gradients)
+    then equal the float32 ones bit for bit.  W = 4: rows shorter than one lane group, scalar
+    loads; W = 16: half-filled 32-pixel segments, vector loads."""
+    torch = _cuda()
+    from paper_2410_17446_amd.unet import HP_UNET_BF16, UNet
+    rng = np.random.default_rng(4)
+    a = UNet(1, 40, 7, 2, seed=0)
+    p = (rng.integers(-1, 2, size=a.nparam) * (rng.random(a.nparam) < 0.25)).astype(np.float32)
+    a.load_state(p)
+    b = UNet(1, 40, 7, 2, seed=0, precision=HP_UNET_BF16)
+    b.load_state(p)
+    x = to_gpu(rng.integers(-2, 3, size=(2, 7, H, W)).astype(np.float32))
+    y = a.forward(x).cpu().numpy()
+    t = to_gpu(y - rng.integers(-2, 3, size=y.shape).astype(np.float32))
+    la, lb = a.grad(x, t), b.grad(x, t)
+    ga, gb = a.state()["grads"], b.state()["grads"]
+    assert np.count_nonzero(ga) > ga.size // 10
+    assert la == lb and np.array_equal(ga, gb)
+
+
 @pytest.mark.parametrize("levels", [1, 3])
 def test_bf16_forward_and_gradients_near_oracle(levels):
     """bf16 operands (8 significant bits), float32 accumulation: forward within 2e-2 and the
