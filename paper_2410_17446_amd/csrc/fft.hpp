@@ -19,17 +19,46 @@
 // NT = L/8 threads per transform, each thread holding R values of a stage in
 // registers.  Twiddles come from a table tw[m] = exp(-2 pi i m / L).
 //
-// LDS addresses are padded by one element every eight (pidx): the first
-// stage writes eight consecutive elements per thread, i.e. a 128-byte lane
-// stride for complex128, which would put every lane of a group on the same
-// banks; with the pad the lane stride is 144 bytes and the groups spread over
-// all banks.
+// LDS layout of a transform buffer: element e sits at pidx<T>(e) =
+// e XOR ((e / 8) mod S), S = 256 / sizeof(cx<T>) elements per 256 bytes (16
+// for complex128, 32 for complex64).  The XOR only permutes each aligned run
+// of S elements, so the buffer needs no padding; measured with the LDS
+// bank-conflict counter, a wave reading an aligned run (every stage's reads),
+// writing with a stride of 8 elements (the first stage) or in runs of 8 at a
+// stride of 64 (the second) then meets no conflicts, where a one-in-eight pad
+// left every aligned read with one.
 #pragma once
 #include "cplx.hpp"
 
-__host__ __device__ constexpr int pidx(int e) { return e + (e >> 3); }
-// LDS elements of one padded transform buffer of length L
-__host__ __device__ constexpr int plen(int L) { return L + L / 8; }
+template <typename T>
+__host__ __device__ constexpr int lds_run() {
+  return 256 / (int)sizeof(cx<T>);
+}
+template <typename T>
+__host__ __device__ constexpr int pidx(int e) {
+  return e ^ ((e >> 3) & (lds_run<T>() - 1));
+}
+// Indices e0 + k STRIDE of one thread: when STRIDE is a multiple of
+// 8 lds_run<T>() the XOR term of every one of them equals that of e0, so they
+// are pidx(e0) + k STRIDE (constant offsets, no per-element address VGPRs).
+template <typename T, int STRIDE>
+struct PStep {
+  static constexpr bool LINEAR = STRIDE % (8 * lds_run<T>()) == 0;
+  int e0, p0;
+  __device__ __forceinline__ explicit PStep(int e) : e0(e), p0(pidx<T>(e)) {}
+  __device__ __forceinline__ int operator()(int k) const {
+    if constexpr (LINEAR)
+      return p0 + k * STRIDE;
+    else
+      return pidx<T>(e0 + k * STRIDE);
+  }
+};
+
+// LDS elements of one transform buffer of length L (whole runs)
+template <typename T>
+__host__ __device__ constexpr int plen(int L) {
+  return (L + lds_run<T>() - 1) / lds_run<T>() * lds_run<T>();
+}
 
 template <typename T>
 __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
@@ -124,8 +153,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
   for (int q = 0; q < PER; ++q) {
     const int j = t + q * NT;
     if (!EXACT && j >= NB) continue;
+    const PStep<T, NB> at(j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q][r] = buf[pidx(j + r * NB)];
+    for (int r = 0; r < R; ++r) v[q][r] = buf[at(r)];
     if constexpr (NS > 1) {
       const int k = j % NS;
       constexpr int STEP = L / (NS * R);
@@ -153,7 +183,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
     if (!EXACT && j >= NB) continue;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[pidx(base + r * NS)] = v[q][r];
+    for (int r = 0; r < R; ++r) buf[pidx<T>(base + r * NS)] = v[q][r];
   }
   __syncthreads();
 }
@@ -184,27 +214,27 @@ __device__ __forceinline__ void fft(cx<T>* buf, const cx<T>* __restrict__ tw, in
 template <typename T>
 __device__ __forceinline__ void odd_store(cx<T>* buf, int n, int m, cx<T> x) {
   if (m == 0) {
-    buf[pidx(0)] = mk<T>(0, 0);
-    buf[pidx(n)] = mk<T>(0, 0);
+    buf[pidx<T>(0)] = mk<T>(0, 0);
+    buf[pidx<T>(n)] = mk<T>(0, 0);
   } else {
-    buf[pidx(m)] = x;
-    buf[pidx(2 * n - m)] = -x;
+    buf[pidx<T>(m)] = x;
+    buf[pidx<T>(2 * n - m)] = -x;
   }
 }
 
 // DST-I coefficient p (1..n-1) from the FFT of the odd extension.
 template <typename T>
 __device__ __forceinline__ cx<T> dst_out(const cx<T>* buf, int p, T scale) {
-  return scale * mul_i(buf[pidx(p)]);
+  return scale * mul_i(buf[pidx<T>(p)]);
 }
 
 // Value at index i (any integer in (-n, 2n)) of the odd-periodic sequence whose
 // entries 1..n-1 sit (FFT output, unscaled) in buf: reflection about 0 and n.
 template <typename T>
 __device__ __forceinline__ cx<T> odd_at(const cx<T>* buf, int n, int i) {
-  if (i > 0 && i < n) return buf[pidx(i)];
-  if (i < 0 && i > -n) return -buf[pidx(-i)];
-  if (i > n && i < 2 * n) return -buf[pidx(2 * n - i)];
+  if (i > 0 && i < n) return buf[pidx<T>(i)];
+  if (i < 0 && i > -n) return -buf[pidx<T>(-i)];
+  if (i > n && i < 2 * n) return -buf[pidx<T>(2 * n - i)];
   return mk<T>(0, 0);
 }
 
@@ -272,29 +302,29 @@ __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, c
   const cx<T>* sintab = tw + N;
   // pre-processing, one thread per pair (j, n - j), j = 1..n/2
   for (int j = 1 + t; j <= N / 2; j += NT) {
-    const cx<T> a = buf[pidx(j)];
+    const cx<T> a = buf[pidx<T>(j)];
     const T sj = sintab[j].re;
     if (j == N / 2) {
-      buf[pidx(j)] = (T)2 * sj * a;
+      buf[pidx<T>(j)] = (T)2 * sj * a;
     } else {
-      const cx<T> b = buf[pidx(N - j)];
+      const cx<T> b = buf[pidx<T>(N - j)];
       const cx<T> sum = sj * (a + b), dif = (T)0.5 * (a - b);
-      buf[pidx(j)] = sum + dif;
-      buf[pidx(N - j)] = sum - dif;
+      buf[pidx<T>(j)] = sum + dif;
+      buf[pidx<T>(N - j)] = sum - dif;
     }
   }
-  if (t == 0) buf[pidx(0)] = mk<T>(0, 0);
+  if (t == 0) buf[pidx<T>(0)] = mk<T>(0, 0);
   __syncthreads();
   fft<T, N>(buf, tw, t);
   // post-processing: thread t owns k = 4t+1 .. 4t+4 (k <= n/2 - 1)
-  const cx<T> f0 = buf[pidx(0)];
+  const cx<T> f0 = buf[pidx<T>(0)];
   cx<T> ev[4], od[4];
   cx<T> run = mk<T>(0, 0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int k = 4 * t + 1 + i;
     if (k < N / 2) {
-      const cx<T> fk = buf[pidx(k)], fn = buf[pidx(N - k)];
+      const cx<T> fk = buf[pidx<T>(k)], fn = buf[pidx<T>(N - k)];
       ev[i] = (T)0.5 * mul_i(fk - fn);
       run = run + (T)0.5 * (fk + fn);
     }
@@ -307,13 +337,13 @@ __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, c
   for (int i = 0; i < 4; ++i) {
     const int k = 4 * t + 1 + i;
     if (k < N / 2) {
-      buf[pidx(2 * k)] = ev[i];
-      buf[pidx(2 * k + 1)] = base + od[i];
+      buf[pidx<T>(2 * k)] = ev[i];
+      buf[pidx<T>(2 * k + 1)] = base + od[i];
     }
   }
   if (t == 0) {
-    buf[pidx(0)] = mk<T>(0, 0);
-    buf[pidx(1)] = (T)0.5 * f0;
+    buf[pidx<T>(0)] = mk<T>(0, 0);
+    buf[pidx<T>(1)] = (T)0.5 * f0;
   }
   __syncthreads();
 }
@@ -321,5 +351,5 @@ __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, c
 // Orthonormal DST-I value p from dst1 output.
 template <typename T>
 __device__ __forceinline__ cx<T> dst_val(const cx<T>* buf, int p, T scale) {
-  return scale * buf[pidx(p)];
+  return scale * buf[pidx<T>(p)];
 }

@@ -70,7 +70,7 @@ template <typename T, typename C, int N>
 struct ColCfg {
   static constexpr int TW = Tile<T>::W;
   static constexpr int NT = N / 8;
-  static constexpr int PB = plen(N) * (int)sizeof(cx<C>);
+  static constexpr int PB = plen<C>(N) * (int)sizeof(cx<C>);
   static constexpr int G0 = kColLdsBytes / PB;
   static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
   static constexpr int G2 = (G1 * NT > 1024) ? 1024 / NT : G1;
@@ -79,11 +79,11 @@ struct ColCfg {
   static_assert(TW % GC == 0, "column groups tile the 128-byte row");
   static constexpr int WG = GC * NT;
   static constexpr int SCR = ScanScratch<NT>::SIZE;
-  // LDS stride between the GC column buffers: plen(N) (a multiple of 256 bytes
-  // for the sizes used) plus 256/GC bytes, so that neighbouring threads, which
-  // alternate columns in the load, divide and store loops, hit different banks
+  // LDS stride between the GC column buffers: plen<C>(N) (a multiple of 256
+  // bytes) plus 256/GC bytes, so that neighbouring threads, which alternate
+  // columns in the load, divide and store loops, hit different banks
   static constexpr int SHIFT = (256 / GC) / (int)sizeof(cx<C>) > 0 ? (256 / GC) / (int)sizeof(cx<C>) : 1;
-  static constexpr int PLC = plen(N) + SHIFT;
+  static constexpr int PLC = plen<C>(N) + SHIFT;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -128,15 +128,16 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restric
                                                            int ny, size_t fsz, int nblk) {
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT;
-  __shared__ cx<C> lds[RPW * plen(N)];
+  __shared__ cx<C> lds[RPW * plen<C>(N)];
   __shared__ cx<C> scr[RPW * RC::SCR];
   __shared__ double red[(WG + 63) / 64];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = 1 + blockIdx.x * RPW + g;
   const int comp = blockIdx.y;
   const bool valid = row < ny;
-  cx<C>* buf = lds + g * plen(N);
+  cx<C>* buf = lds + g * plen<C>(N);
   const c128* src = in + comp * fsz + (size_t)row * N;
+  const PStep<C, NT> at(t);  // LDS index of element t + s NT
   double nrm = 0.0;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restric
       nrm += abs2(a);
       v = cvt<C>(a);
     }
-    buf[pidx(m)] = v;
+    buf[at(s)] = v;
   }
   __syncthreads();
   dst1<C, N>(buf, tw, scr + g * RC::SCR, t);
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restric
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int p = t + s * NT;
-      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : cvt<T>(dst_val(buf, p, scale));
+      dst[tix<TW>(row, p, ny)] = (p == 0) ? czero<T>() : cvt<T>(scale * buf[at(s)]);
     }
   }
   double sum = block_sum<WG>(nrm, red);
@@ -171,18 +172,19 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restri
                                                            const cx<C>* __restrict__ tw, int ny, size_t fsz) {
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT;
-  __shared__ cx<C> lds[RPW * plen(N)];
+  __shared__ cx<C> lds[RPW * plen<C>(N)];
   __shared__ cx<C> scr[RPW * RC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // all rows, row 0 -> zeros
   const int comp = blockIdx.y;
   const bool valid = row < ny && row > 0;
-  cx<C>* buf = lds + g * plen(N);
+  cx<C>* buf = lds + g * plen<C>(N);
   const cx<T>* src = in + comp * fsz;
+  const PStep<C, NT> at(t);  // LDS index of element t + s NT
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int m = t + s * NT;
-    buf[pidx(m)] = (valid && m > 0) ? cvt<C>(src[tix<TW>(row, m, ny)]) : czero<C>();
+    buf[at(s)] = (valid && m > 0) ? cvt<C>(src[tix<TW>(row, m, ny)]) : czero<C>();
   }
   __syncthreads();
   dst1<C, N>(buf, tw, scr + g * RC::SCR, t);
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restri
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int p = t + s * NT;
-      dst[p] = (!valid || p == 0) ? mk(0.0, 0.0) : cvt<double>(dst_val(buf, p, scale));
+      dst[p] = (!valid || p == 0) ? mk(0.0, 0.0) : cvt<double>(scale * buf[at(s)]);
     }
   }
 }
@@ -233,7 +235,6 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
   using CC = ColCfg<T, C, N>;
   constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
   constexpr int PL = CC::PLC;  // padded per-column stride
-  constexpr int NE = (N - 1) * GC;  // elements of one group (rows 1..N-1)
   __shared__ cx<C> lds[GC * PL];
   __shared__ cx<C> scr[GC * CC::SCR];
   int tile, sub;
@@ -253,30 +254,40 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
   const cx<T>* u = uptr[k * (HP_MAXM + 1) + m] + tbase;
   cx<T>* z = zbase + k * zsp + m * zsi + tbase;
   cx<T>* dz = (NC == 2) ? dzbase + k * dzsp + tbase : nullptr;
+  // The loops below give consecutive threads the columns of a row in turn,
+  // from row 0, so that every 16 threads touch one aligned run of rows:
+  // thread tid takes column c = tid % GC, rows r0 + i NT (i = 0..7).
+  const int c = tid % GC, r0 = tid / GC, q = col0 + c0 + c;
+  cx<C>* bc = lds + c * PL;
+  const PStep<C, NT> at(r0);
   {
-    for (int e = tid; e < NE; e += WG) {
-      const int r = 1 + e / GC, c = e % GC;
-      lds[c * PL + pidx(r)] = cvt<C>(u[(size_t)r * TW + c0 + c]);
+#pragma unroll 2
+    for (int i = 0; i < N / NT; ++i) {
+      const int r = r0 + i * NT;
+      bc[at(i)] = r == 0 ? czero<C>() : cvt<C>(u[(size_t)r * TW + c0 + c]);
     }
-    if (tid < GC) lds[tid * PL + pidx(0)] = czero<C>();
     __syncthreads();
     dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
     // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
-    for (int e = tid; e < NE; e += WG) {
-      const int p = 1 + e / GC, c = e % GC, q = col0 + c0 + c;
-      cx<C>* bc = lds + c * PL;
-      const cx<C> X = dst_val(bc, p, scale);
+#pragma unroll 2
+    for (int i = 0; i < N / NT; ++i) {
+      const int p = r0 + i * NT;
+      if (p == 0) {
+        bc[at(i)] = czero<C>();
+        continue;
+      }
+      const cx<C> X = scale * bc[at(i)];
       const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
       const double den = lr * lr + li * li;
-      bc[pidx(p)] = X * mk<C>((C)(lr / den), (C)(-li / den));
+      bc[at(i)] = X * mk<C>((C)(lr / den), (C)(-li / den));
     }
-    if (tid < GC) lds[tid * PL + pidx(0)] = czero<C>();
     __syncthreads();
     dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
-    for (int e = tid; e < NE; e += WG) {
-      const int p = 1 + e / GC, c = e % GC;
-      const cx<C>* bc = lds + c * PL;
-      z[(size_t)p * TW + c0 + c] = cvt<T>(sc2 * bc[pidx(p)]);
+#pragma unroll 2
+    for (int i = 0; i < N / NT; ++i) {
+      const int p = r0 + i * NT;
+      if (p == 0) continue;
+      z[(size_t)p * TW + c0 + c] = cvt<T>(sc2 * bc[at(i)]);
       if constexpr (NC == 2) {
         // D1y of the column, physical in y (odd reflection about rows 0 and N)
         cx<double> acc = mk(0.0, 0.0);
@@ -323,7 +334,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
   using AC = ApplyCfg<N, NC>;
   constexpr int NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
   constexpr int PT = N / NT;  // values per thread per row
-  constexpr int PL = plen(N);
+  constexpr int PL = plen<C>(N);
   __shared__ cx<C> lds[GROUPS * PL * NC];
   __shared__ cx<C> scr[GROUPS * AC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
@@ -339,12 +350,13 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
   const size_t cbase = comp * fsz;
   const size_t ci0 = (size_t)row * N;  // physical row offset
   const RowWalk<TW, NT> toff(cbase, valid ? row : 0, t, ny);  // tiled offsets of the thread's points
+  const PStep<C, NT> at(t);                                    // LDS index of point t + s NT
 
   const cx<T>* z = zbase + k * zsp + m * zsi;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    buf[pidx(j)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
+    buf[at(s)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
   }
   __syncthreads();
   dst1<C, N>(buf, tw, sg, t);
@@ -353,7 +365,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      const cx<C> zj = (j == 0) ? czero<C>() : dst_val(buf, j, scale);
+      const cx<C> zj = (j == 0) ? czero<C>() : scale * buf[at(s)];
       const C v = valid ? coef[ci0 + j] : (C)0;
       pz[s] = v * zj;
     }
@@ -373,7 +385,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
       pz[s] = czero<C>();
       if (!valid || j == 0) continue;
       const size_t ci = ci0 + j;
-      const cx<C> zc = dst_val(buf, j, scale), zo = dst_val(ob, j, scale);
+      const cx<C> zc = scale * buf[at(s)], zo = scale * ob[at(s)];
       cx<C> acc = czero<C>();
 #pragma unroll
       for (int mm = 1; mm <= 6; ++mm) acc = acc + (C)sc.d1x[mm - 1] * (odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
@@ -383,7 +395,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
         pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * dx + pxy * zo;
       } else {
         pz[s] = (coef[4 * fsz + ci] + v) * zc + pxy * zo;
-        xb[pidx(j)] = dx;
+        xb[at(s)] = dx;
       }
     }
     __syncthreads();
@@ -391,7 +403,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
       for (int s = 0; s < PT; ++s) {
         const int j = t + s * NT;
-        if (j > 0) pz[s] = pz[s] + coef[2 * fsz + ci0 + j] * oxb[pidx(j)];
+        if (j > 0) pz[s] = pz[s] + coef[2 * fsz + ci0 + j] * oxb[at(s)];
       }
     }
     // D1y of both components (the column pass's second output), row-transformed
@@ -399,7 +411,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      buf[pidx(j)] = (valid && j > 0) ? cvt<C>(dz[toff.at(s)]) : czero<C>();
+      buf[at(s)] = (valid && j > 0) ? cvt<C>(dz[toff.at(s)]) : czero<C>();
     }
     __syncthreads();
     dst1<C, N>(buf, tw, sg, t);
@@ -409,7 +421,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
         const int j = t + s * NT;
         if (j == 0) continue;
         const size_t ci = ci0 + j;
-        pz[s] = pz[s] + coef[2 * fsz + ci] * dst_val(buf, j, scale) + coef[fsz + ci] * dst_val(ob, j, scale);
+        pz[s] = pz[s] + coef[2 * fsz + ci] * scale * buf[at(s)] + coef[fsz + ci] * scale * ob[at(s)];
       }
     }
     __syncthreads();
@@ -418,7 +430,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    buf[pidx(j)] = (j == 0) ? czero<C>() : pz[s];
+    buf[at(s)] = (j == 0) ? czero<C>() : pz[s];
   }
   __syncthreads();
   dst1<C, N>(buf, tw, sg, t);
@@ -427,7 +439,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
     const int j = t + s * NT;
-    pv[s] = (j == 0 || !valid) ? czero<T>() : cvt<T>(dst_val(buf, j, scale));
+    pv[s] = (j == 0 || !valid) ? czero<T>() : cvt<T>(scale * buf[at(s)]);
     if (valid) p[toff.at(s)] = pv[s];
   }
   // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
@@ -888,13 +900,13 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
                                                          const c128* __restrict__ tw, int nx, int ny, size_t fsz) {
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT, TW = Tile<T>::W;
-  __shared__ c128 lds[RPW * plen(N)];
+  __shared__ c128 lds[RPW * plen<double>(N)];
   __shared__ c128 scr[RPW * RC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int row = blockIdx.x * RPW + g;  // rows 0..ny-1
   const int comp = blockIdx.y;
   const bool valid = row > 0 && row < ny;
-  c128* buf = lds + g * plen(N);
+  c128* buf = lds + g * plen<double>(N);
   const size_t roff = comp * fsz + (size_t)row * N;
   const RowWalk<TW, NT> toff(comp * fsz, valid ? row : 0, t, ny);
   c128 acc[PT];
@@ -918,8 +930,9 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
       }
     }
   }
+  const PStep<double, NT> at(t);  // LDS index of element t + s NT
 #pragma unroll
-  for (int s = 0; s < PT; ++s) buf[pidx(t + s * NT)] = acc[s];
+  for (int s = 0; s < PT; ++s) buf[at(s)] = acc[s];
   __syncthreads();
   dst1<double, N>(buf, tw, scr + g * RC::SCR, t);
   const double scale = sqrt(2.0 / N);
@@ -929,7 +942,7 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
       const int j = t + s * NT;
       c128 v = mk(0.0, 0.0);
       if (valid && j > 0) {
-        const c128 sv = dst_val(buf, j, scale);
+        const c128 sv = scale * buf[at(s)];
         v = edge_loss(row, j, nx, ny, W, eta, loss_coef) * (phase * sv + rinf_phase * w[roff + j]);
       }
       out[roff + j] = v;
