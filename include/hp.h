@@ -196,6 +196,11 @@ enum { HP_K_ROW_FWD = 0, HP_K_COL = 1, HP_K_ROW_APPLY = 2, HP_K_UPDATE = 3, HP_K
        HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_COUNT = 7 };
 int hp_profile(hp_plan plan, int enable);
 int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
+/* Time only every period-th launch of each timed class (period >= 1, counted
+ * per class from the last hp_profile call; 1 = every launch, the default).
+ * A period above 1 takes the event pairs out of most launches, so the step
+ * keeps its untimed rate while the timed launches sample the class. */
+int hp_profile_sample(hp_plan plan, int period);
 
 const char* hp_last_error(hp_plan plan);
 void hp_plan_destroy(hp_plan plan);

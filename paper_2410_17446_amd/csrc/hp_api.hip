@@ -64,13 +64,13 @@ struct hp_plan_s {
   void** uptr = nullptr;
   void** uptr_scratch = nullptr;
   int* active_d = nullptr;
-  int* flags_d = nullptr;
   double* est_d = nullptr;
   double2* part_dots = nullptr;
   double* part_norm = nullptr;
   double* part_misc = nullptr;
   // host
-  int* flags_h = nullptr;  // pinned
+  int* flags_h = nullptr;   // pinned
+  int* flags_hd = nullptr;  // its device address (k_arnoldi writes the flags there)
   double* est_h = nullptr;
   int* active_h = nullptr;
   double* misc_h = nullptr;
@@ -87,6 +87,8 @@ struct hp_plan_s {
   double* guess_part_h = nullptr; // pinned copy (+1 slot: ||w||)
   // kernel timing
   int prof = 0;  // bit c set: launches of kernel class c are timed
+  int prof_every = 1;              // time every prof_every-th launch of a class
+  long prof_seen[HP_K_COUNT] = {};  // launches of each class since hp_profile
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_cls;
@@ -128,6 +130,8 @@ struct Prof {
   double bytes;
   bool on;
   Prof(hp_plan p_, int c, double b) : p(p_), cls(c), bytes(b), on(((p_->prof >> c) & 1) != 0) {
+    if (!on) return;
+    on = (p->prof_seen[c]++ % p->prof_every) == 0;
     if (!on) return;
     if (p->ev_used + 2 > p->ev_pool.size()) {
       for (int i = 0; i < 256; ++i) {
@@ -204,7 +208,6 @@ void layout(hp_plan p, Ws& w) {
   p->uptr = w.take<void*>((size_t)K * (HP_MAXM + 1));
   p->uptr_scratch = w.take<void*>(HP_MAXM + 1);
   p->active_d = w.take<int>(3 * HP_MAXPOLES);
-  p->flags_d = w.take<int>(2 * HP_MAXPOLES);
   p->est_d = w.take<double>(HP_MAXPOLES);
   p->part_dots = w.take<double2>((size_t)K * (HP_MAXM + 1) * 2 * p->napplyblk);
   p->part_norm = w.take<double>((size_t)K * p->nupdblk);
@@ -492,8 +495,6 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   const int ns = (int)subset.size();
   for (int a = 0; a < ns; ++a) act0[a] = subset[a];
   HPCHK(hipMemcpyAsync(p->active_d, act0, ns * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  // device copies of the iteration lists (slot 0 shares its storage with the initial list)
-  std::vector<int> uploaded[2] = {subset, {}};
   launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol, inner_rtol(p),
                     p->stream);
   std::vector<char> live(K, 0);
@@ -547,7 +548,6 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   auto launch_iter = [&](const std::vector<int>& poles) -> int {
     const int slot = (int)(next_iter & 1);
     const int na = (int)poles.size();
-    int* ah = p->active_h + slot * HP_MAXPOLES;
     int* ad = p->active_d + slot * HP_MAXPOLES;
     int maxm = 0;
     double sum_m = 0.0;
@@ -556,16 +556,13 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       maxm = std::max(maxm, mk_);
       sum_m += mk_;
     }
-    if (uploaded[slot] != poles) {  // the slot's device list changes only when poles finish
-      for (int a = 0; a < na; ++a) ah[a] = poles[a];
-      HPCHK(hipMemcpyAsync(ad, ah, na * sizeof(int), hipMemcpyHostToDevice, p->stream));
-      uploaded[slot] = poles;
-    }
     {
+      // the column pass takes the list in its arguments and stores it to ad
+      // for the kernels after it (no host-to-device copy per round)
       const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
       Prof pr(p, HP_K_COL, U1 * es * (na + outs));
-      launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, ad, na, false, p->mu_x, p->mu_y, twy, p->geo, p->sc,
-                    p->stream);
+      launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, poles.data(), na, ad, p->mu_x, p->mu_y, twy, p->geo,
+                       p->sc, p->stream);
     }
     {
       const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
@@ -585,11 +582,10 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     }
     {
       Prof pr(p, HP_K_SMALL, 0.0);
-      launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->flags_d + slot * HP_MAXPOLES, p->est_d,
+      // flags go straight to pinned host memory (read after the event below)
+      launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->flags_hd + slot * HP_MAXPOLES, p->est_d,
                      p->stream);
     }
-    HPCHK(hipMemcpyAsync(p->flags_h + slot * HP_MAXPOLES, p->flags_d + slot * HP_MAXPOLES, K * sizeof(int),
-                         hipMemcpyDeviceToHost, p->stream));
     HPCHK(hipEventRecord(p->iter_ev[slot], p->stream));
     q.push_back(Flight{poles, slot, next_iter});
     ++next_iter;
@@ -721,16 +717,15 @@ int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
   h.sigma[0] = 1.0;
   void* tbl[HP_MAXM + 1] = {nullptr};
   tbl[0] = p->tmpR;
-  int zero = 0;
+  const int zero = 0;
   HPCHK(hipMemcpyAsync(p->st_scratch, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(p->uptr_scratch, tbl, sizeof(tbl), hipMemcpyHostToDevice, p->stream));
-  HPCHK(hipMemcpyAsync(p->active_d + 3 * HP_MAXPOLES - 2, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
   launch_row_fwd<T, C>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<C>*>(p->tw_x),
                     p->geo, p->stream);
   // the first basis slot of pole 0 in Z serves as output; the DZ slot as scratch
   cx<T>* zout = reinterpret_cast<cx<T>*>(p->P);
   launch_col<T, C>(reinterpret_cast<const cx<T>* const*>(p->uptr_scratch), zout, 0, 0, reinterpret_cast<cx<T>*>(p->DZ), 0,
-                p->st_scratch, p->active_d + 3 * HP_MAXPOLES - 2, 1, false, p->mu_x, p->mu_y,
+                p->st_scratch, &zero, 1, nullptr, p->mu_x, p->mu_y,
                 reinterpret_cast<const cx<C>*>(p->tw_y), p->geo, p->sc, p->stream);
   launch_row_inv<T, C>(zout, y, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
   HPCHK(hipStreamSynchronize(p->stream));
@@ -836,6 +831,11 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
     hp_plan_destroy(p);
     return fail(nullptr, HP_ENOMEM, "pinned host allocation failed");
   }
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&p->flags_hd), p->flags_h, 0) != hipSuccess) {
+    hp_plan_destroy(p);
+    return fail(nullptr, HP_EHIP, "no device address for the pinned flag buffer");
+  }
+  memset(p->flags_h, 0, 2 * HP_MAXPOLES * sizeof(int));
   int rc = (p->mixed && !p->mixed64) ? upload_tables<float>(p) : upload_tables<double>(p);
   if (rc) {
     g_thread_error = p->err;
@@ -1030,7 +1030,15 @@ int hp_profile(hp_plan p, int enable) {
     p->prof_n[c] = 0;
     p->prof_ms[c] = 0.0;
     p->prof_b[c] = 0.0;
+    p->prof_seen[c] = 0;
   }
+  return HP_OK;
+}
+
+int hp_profile_sample(hp_plan p, int period) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (period < 1) return fail(p, HP_EINVAL, "period must be >= 1");
+  p->prof_every = period;
   return HP_OK;
 }
 

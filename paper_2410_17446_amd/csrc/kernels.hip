@@ -229,9 +229,9 @@ struct ColWaves {
 template <typename T, typename C, int N, int NC>
 __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_col(
     const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
-    cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const int* __restrict__ active,
-    const double* __restrict__ mu_x, const double* __restrict__ mu_y, const cx<C>* __restrict__ tw, size_t fsz,
-    StencilCoef sc) {
+    cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const PoleList list,
+    int* __restrict__ active_out, const double* __restrict__ mu_x, const double* __restrict__ mu_y,
+    const cx<C>* __restrict__ tw, size_t fsz, StencilCoef sc) {
   using CC = ColCfg<T, C, N>;
   constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
   constexpr int PL = CC::PLC;  // padded per-column stride
@@ -245,8 +245,13 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
   const int tid = threadIdx.x;
   const int g = tid / NT, t = tid % NT;
   const C scale = (C)sqrt(2.0 / N);
-  const int k = active[blockIdx.y / NC];
-  if (st[k].flag) return;
+  // workgroup (0, 0) stores the pole list for the round's later kernels
+  const bool writer = active_out && blockIdx.x == 0 && blockIdx.y == 0;
+  const int k = list.k[blockIdx.y / NC];
+  if (st[k].flag) {
+    if (writer && tid < list.n) active_out[tid] = list.k[tid];
+    return;
+  }
   const int m = st[k].m;
   const c128 b = st[k].bk;
   const C sc2 = (C)st[k].sigma[m] * scale;
@@ -298,6 +303,7 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
       }
     }
   }
+  if (writer && tid < list.n) active_out[tid] = list.k[tid];
 }
 
 // ------------------------------------------------------------------ row pass (medium part + inner products)
@@ -1185,18 +1191,20 @@ void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, i
 
 template <typename T, typename C>
 void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
-                const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
+                const PoleState* st, const int* poles, int nactive, int* active_out, const double* mu_x,
                 const double* mu_y, const cx<C>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s) {
-  (void)shared;
+  PoleList list;
+  list.n = nactive;
+  for (int a = 0; a < HP_MAXPOLES; ++a) list.k[a] = a < nactive ? poles[a] : 0;
 #define L_(NN)                                                                                                 \
   {                                                                                                            \
     dim3 grid(g.nx / ColCfg<T, C, NN>::GC, g.ncomp * nactive);                                                 \
     if (g.ncomp == 1)                                                                                          \
       hipLaunchKernelGGL((k_col<T, C, NN, 1>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
-                         dzbase, dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                 \
+                         dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);                       \
     else                                                                                                       \
       hipLaunchKernelGGL((k_col<T, C, NN, 2>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
-                         dzbase, dzsp, st, active, mu_x, mu_y, tw, g.fsz, sc);                                 \
+                         dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);                       \
   }
   HP_DISPATCH_N(g.ny, L_)
 #undef L_
@@ -1347,7 +1355,7 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   template void launch_row_fwd<T, C>(const c128*, cx<T>*, double*, const cx<C>*, const Geo&, hipStream_t, int);      \
   template void launch_row_inv<T, C>(const cx<T>*, c128*, const cx<C>*, const Geo&, int, hipStream_t);               \
   template void launch_col<T, C>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,      \
-                                 const int*, int, bool, const double*, const double*, const cx<C>*, const Geo&,      \
+                                 const int*, int, int*, const double*, const double*, const cx<C>*, const Geo&,      \
                                  const StencilCoef&, hipStream_t);                                                   \
   template void launch_row_apply<T, C>(const cx<T>*, size_t, size_t, const cx<T>*, size_t, cx<T>*, size_t,           \
                                        const cx<T>* const*, const C*, const PoleState*, const int*, int, double2*,   \

@@ -33,11 +33,13 @@ template <typename T, typename C = T>
 void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s);
 
 // Column pass: z = sigma_m * S_y diag(1/(mu_y + mu_x - b_k)) S_y u_m for the
-// active poles.  shared: every pole reads the same u (the step's S_x w).
-// Vector fields also get dz = D1y z (the y derivative the row pass needs).
+// poles poles[0..nactive) (a host array, passed by value in the kernel
+// arguments; the kernel also stores it to active_out, when not null, for the
+// kernels after it on the stream).  Vector fields also get dz = D1y z (the y
+// derivative the row pass needs).
 template <typename T, typename C = T>
 void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, cx<T>* dzbase, size_t dzsp,
-                const PoleState* st, const int* active, int nactive, bool shared, const double* mu_x,
+                const PoleState* st, const int* poles, int nactive, int* active_out, const double* mu_x,
                 const double* mu_y, const cx<C>* tw, const Geo& g, const StencilCoef& sc, hipStream_t s);
 
 // Row pass: p = S_x (P (S_x z_m)) with P the medium part of Zbar, plus the

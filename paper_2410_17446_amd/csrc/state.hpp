@@ -47,3 +47,10 @@ struct PoleState {
   c128 Pd[HP_MAXM + 1];               // reduced <u_i, p> of the current step
   c128 Qd[HP_MAXM + 1];               // reduced <u_i, u_m> of the current step
 };
+
+// The poles of one launch, passed by value in the kernel arguments (no copy to
+// the device before the launch).
+struct PoleList {
+  int n;
+  int k[HP_MAXPOLES];
+};

@@ -23,7 +23,7 @@ HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
            "hp_step_guess", "hp_set_guess", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
-           "hp_profile", "hp_profile_read", "hp_last_error", "hp_plan_destroy",
+           "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_last_error", "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
 KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
 
@@ -70,6 +70,7 @@ def lib():
         L.hp_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp]
         L.hp_profile.argtypes = [vp, C.c_int]
         L.hp_profile_read.argtypes = [vp, C.POINTER(C.c_long), dp, dp]
+        L.hp_profile_sample.argtypes = [vp, C.c_int]
         L.hp_last_error.argtypes = [vp]
         L.hp_last_error.restype = C.c_char_p
         L.hp_plan_destroy.argtypes = [vp]
@@ -209,6 +210,10 @@ class Plan:
         if enable:
             mask = -1 if classes is None else sum(1 << KERNEL_CLASSES.index(c) for c in classes)
         return self._check(self.L.hp_profile(self.handle, mask), "hp_profile")
+
+    def profile_sample(self, period):
+        """Time every period-th launch of each timed class (1 = all)."""
+        return self._check(self.L.hp_profile_sample(self.handle, int(period)), "hp_profile_sample")
 
     def profile_read(self):
         """{kernel class: (launches, total ms, total algorithmic bytes)}."""
