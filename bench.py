@@ -415,6 +415,7 @@ def main():
                                 "achieved": inner_b / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else 0.0,
                                 "frac": (inner_b / (inner_ms * 1e-3) / 1e9) / HBM_PEAK_GBS if inner_ms > 0 else 0.0},
         "warmup_kernel_ms": {k: brk[k][1] for k in brk},
+        "warmup_kernel_GBps": {k: brk[k][2] / (brk[k][1] * 1e-3) / 1e9 for k in brk if brk[k][1] > 0 and brk[k][2] > 0},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_poles)

@@ -209,25 +209,6 @@ __device__ __forceinline__ void fft(cx<T>* buf, const cx<T>* __restrict__ tw, in
   fft_stages<T, L, 1, L / 8>(buf, tw, t);
 }
 
-// Store x_m (m = 1..n-1) and its odd image into the length-2n buffer; m = 0
-// writes the two Dirichlet zeros.  x is the value for index m.
-template <typename T>
-__device__ __forceinline__ void odd_store(cx<T>* buf, int n, int m, cx<T> x) {
-  if (m == 0) {
-    buf[pidx<T>(0)] = mk<T>(0, 0);
-    buf[pidx<T>(n)] = mk<T>(0, 0);
-  } else {
-    buf[pidx<T>(m)] = x;
-    buf[pidx<T>(2 * n - m)] = -x;
-  }
-}
-
-// DST-I coefficient p (1..n-1) from the FFT of the odd extension.
-template <typename T>
-__device__ __forceinline__ cx<T> dst_out(const cx<T>* buf, int p, T scale) {
-  return scale * mul_i(buf[pidx<T>(p)]);
-}
-
 // Value at index i (any integer in (-n, 2n)) of the odd-periodic sequence whose
 // entries 1..n-1 sit (FFT output, unscaled) in buf: reflection about 0 and n.
 template <typename T>

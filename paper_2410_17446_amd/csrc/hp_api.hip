@@ -84,6 +84,8 @@ struct hp_plan_s {
   std::vector<int> accepted;      // per pole: the last step started from a guess
   c128* guess_r = nullptr;        // per pole: residual of its guess (allocated on first use)
   double* guess_part = nullptr;   // per pole: partial sums of |r0|^2
+  c128* guess_x = nullptr;        // per pole: physical previous-step solution (first use)
+  double* guess_rpart = nullptr;  // per pole: partial norms of S_x r0
   double* guess_part_h = nullptr; // pinned copy (+1 slot: ||w||)
   // kernel timing
   int prof = 0;  // bit c set: launches of kernel class c are timed
@@ -400,12 +402,15 @@ void fold(hp_plan p, int k) {
 
 // Guess residuals for several poles at once: one buffer and one set of
 // partial sums per pole (allocated on first use, freed with the plan).
-int ensure_guess_buffers(hp_plan p) {
-  if (p->guess_r) return HP_OK;
+int ensure_guess_buffers(hp_plan p, bool prev) {
   const int K = p->d.npoles;
-  HPCHK(hipMalloc(&p->guess_r, (size_t)K * p->fieldn * sizeof(c128)));
-  HPCHK(hipMalloc(&p->guess_part, (size_t)K * p->nopblk * sizeof(double)));
-  HPCHK(hipHostMalloc(&p->guess_part_h, ((size_t)K * p->nopblk + 1) * sizeof(double)));
+  if (!p->guess_r) {
+    HPCHK(hipMalloc(&p->guess_r, (size_t)K * p->fieldn * sizeof(c128)));
+    HPCHK(hipMalloc(&p->guess_part, (size_t)K * p->nopblk * sizeof(double)));
+    HPCHK(hipMalloc(&p->guess_rpart, (size_t)K * p->nrowblk * p->d.ncomp * sizeof(double)));
+    HPCHK(hipHostMalloc(&p->guess_part_h, ((size_t)K * p->nopblk + 1) * sizeof(double)));
+  }
+  if (prev && !p->guess_x) HPCHK(hipMalloc(&p->guess_x, (size_t)K * p->fieldn * sizeof(c128)));
   return HP_OK;
 }
 
@@ -419,19 +424,33 @@ template <typename T, typename C>
 int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, const c128* const* x0,
                        const int* st_first, std::vector<int>& acc, std::vector<char>& done,
                        std::vector<double>& rel) {
-  int rc = ensure_guess_buffers(p);
-  if (rc) return rc;
   const size_t fn = p->fieldn;
   const int nc = (int)cand.size();
-  for (int j = 0; j < nc; ++j) {
-    const int k = cand[j];
-    const c128* xp = x0 ? x0[j] : nullptr;
-    if (!xp) {
-      launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
-      xp = p->tmp1;
+  // previous-step candidates have no explicit guess (a NULL entry): their x0
+  // is S_x^-1 X_k; when all are such, every kernel covers all of them at once
+  bool prev = true;
+  for (int j = 0; j < nc; ++j) prev = prev && !(x0 && x0[j]);
+  int rc = ensure_guess_buffers(p, prev);
+  if (rc) return rc;
+  if (prev) {
+    // previous-step solutions: all candidates in one launch per kernel
+    std::vector<c128> shifts(nc);
+    for (int j = 0; j < nc; ++j) shifts[j] = mk(p->poles[cand[j]].re, p->poles[cand[j]].im);
+    launch_row_inv_batch<double>(p->X, fn, cand.data(), nc, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
+                                 p->stream);
+    launch_apply_op_batch(p->guess_x, fn, w, p->guess_r, fn, p->coef, shifts.data(), nc, p->sc, p->geo,
+                          p->guess_part, p->nopblk, p->stream);
+  } else {
+    for (int j = 0; j < nc; ++j) {
+      const int k = cand[j];
+      const c128* xp = x0 ? x0[j] : nullptr;
+      if (!xp) {
+        launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+        xp = p->tmp1;
+      }
+      launch_apply_op(xp, w, p->guess_r + (size_t)j * fn, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc,
+                      p->geo, p->guess_part + (size_t)j * p->nopblk, p->stream);
     }
-    launch_apply_op(xp, w, p->guess_r + (size_t)j * fn, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc,
-                    p->geo, p->guess_part + (size_t)j * p->nopblk, p->stream);
   }
   HPCHK(hipMemcpyAsync(p->guess_part_h, p->guess_part, (size_t)nc * p->nopblk * sizeof(double),
                        hipMemcpyDeviceToHost, p->stream));
@@ -443,6 +462,7 @@ int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, c
   acc.assign(nc, 0);
   done.assign(nc, 0);
   rel.assign(nc, 0.0);
+  std::vector<int> rs, rj;  // poles that restart from their guess residual, and their slots
   for (int j = 0; j < nc; ++j) {
     const int k = cand[j];
     double s2 = 0.0;
@@ -451,14 +471,42 @@ int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, c
     rel[j] = beta0 > 0 ? r0 / beta0 : 0.0;
     if (!(r0 < beta0)) continue;  // also rejects NaN
     acc[j] = 1;
-    HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
     if (r0 <= p->d.tol * beta0) {
       done[j] = 1;
+      HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
       continue;
     }
-    rc = restart_pole<T, C>(p, k, p->guess_r + (size_t)j * fn);
+    rs.push_back(k);
+    rj.push_back(j);
+  }
+  if (rs.empty()) return HP_OK;
+  // new cycles from the residuals: S_x r0 into each pole's first basis vector,
+  // then one cycle start for all of them (has_x: X_k is the solution so far)
+  const int nr = (int)rs.size();
+  const size_t rblk = (size_t)p->nrowblk * p->d.ncomp;
+  const size_t ustride = (size_t)(p->d.restart + 1) * fn;
+  {
+    Prof pr(p, HP_K_ROW_FWD, nr * (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
+    launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
+                               p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
+  }
+  bool changed = false;
+  for (int k : rs) {
+    void* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
+    if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != u0) {
+      p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
+      changed = true;
+    }
+  }
+  if (changed) {
+    rc = upload_uptr(p);
     if (rc) return rc;
   }
+  int* list_h = p->active_h + 2 * HP_MAXPOLES;  // free after the synchronisation above
+  int* list_d = p->active_d + 2 * HP_MAXPOLES;
+  for (int a = 0; a < nr; ++a) list_h[a] = rs[a];
+  HPCHK(hipMemcpyAsync(list_d, list_h, nr * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, list_d, nr, p->guess_rpart, (int)rblk, 0, p->d.tol, inner_rtol(p), p->stream, rblk, 1);
   return HP_OK;
 }
 
@@ -679,7 +727,9 @@ int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullpt
                     p->geo, p->stream);
   }
   if (p->guess_mode == HP_GUESS_PREV) {  // keep the solutions as the next step's guesses
-    for (int k = 0; k < K; ++k) fold<T>(p, k);
+    launch_accum_batch<T>(p->X, p->fieldn, fld<T>(p->Z, 0, p->fieldn), (size_t)d.restart * p->fieldn, p->fieldn,
+                          p->st, all.data(), K, p->geo, p->stream);
+    launch_mark_folded(p->st, 0, K, p->stream);
     p->prev_valid = true;
   }
   HPCHK(hipGetLastError());
@@ -1077,6 +1127,8 @@ void hp_plan_destroy(hp_plan p) {
   if (p->misc_h) (void)hipHostFree(p->misc_h);
   if (p->guess_r) (void)hipFree(p->guess_r);
   if (p->guess_part) (void)hipFree(p->guess_part);
+  if (p->guess_x) (void)hipFree(p->guess_x);
+  if (p->guess_rpart) (void)hipFree(p->guess_rpart);
   if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->iter_ev)

@@ -125,7 +125,13 @@ __device__ __forceinline__ double edge_loss(int i, int j, int nx, int ny, int W,
 template <typename T, typename C, int N, int TW>
 __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restrict__ in, cx<T>* __restrict__ out,
                                                            double* __restrict__ part, const cx<C>* __restrict__ tw,
-                                                           int ny, size_t fsz, int nblk) {
+                                                           int ny, size_t fsz, int nblk, const PoleList isel,
+                                                           const PoleList osel, size_t in_bs, size_t out_bs,
+                                                           size_t part_bs) {
+  // batch entry z = blockIdx.z: input isel.k[z], output osel.k[z], partial sums z
+  in += (size_t)isel.k[blockIdx.z] * in_bs;
+  out += (size_t)osel.k[blockIdx.z] * out_bs;
+  part += (size_t)blockIdx.z * part_bs;
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, WG = RC::WG, PT = RC::PT;
   __shared__ cx<C> lds[RPW * plen<C>(N)];
@@ -169,7 +175,11 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_fwd(const c128* __restric
 
 template <typename T, typename C, int N, int TW>
 __global__ __launch_bounds__(RowCfg<N>::WG) void k_row_inv(const cx<T>* __restrict__ in, c128* __restrict__ out,
-                                                           const cx<C>* __restrict__ tw, int ny, size_t fsz) {
+                                                           const cx<C>* __restrict__ tw, int ny, size_t fsz,
+                                                           const PoleList sel, size_t in_bs, size_t out_bs) {
+  // batch entry z = blockIdx.z: input entry sel.k[z], output z
+  in += (size_t)sel.k[blockIdx.z] * in_bs;
+  out += (size_t)blockIdx.z * out_bs;
   using RC = RowCfg<N>;
   constexpr int NT = RC::NT, RPW = RC::RPW, PT = RC::PT;
   __shared__ cx<C> lds[RPW * plen<C>(N)];
@@ -869,8 +879,9 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
 
 __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, const int* __restrict__ poles,
                                                    const double* __restrict__ part, int nblk, int first, double tol,
-                                                   double rtol_cycle) {
+                                                   double rtol_cycle, size_t part_bs, int set_has_x) {
   const int k = poles[blockIdx.x];
+  part += (size_t)blockIdx.x * part_bs;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) s += part[b];
   s = wave_sum(s);
@@ -893,6 +904,7 @@ __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, c
   S.g[0] = mk(beta, 0.0);
   S.sigma[0] = (beta > 0.0) ? 1.0 / beta : 0.0;
   S.correct = 0;
+  if (set_has_x) S.has_x = 1;
 }
 
 // ------------------------------------------------------------------ residue-weighted sum and output
@@ -958,7 +970,12 @@ __global__ __launch_bounds__(RowCfg<N>::WG) void k_final(const c128* __restrict_
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_accum(c128* __restrict__ xacc, const cx<T>* __restrict__ z, size_t zsi,
-                                               const PoleState* __restrict__ st, int pole, size_t total) {
+                                               const PoleState* __restrict__ st, const PoleList sel, size_t xsp,
+                                               size_t zsp, size_t total) {
+  // one pole per blockIdx.y: X_k += its cycle's terms
+  const int pole = sel.k[blockIdx.y];
+  xacc += (size_t)pole * xsp;
+  z += (size_t)pole * zsp;
   const int m = st[pole].m;
   const int hx = st[pole].has_x;
   for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
@@ -1000,9 +1017,15 @@ constexpr int OP_LX = OP_TX + 2 * OP_H, OP_LY = OP_TY + 2 * OP_H;
 // pixels of a column of the tile.
 template <int NC>
 __global__ __launch_bounds__(OP_WG) void k_apply_op(const c128* __restrict__ x, const c128* __restrict__ rhs,
-                                                    c128* __restrict__ y, const double* __restrict__ coef, c128 b,
-                                                    StencilCoef sc, int nx, int ny, size_t fsz,
-                                                    double* __restrict__ part, int medium_only) {
+                                                    c128* __restrict__ y, const double* __restrict__ coef,
+                                                    const ShiftList sh, StencilCoef sc, int nx, int ny, size_t fsz,
+                                                    double* __restrict__ part, int medium_only, size_t xbs,
+                                                    size_t ybs, size_t pbs) {
+  // batch entry z = blockIdx.z: field z, shift sh.b[z]
+  const c128 b = sh.b[blockIdx.z];
+  x += (size_t)blockIdx.z * xbs;
+  y += (size_t)blockIdx.z * ybs;
+  if (part) part += (size_t)blockIdx.z * pbs;
   __shared__ c128 tile[NC][OP_LY * OP_LX];
   __shared__ double red[OP_WG / 64];
   const int ntx = (nx + OP_TX - 1) / OP_TX;
@@ -1158,35 +1181,61 @@ int row_blocks(int nx) {
 }
 
 template <typename T, typename C>
-void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<C>* tw, const Geo& g, hipStream_t s,
-                    int tile_w) {
+void launch_row_fwd_batch(const c128* in, size_t in_bs, const int* isel_h, cx<T>* out, size_t out_bs,
+                          const int* osel_h, int n, double* part, size_t part_bs, const cx<C>* tw, const Geo& g,
+                          hipStream_t s, int tile_w) {
   const int rpw = row_blocks<T>(g.nx);
   const int nblk = (g.ny - 1 + rpw - 1) / rpw;
-  dim3 grid(nblk, g.ncomp);
+  dim3 grid(nblk, g.ncomp, n);
   if (tile_w <= 0) tile_w = tile_width<T>();
+  PoleList isel, osel;
+  isel.n = osel.n = n;
+  for (int a = 0; a < HP_MAXPOLES; ++a) {
+    isel.k[a] = a < n ? isel_h[a] : 0;
+    osel.k[a] = a < n ? osel_h[a] : 0;
+  }
 #define L_(NN)                                                                                                    \
   if (tile_w == 8)                                                                                                \
     hipLaunchKernelGGL((k_row_fwd<T, C, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,   \
-                       nblk);                                                                                     \
+                       nblk, isel, osel, in_bs, out_bs, part_bs);                                                        \
   else                                                                                                            \
     hipLaunchKernelGGL((k_row_fwd<T, C, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, part, tw, g.ny, g.fsz,  \
-                       nblk);
+                       nblk, isel, osel, in_bs, out_bs, part_bs);
+  HP_DISPATCH_N(g.nx, L_)
+#undef L_
+}
+
+template <typename T, typename C>
+void launch_row_fwd(const c128* in, cx<T>* out, double* part, const cx<C>* tw, const Geo& g, hipStream_t s,
+                    int tile_w) {
+  const int zero = 0;
+  launch_row_fwd_batch<T, C>(in, 0, &zero, out, 0, &zero, 1, part, 0, tw, g, s, tile_w);
+}
+
+template <typename T, typename C>
+void launch_row_inv_batch(const cx<T>* in, size_t in_bs, const int* sel_h, int n, c128* out, size_t out_bs,
+                          const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s) {
+  const int rpw = row_blocks<T>(g.nx);
+  const int nblk = (g.ny + rpw - 1) / rpw;
+  dim3 grid(nblk, g.ncomp, n);
+  PoleList sel;
+  sel.n = n;
+  for (int a = 0; a < HP_MAXPOLES; ++a) sel.k[a] = a < n ? sel_h[a] : 0;
+#define L_(NN)                                                                                                  \
+  if (tile_w == 8)                                                                                              \
+    hipLaunchKernelGGL((k_row_inv<T, C, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz, sel,  \
+                       in_bs, out_bs);                                                                          \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_row_inv<T, C, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz, sel, \
+                       in_bs, out_bs);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
 
 template <typename T, typename C>
 void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s) {
-  const int rpw = row_blocks<T>(g.nx);
-  const int nblk = (g.ny + rpw - 1) / rpw;
-  dim3 grid(nblk, g.ncomp);
-#define L_(NN)                                                                                                  \
-  if (tile_w == 8)                                                                                              \
-    hipLaunchKernelGGL((k_row_inv<T, C, NN, 8>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);      \
-  else                                                                                                          \
-    hipLaunchKernelGGL((k_row_inv<T, C, NN, 16>), grid, dim3(RowCfg<NN>::WG), 0, s, in, out, tw, g.ny, g.fsz);
-  HP_DISPATCH_N(g.nx, L_)
-#undef L_
+  const int zero = 0;
+  launch_row_inv_batch<T, C>(in, 0, &zero, 1, out, 0, tw, g, tile_w, s);
 }
 
 template <typename T, typename C>
@@ -1273,8 +1322,9 @@ void launch_arnoldi(PoleState* st, const int* active, int nactive, const double*
 }
 
 void launch_cycle_init(PoleState* st, const int* poles, int npoles_in, const double* part, int nblk, int first,
-                       double tol, double rtol_cycle, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_init, dim3(npoles_in), dim3(64), 0, s, st, poles, part, nblk, first, tol, rtol_cycle);
+                       double tol, double rtol_cycle, hipStream_t s, size_t part_bs, int set_has_x) {
+  hipLaunchKernelGGL(k_cycle_init, dim3(npoles_in), dim3(64), 0, s, st, poles, part, nblk, first, tol, rtol_cycle,
+                     part_bs, set_has_x);
 }
 
 template <typename T>
@@ -1291,22 +1341,42 @@ void launch_final(const c128* w, c128* out, const cx<T>* zbase, size_t zsp, size
 }
 
 template <typename T>
+void launch_accum_batch(c128* xacc, size_t xsp, const cx<T>* z, size_t zsp, size_t zsi, const PoleState* st,
+                        const int* sel_h, int n, const Geo& g, hipStream_t s) {
+  const size_t total = (size_t)g.ncomp * g.fsz;
+  PoleList sel;
+  sel.n = n;
+  for (int a = 0; a < HP_MAXPOLES; ++a) sel.k[a] = a < n ? sel_h[a] : 0;
+  const int nb = std::max(1, update_blocks(total) / n);
+  hipLaunchKernelGGL((k_accum<T>), dim3(nb, n), dim3(256), 0, s, xacc, z, zsi, st, sel, xsp, zsp, total);
+}
+
+template <typename T>
 void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, int pole, const Geo& g,
                   hipStream_t s) {
-  const size_t total = (size_t)g.ncomp * g.fsz;
-  hipLaunchKernelGGL((k_accum<T>), dim3(update_blocks(total)), dim3(256), 0, s, xacc, z, zsi, st, pole, total);
+  // xacc and z are pole k's already: a one-entry list with zero strides
+  launch_accum_batch<T>(xacc, 0, z, 0, zsi, st, &pole, 1, g, s);
 }
 
 int op_blocks(const Geo& g) { return ((g.nx + OP_TX - 1) / OP_TX) * ((g.ny + OP_TY - 1) / OP_TY); }
 
+void launch_apply_op_batch(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
+                           const c128* shifts_h, int n, const StencilCoef& sc, const Geo& g, double* part, size_t pbs,
+                           hipStream_t s, int medium_only) {
+  ShiftList sh;
+  for (int a = 0; a < HP_MAXPOLES; ++a) sh.b[a] = a < n ? shifts_h[a] : mk(0.0, 0.0);
+  const dim3 grid(op_blocks(g), 1, n);
+  if (g.ncomp == 2)
+    hipLaunchKernelGGL((k_apply_op<2>), grid, dim3(OP_WG), 0, s, x, rhs, y, coef, sh, sc, g.nx, g.ny, g.fsz, part,
+                       medium_only, xbs, ybs, pbs);
+  else
+    hipLaunchKernelGGL((k_apply_op<1>), grid, dim3(OP_WG), 0, s, x, rhs, y, coef, sh, sc, g.nx, g.ny, g.fsz, part,
+                       medium_only, xbs, ybs, pbs);
+}
+
 void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
                      const Geo& g, double* part, hipStream_t s, int medium_only) {
-  if (g.ncomp == 2)
-    hipLaunchKernelGGL((k_apply_op<2>), dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny,
-                       g.fsz, part, medium_only);
-  else
-    hipLaunchKernelGGL((k_apply_op<1>), dim3(op_blocks(g)), dim3(OP_WG), 0, s, x, rhs, y, coef, b, sc, g.nx, g.ny,
-                       g.fsz, part, medium_only);
+  launch_apply_op_batch(x, 0, rhs, y, 0, coef, &b, 1, sc, g, part, 0, s, medium_only);
 }
 
 void launch_coef(const double* n2, double* coef, double* scratch, double n0, double s_scale, int W,
@@ -1348,12 +1418,18 @@ void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   template void launch_final<T>(const c128*, c128*, const cx<T>*, size_t, size_t, const c128*, size_t,               \
                                 const PoleState*, int, c128, c128, double, double, int, const c128*, const Geo&,     \
                                 hipStream_t);                                                                        \
-  template void launch_accum<T>(c128*, const cx<T>*, size_t, const PoleState*, int, const Geo&, hipStream_t);
+  template void launch_accum<T>(c128*, const cx<T>*, size_t, const PoleState*, int, const Geo&, hipStream_t);      \
+  template void launch_accum_batch<T>(c128*, size_t, const cx<T>*, size_t, size_t, const PoleState*, const int*,     \
+                                      int, const Geo&, hipStream_t);
 
 // storage type T, compute type C of the transforms
 #define HP_INST2(T, C)                                                                                               \
   template void launch_row_fwd<T, C>(const c128*, cx<T>*, double*, const cx<C>*, const Geo&, hipStream_t, int);      \
   template void launch_row_inv<T, C>(const cx<T>*, c128*, const cx<C>*, const Geo&, int, hipStream_t);               \
+  template void launch_row_fwd_batch<T, C>(const c128*, size_t, const int*, cx<T>*, size_t, const int*, int,       \
+                                           double*, size_t, const cx<C>*, const Geo&, hipStream_t, int);             \
+  template void launch_row_inv_batch<T, C>(const cx<T>*, size_t, const int*, int, c128*, size_t, const cx<C>*,       \
+                                           const Geo&, int, hipStream_t);                                            \
   template void launch_col<T, C>(const cx<T>* const*, cx<T>*, size_t, size_t, cx<T>*, size_t, const PoleState*,      \
                                  const int*, int, int*, const double*, const double*, const cx<C>*, const Geo&,      \
                                  const StencilCoef&, hipStream_t);                                                   \

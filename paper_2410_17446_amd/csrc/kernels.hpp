@@ -31,6 +31,17 @@ int row_blocks(int nx);
 // elements per tile row.
 template <typename T, typename C = T>
 void launch_row_inv(const cx<T>* in, c128* out, const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s);
+// Batched forms (index lists are host arrays of n entries): row_fwd entry z
+// reads in + isel[z] in_bs, writes out + osel[z] out_bs and its partial norms
+// to part + z part_bs; row_inv entry z reads in + sel[z] in_bs and writes
+// out + z out_bs.
+template <typename T, typename C = T>
+void launch_row_fwd_batch(const c128* in, size_t in_bs, const int* isel, cx<T>* out, size_t out_bs, const int* osel,
+                          int n, double* part, size_t part_bs, const cx<C>* tw, const Geo& g, hipStream_t s,
+                          int tile_w = 0);
+template <typename T, typename C = T>
+void launch_row_inv_batch(const cx<T>* in, size_t in_bs, const int* sel, int n, c128* out, size_t out_bs,
+                          const cx<C>* tw, const Geo& g, int tile_w, hipStream_t s);
 
 // Column pass: z = sigma_m * S_y diag(1/(mu_y + mu_x - b_k)) S_y u_m for the
 // poles poles[0..nactive) (a host array, passed by value in the kernel
@@ -78,8 +89,10 @@ void launch_arnoldi(PoleState* st, const int* active, int nactive, const double*
 
 // Start a cycle: beta = sqrt(sum part), g = beta e1, sigma_0 = 1/beta.
 // Cycle tolerance on the estimate: max(tol * beta0, rtol_cycle * beta).
+// part_bs: stride between the poles' partial sums (0: all read the same);
+// set_has_x: the poles' X accumulators hold a solution so far.
 void launch_cycle_init(PoleState* st, const int* poles, int npoles_in, const double* part, int nblk, int first,
-                       double tol, double rtol_cycle, hipStream_t s);
+                       double tol, double rtol_cycle, hipStream_t s, size_t part_bs = 0, int set_has_x = 0);
 
 // out = mask * (e^{-iK} r_inf w + e^{-iK} S_x (sum_k a_k [X_k + sum_i y_ki Z_ki])).
 template <typename T>
@@ -91,12 +104,21 @@ void launch_final(const c128* w, c128* out, const cx<T>* zbase, size_t zsp, size
 template <typename T>
 void launch_accum(c128* xacc, const cx<T>* z, size_t zsi, const PoleState* st, int pole, const Geo& g,
                   hipStream_t s);
+// The same for the poles sel[0..n) (host array): X at xacc + k xsp, Z at z + k zsp.
+template <typename T>
+void launch_accum_batch(c128* xacc, size_t xsp, const cx<T>* z, size_t zsp, size_t zsi, const PoleState* st,
+                        const int* sel, int n, const Geo& g, hipStream_t s);
 
 // y = rhs - (Zbar - b I) x  (rhs may be NULL: y = (Zbar - b I) x), explicit
 // 13-point stencils, complex128; partial |y|^2 per block.  medium_only: the
 // medium part P of Zbar alone (V x, plus the psi terms of the vector operator).
 void launch_apply_op(const c128* x, const c128* rhs, c128* y, const double* coef, c128 b, const StencilCoef& sc,
                      const Geo& g, double* part, hipStream_t s, int medium_only = 0);
+// n fields at once: field z at x + z xbs, y + z ybs, partial sums part + z pbs,
+// shift shifts[z] (host array of n <= HP_MAXPOLES).
+void launch_apply_op_batch(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
+                           const c128* shifts, int n, const StencilCoef& sc, const Geo& g, double* part, size_t pbs,
+                           hipStream_t s, int medium_only = 0);
 int op_blocks(const Geo& g);
 
 // Coefficient planes from n^2: V (plane 0) and, for the vector operator,

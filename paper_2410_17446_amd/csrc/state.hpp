@@ -54,3 +54,8 @@ struct PoleList {
   int n;
   int k[HP_MAXPOLES];
 };
+
+// Shifts b_k of the fields of one batched launch of the explicit operator.
+struct ShiftList {
+  c128 b[HP_MAXPOLES];
+};
