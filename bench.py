@@ -20,9 +20,10 @@ counts for the timed launches over their event time.  cpu_baseline times the CPU
 oracle on a bounded sample of the same workload.
 
 Other workloads (--config): batch64 (64 independent propagations of uneven
-sizes run concurrently) and learned (a U-Net trained on the GPU from the
+sizes run concurrently), learned (a U-Net trained on the GPU from the
 propagator's own solves supplies GMRES starting points; timed against the plain
-method and the previous-step start on scalar1024).
+method and the previous-step start on scalar1024), unet (training steps of that
+U-Net at its training shape) and copy (the HBM reference for the counters).
 """
 from __future__ import annotations
 
@@ -249,6 +250,47 @@ def run_learned(args):
     return 0
 
 
+def run_unet(args):
+    """U-Net training throughput (the learned-guess network, 4 levels, --unet-base channels, 7 inputs,
+    2 outputs) at the training shape: batches of 8 synthetic 256^2 samples (--train-n), one step =
+    forward, reverse pass and Adam update.  FLOPs per step: 3x the forward's multiply-adds x 2
+    (data and weight gradients each cost a forward); roofline against the bf16 matrix-core peak
+    (or the fp32 vector peak with --unet-precision f32)."""
+    import torch
+
+    from paper_2410_17446_amd.unet import HP_UNET_BF16, HP_UNET_F32, UNet
+    levels, base, B, H = 4, args.unet_base, 8, args.train_n
+    prec = HP_UNET_BF16 if args.unet_precision == "bf16" else HP_UNET_F32
+    net = UNet(levels, base, 7, 2, seed=0, precision=prec)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((B, 7, H, H), device="cuda", generator=g)
+    t = torch.randn((B, 2, H, H), device="cuda", generator=g)
+    for _ in range(args.warmup):
+        net.grad(x, t)
+        net.adam(1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.grad(x, t)
+        net.adam(1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    flops = 3 * unet_forward_flops(levels, base, 7, 2, H, H) * B
+    tf = flops / dt / 1e12
+    peak, bound = (2500.0, "mfma") if args.unet_precision == "bf16" else (157.3, "alu")
+    line = {"metric": "U-Net training steps/s (forward + gradients + Adam, batch 8)", "value": 1.0 / dt,
+            "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 operands, f32 accumulate" if args.unet_precision == "bf16" else "f32",
+            "data": "synthetic",
+            "config": {"workload": "unet_train", "levels": levels, "base": base, "batch": B, "grid": H,
+                       "params": net.nparam},
+            "roofline": {"bound": bound, "kernel": "whole training step", "achieved": tf, "peak": peak,
+                         "unit": "TFLOP/s", "frac": tf / peak, "traffic": None}}
+    print(json.dumps(line))
+    return 0
+
+
 def run_copy(args):
     """Reference for HBM counters: `steps` launches of a plain elementwise copy (torch.add(a, 0)) of
     a 1 GiB float64 buffer into another; algorithmic bytes 2 GiB per launch."""
@@ -351,6 +393,8 @@ def main():
         return run_learned(args)
     if args.config == "copy":
         return run_copy(args)
+    if args.config == "unet":
+        return run_unet(args)
     import numpy as np
     import torch
 

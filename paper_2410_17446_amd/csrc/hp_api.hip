@@ -325,33 +325,6 @@ int upload_uptr(hp_plan p) {
   return HP_OK;
 }
 
-// End of a cycle for pole k: fold the cycle into X_k and compute the true
-// residual r = w - A_k x_k in FP64 (x_k = S_x X_k).  Leaves r in tmp2 and
-// returns ||r|| in *res.
-template <typename T>
-int true_residual(hp_plan p, int k, const c128* w, double* res) {
-  const size_t fn = p->fieldn;
-  const double U1 = (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp;
-  {
-  Prof pr(p, HP_K_RESIDUAL, U1 * (sizeof(cx<T>) * (double)p->m_h[k] + 16.0 * 7));
-  launch_accum<T>(p->X + (size_t)k * fn, fld<T>(p->Z, (size_t)k * p->d.restart, fn), fn, p->st, k, p->geo,
-                  p->stream);
-  // X_k now holds the whole solution; the cycle's own terms are folded in
-  static const int one = 1, zero = 0;
-  HPCHK(hipMemcpyAsync(&p->st[k].has_x, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  HPCHK(hipMemcpyAsync(&p->st[k].m, &zero, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_row_inv<double>(p->X + (size_t)k * fn, p->tmp1, p->tw64_x, p->geo, tile_width<T>(), p->stream);
-  launch_apply_op(p->tmp1, w, p->tmp2, p->coef, mk(p->poles[k].re, p->poles[k].im), p->sc, p->geo, p->part_misc,
-                  p->stream);
-  }
-  HPCHK(hipMemcpyAsync(p->misc_h, p->part_misc, p->nopblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HPCHK(hipStreamSynchronize(p->stream));
-  double s = 0.0;
-  for (int b = 0; b < p->nopblk; ++b) s += p->misc_h[b];
-  *res = sqrt(s);
-  return HP_OK;
-}
-
 // Cycle tolerance relative to the cycle's starting residual: complex64
 // transforms stop each cycle at 1e-5 (the FP64 true residual then restarts
 // the solve); with FP64 transforms a cycle runs to tol like FP64 mode.
@@ -361,30 +334,6 @@ double inner_rtol(hp_plan p) { return (p->mixed && !p->mixed64) ? kInnerRtolMixe
 #define HP_BY_PRECISION(p, fn, ...)                                                                   \
   ((p)->mixed ? ((p)->mixed64 ? fn<float, double>(__VA_ARGS__) : fn<float, float>(__VA_ARGS__)) \
               : fn<double, double>(__VA_ARGS__))
-
-// Start a new cycle for pole k from the residual r (physical complex128; tmp2 by default).
-template <typename T, typename C>
-int restart_pole(hp_plan p, int k, const c128* r = nullptr) {
-  const size_t fn = p->fieldn;
-  cx<T>* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
-  {
-    Prof pr(p, HP_K_ROW_FWD, (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
-    launch_row_fwd<T, C>(r ? r : p->tmp2, u0, p->part_misc, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo,
-                      p->stream);
-  }
-  if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != (void*)u0) {
-    p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
-    HPCHK(hipMemcpyAsync(p->uptr + (size_t)k * (HP_MAXM + 1), &p->uptr_h[(size_t)k * (HP_MAXM + 1)], sizeof(void*),
-                         hipMemcpyHostToDevice, p->stream));
-  }
-  int* slot_h = p->active_h + 3 * HP_MAXPOLES - 1;
-  int* slot_d = p->active_d + 3 * HP_MAXPOLES - 1;
-  *slot_h = k;
-  HPCHK(hipMemcpyAsync(slot_d, slot_h, sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, slot_d, 1, p->part_misc, p->nrowblk * p->d.ncomp, 0, p->d.tol, inner_rtol(p),
-                    p->stream);
-  return HP_OK;
-}
 
 // One step: the lockstep Arnoldi iterations of all poles, pipelined one deep:
 // iteration j+1 is enqueued before the flags of iteration j are read, and a
@@ -411,6 +360,84 @@ int ensure_guess_buffers(hp_plan p, bool prev) {
     HPCHK(hipHostMalloc(&p->guess_part_h, ((size_t)K * p->nopblk + 1) * sizeof(double)));
   }
   if (prev && !p->guess_x) HPCHK(hipMalloc(&p->guess_x, (size_t)K * p->fieldn * sizeof(c128)));
+  return HP_OK;
+}
+
+// New cycles for the poles rs[a] from the FP64 residuals held in guess_r slot
+// rj[a]: S_x r into each pole's first basis vector, then one cycle start for
+// all of them (their X_k is the solution so far).
+template <typename T, typename C>
+int restart_from_residuals(hp_plan p, const std::vector<int>& rs, const std::vector<int>& rj) {
+  const size_t fn = p->fieldn;
+  const int nr = (int)rs.size();
+  const size_t rblk = (size_t)p->nrowblk * p->d.ncomp;
+  const size_t ustride = (size_t)(p->d.restart + 1) * fn;
+  {
+    Prof pr(p, HP_K_ROW_FWD, nr * (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
+    launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
+                               p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
+  }
+  bool changed = false;
+  for (int k : rs) {
+    void* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
+    if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != u0) {
+      p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
+      changed = true;
+    }
+  }
+  if (changed) {
+    int rc = upload_uptr(p);
+    if (rc) return rc;
+  }
+  // the list goes through pinned slot 2; the host wrote it only after the
+  // caller's last synchronisation, and no copy from it is pending
+  int* list_h = p->active_h + 2 * HP_MAXPOLES;
+  int* list_d = p->active_d + 2 * HP_MAXPOLES;
+  for (int a = 0; a < nr; ++a) list_h[a] = rs[a];
+  HPCHK(hipMemcpyAsync(list_d, list_h, nr * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  launch_cycle_init(p->st, list_d, nr, p->guess_rpart, (int)rblk, 0, p->d.tol, inner_rtol(p), p->stream, rblk, 1);
+  return HP_OK;
+}
+
+// End of a cycle for the poles chk[a] (one flight): fold each cycle into X_k,
+// then the FP64 true residuals r = w - A_k S_x X_k of all of them (residuals in
+// guess_r slot a) with one synchronisation; res[a] = ||r||, *beta0 = ||w||.
+template <typename T, typename C>
+int check_poles(hp_plan p, const std::vector<int>& chk, const c128* w, int beta_pole, std::vector<double>& res,
+                double* beta0) {
+  int rc = ensure_guess_buffers(p, true);
+  if (rc) return rc;
+  const size_t fn = p->fieldn;
+  const int n = (int)chk.size();
+  const double U1 = (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp;
+  double bytes = 0.0;
+  std::vector<c128> shifts(n);
+  for (int a = 0; a < n; ++a) {
+    bytes += U1 * (sizeof(cx<T>) * (double)p->m_h[chk[a]] + 16.0 * 7);
+    shifts[a] = mk(p->poles[chk[a]].re, p->poles[chk[a]].im);
+  }
+  {
+    Prof pr(p, HP_K_RESIDUAL, bytes);
+    launch_accum_batch<T>(p->X, fn, fld<T>(p->Z, 0, fn), (size_t)p->d.restart * fn, fn, p->st, chk.data(), n,
+                          p->geo, p->stream);
+    launch_mark_list(p->st, chk.data(), n, p->stream);  // X_k now holds the whole solution
+    launch_row_inv_batch<double>(p->X, fn, chk.data(), n, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
+                                 p->stream);
+    launch_apply_op_batch(p->guess_x, fn, w, p->guess_r, fn, p->coef, shifts.data(), n, p->sc, p->geo,
+                          p->guess_part, p->nopblk, p->stream);
+  }
+  HPCHK(hipMemcpyAsync(p->guess_part_h, p->guess_part, (size_t)n * p->nopblk * sizeof(double),
+                       hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipMemcpyAsync(p->guess_part_h + (size_t)n * p->nopblk, &p->st[beta_pole].beta0, sizeof(double),
+                       hipMemcpyDeviceToHost, p->stream));
+  HPCHK(hipStreamSynchronize(p->stream));
+  res.assign(n, 0.0);
+  for (int a = 0; a < n; ++a) {
+    double s2 = 0.0;
+    for (int b = 0; b < p->nopblk; ++b) s2 += p->guess_part_h[(size_t)a * p->nopblk + b];
+    res[a] = sqrt(s2);
+  }
+  *beta0 = p->guess_part_h[(size_t)n * p->nopblk];
   return HP_OK;
 }
 
@@ -479,35 +506,7 @@ int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, c
     rs.push_back(k);
     rj.push_back(j);
   }
-  if (rs.empty()) return HP_OK;
-  // new cycles from the residuals: S_x r0 into each pole's first basis vector,
-  // then one cycle start for all of them (has_x: X_k is the solution so far)
-  const int nr = (int)rs.size();
-  const size_t rblk = (size_t)p->nrowblk * p->d.ncomp;
-  const size_t ustride = (size_t)(p->d.restart + 1) * fn;
-  {
-    Prof pr(p, HP_K_ROW_FWD, nr * (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
-    launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
-                               p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
-  }
-  bool changed = false;
-  for (int k : rs) {
-    void* u0 = fld<T>(p->U, (size_t)k * (p->d.restart + 1), fn);
-    if (p->uptr_h[(size_t)k * (HP_MAXM + 1)] != u0) {
-      p->uptr_h[(size_t)k * (HP_MAXM + 1)] = u0;
-      changed = true;
-    }
-  }
-  if (changed) {
-    rc = upload_uptr(p);
-    if (rc) return rc;
-  }
-  int* list_h = p->active_h + 2 * HP_MAXPOLES;  // free after the synchronisation above
-  int* list_d = p->active_d + 2 * HP_MAXPOLES;
-  for (int a = 0; a < nr; ++a) list_h[a] = rs[a];
-  HPCHK(hipMemcpyAsync(list_d, list_h, nr * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, list_d, nr, p->guess_rpart, (int)rblk, 0, p->d.tol, inner_rtol(p), p->stream, rblk, 1);
-  return HP_OK;
+  return rs.empty() ? HP_OK : restart_from_residuals<T, C>(p, rs, rj);
 }
 
 template <typename T, typename C>
@@ -664,6 +663,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     q.erase(q.begin());
     HPCHK(hipEventSynchronize(p->iter_ev[f.slot]));
     const int* fl = p->flags_h + f.slot * HP_MAXPOLES;
+    std::vector<int> chk;  // poles whose cycle ended and whose true residual decides
     for (int k : f.poles) {
       if (!live[k] || f.iter < since[k]) continue;
       const int flag = fl[k];
@@ -675,27 +675,32 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
         p->relres[k] = -1.0;
         continue;
       }
-      // cycle ended without convergence (2), mixed precision, or flag 3: the
-      // true residual decides, and a new cycle starts from it if needed
-      if (beta0 < 0) {
-        HPCHK(hipMemcpyAsync(p->misc_h, &p->st[0].beta0, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-        HPCHK(hipStreamSynchronize(p->stream));
-        beta0 = p->misc_h[0];
-      }
+      // cycle ended without convergence (2), mixed precision, or flag 3
       p->m_h[k] = done_m[k];
-      double res = 0.0;
-      int rc = true_residual<T>(p, k, w, &res);
-      if (rc) return rc;
+      chk.push_back(k);
+    }
+    if (chk.empty()) continue;
+    std::vector<double> res;
+    int rc = check_poles<T, C>(p, chk, w, subset[0], res, &beta0);
+    if (rc) return rc;
+    std::vector<int> rs, rj;  // poles that start a new cycle from their residual
+    for (size_t a = 0; a < chk.size(); ++a) {
+      const int k = chk[a];
       done_m[k] = 0;
-      const double rel = beta0 > 0 ? res / beta0 : 0.0;
+      const double rel = beta0 > 0 ? res[a] / beta0 : 0.0;
       p->relres[k] = rel;
       if (rel <= d.tol) continue;
       if (++cycles[k] >= d.max_cycles) {
         noconv = true;
         continue;
       }
-      rc = restart_pole<T, C>(p, k);
-      if (rc) return rc;
+      rs.push_back(k);
+      rj.push_back((int)a);
+    }
+    if (rs.empty()) continue;
+    rc = restart_from_residuals<T, C>(p, rs, rj);
+    if (rc) return rc;
+    for (int k : rs) {
       live[k] = 1;
       since[k] = next_iter;
     }

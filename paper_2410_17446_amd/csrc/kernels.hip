@@ -1149,6 +1149,13 @@ __global__ void k_mark_folded(PoleState* __restrict__ st, int first, int count) 
   }
 }
 
+__global__ void k_mark_list(PoleState* __restrict__ st, const PoleList sel) {
+  if ((int)threadIdx.x < sel.n) {
+    st[sel.k[threadIdx.x]].has_x = 1;
+    st[sel.k[threadIdx.x]].m = 0;
+  }
+}
+
 __global__ void k_fill_zero(c128* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = mk(0.0, 0.0);
@@ -1389,6 +1396,13 @@ void launch_coef(const double* n2, double* coef, double* scratch, double n0, dou
     hipLaunchKernelGGL(k_coef_c, dim3(nb), dim3(256), 0, s, scratch, scratch + g.fsz, coef, s_scale, sc, W, g.nx,
                        g.ny, g.fsz);
   }
+}
+
+void launch_mark_list(PoleState* st, const int* poles, int n, hipStream_t s) {
+  PoleList sel;
+  sel.n = n;
+  for (int a = 0; a < HP_MAXPOLES; ++a) sel.k[a] = a < n ? poles[a] : 0;
+  hipLaunchKernelGGL(k_mark_list, dim3(1), dim3(HP_MAXPOLES), 0, s, st, sel);
 }
 
 void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s) {

@@ -129,6 +129,8 @@ void launch_coef(const double* n2, double* coef, double* scratch, double n0, dou
 // Poles first..first+count-1 (count <= HP_MAXPOLES): has_x = 1, m = 0 (their
 // X accumulators now hold the whole solution).
 void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s);
+// The same for the poles poles[0..n) (host array, n <= HP_MAXPOLES).
+void launch_mark_list(PoleState* st, const int* poles, int n, hipStream_t s);
 
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);
 void launch_to_float(const double* a, float* b, size_t n, hipStream_t s);
