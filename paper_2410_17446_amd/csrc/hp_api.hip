@@ -69,8 +69,11 @@ struct hp_plan_s {
   double* part_norm = nullptr;
   double* part_misc = nullptr;
   // host
-  int* flags_h = nullptr;   // pinned
-  int* flags_hd = nullptr;  // its device address (k_arnoldi writes the flags there)
+  // per slot and pole: (round << 8) | flag, written by k_arnoldi into
+  // host-coherent pinned memory and polled by the host
+  unsigned long long* ftag_h = nullptr;
+  unsigned long long* ftag_hd = nullptr;  // its device address
+  unsigned long long seq = 0;             // rounds launched (the tags)
   double* est_h = nullptr;
   int* active_h = nullptr;
   double* misc_h = nullptr;
@@ -99,7 +102,6 @@ struct hp_plan_s {
   double prof_ms[HP_K_COUNT]{}, prof_b[HP_K_COUNT]{};
   std::vector<int> m_h;  // Arnoldi columns per pole (host mirror)
   std::vector<double> incons;  // eps kappa(M_k) per pole
-  hipEvent_t iter_ev[2] = {nullptr, nullptr};
   c128 phase{}, rinf_phase{};  // e^{-iK}, e^{-iK} r_inf
   double loss_coef = 0.0;      // k0 dz / (2 n0)
   std::string err;
@@ -560,6 +562,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     std::vector<int> poles;
     int slot;
     long iter;
+    unsigned long long seq;  // tag of the round's flags
   };
   // initial guesses (explicit, or the previous step's solutions held in X)
   p->accepted.assign(K, 0);
@@ -629,12 +632,11 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     }
     {
       Prof pr(p, HP_K_SMALL, 0.0);
-      // flags go straight to pinned host memory (read after the event below)
-      launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->flags_hd + slot * HP_MAXPOLES, p->est_d,
-                     p->stream);
+      // flags go straight to host memory, tagged with the round
+      launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->ftag_hd + slot * HP_MAXPOLES, ++p->seq,
+                     p->est_d, p->stream);
     }
-    HPCHK(hipEventRecord(p->iter_ev[slot], p->stream));
-    q.push_back(Flight{poles, slot, next_iter});
+    q.push_back(Flight{poles, slot, next_iter, p->seq});
     ++next_iter;
     return HP_OK;
   };
@@ -661,12 +663,28 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     }
     Flight f = q.front();
     q.erase(q.begin());
-    HPCHK(hipEventSynchronize(p->iter_ev[f.slot]));
-    const int* fl = p->flags_h + f.slot * HP_MAXPOLES;
+    // wait for the round's tags of the poles read below (every one of them
+    // takes the step, so its k_arnoldi block writes the tag); should they not
+    // arrive within a second the stream is drained and they must be there
+    const volatile unsigned long long* ft = p->ftag_h + f.slot * HP_MAXPOLES;
+    {
+      const auto t0 = std::chrono::steady_clock::now();
+      bool drained = false;
+      for (int k : f.poles) {
+        if (!live[k] || f.iter < since[k]) continue;
+        while ((ft[k] >> 8) != f.seq) {
+          if (drained) return fail(p, HP_EHIP, "round flags did not reach host memory");
+          if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+            HPCHK(hipStreamSynchronize(p->stream));
+            drained = true;
+          }
+        }
+      }
+    }
     std::vector<int> chk;  // poles whose cycle ended and whose true residual decides
     for (int k : f.poles) {
       if (!live[k] || f.iter < since[k]) continue;
-      const int flag = fl[k];
+      const int flag = (int)(ft[k] & 0xff);
       if (flag == 0) continue;
       live[k] = 0;
       done_m[k] = (int)(f.iter - since[k] + 1);
@@ -877,20 +895,19 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
   w.base = p->ws;
   w.dry = false;
   layout(p, w);
-  if (hipHostMalloc(&p->flags_h, 2 * HP_MAXPOLES * sizeof(int)) != hipSuccess ||
+  if (hipHostMalloc(&p->ftag_h, 2 * HP_MAXPOLES * sizeof(unsigned long long),
+                    hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc(&p->est_h, HP_MAXPOLES * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&p->active_h, 3 * HP_MAXPOLES * sizeof(int)) != hipSuccess ||
-      hipEventCreateWithFlags(&p->iter_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->iter_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(&p->misc_h, (std::max(p->nopblk, p->nrowblk * 2) + 64) * sizeof(double)) != hipSuccess) {
     hp_plan_destroy(p);
     return fail(nullptr, HP_ENOMEM, "pinned host allocation failed");
   }
-  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&p->flags_hd), p->flags_h, 0) != hipSuccess) {
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&p->ftag_hd), p->ftag_h, 0) != hipSuccess) {
     hp_plan_destroy(p);
     return fail(nullptr, HP_EHIP, "no device address for the pinned flag buffer");
   }
-  memset(p->flags_h, 0, 2 * HP_MAXPOLES * sizeof(int));
+  memset(p->ftag_h, 0, 2 * HP_MAXPOLES * sizeof(unsigned long long));
   int rc = (p->mixed && !p->mixed64) ? upload_tables<float>(p) : upload_tables<double>(p);
   if (rc) {
     g_thread_error = p->err;
@@ -1126,7 +1143,7 @@ void hp_plan_destroy(hp_plan p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   if (p->own_ws && p->ws) (void)hipFree(p->ws);
-  if (p->flags_h) (void)hipHostFree(p->flags_h);
+  if (p->ftag_h) (void)hipHostFree(p->ftag_h);
   if (p->est_h) (void)hipHostFree(p->est_h);
   if (p->active_h) (void)hipHostFree(p->active_h);
   if (p->misc_h) (void)hipHostFree(p->misc_h);
@@ -1136,8 +1153,6 @@ void hp_plan_destroy(hp_plan p) {
   if (p->guess_rpart) (void)hipFree(p->guess_rpart);
   if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : p->iter_ev)
-    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 

@@ -736,7 +736,8 @@ __device__ void upper_solve(const c128* __restrict__ R, const c128* rhs, c128* x
 
 __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, const int* __restrict__ active,
                                                 const double* __restrict__ part, int nblk, int restart,
-                                                int* __restrict__ flags, double* __restrict__ ests) {
+                                                unsigned long long* __restrict__ ftag, unsigned long long seq,
+                                                double* __restrict__ ests) {
   __shared__ c128 c1[HP_MAXM + 2], c2[HP_MAXM + 2], sn[HP_MAXM], rhs[HP_MAXM + 1], y[HP_MAXM];
   __shared__ double cs[HP_MAXM];
   __shared__ int flag_s;
@@ -872,8 +873,12 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
   }
   if (tid == 0) {
     S.flag = flag;
-    flags[k] = flag;
     ests[k] = S.est;
+    // the round's tag and the flag in one 8-byte system-scope store to host
+    // memory, which the host polls (no event per round); the host reads
+    // nothing else of this round before a synchronisation, so no release
+    __hip_atomic_store(&ftag[k], (seq << 8) | (unsigned long long)flag, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1324,8 +1329,8 @@ void launch_update(const cx<T>* pbase, size_t psp, cx<T>* const* uptr, const Pol
 }
 
 void launch_arnoldi(PoleState* st, const int* active, int nactive, const double* part, int nblk, int restart,
-                    int* flags, double* est, hipStream_t s) {
-  hipLaunchKernelGGL(k_arnoldi, dim3(nactive), dim3(64), 0, s, st, active, part, nblk, restart, flags, est);
+                    unsigned long long* ftag, unsigned long long seq, double* est, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi, dim3(nactive), dim3(64), 0, s, st, active, part, nblk, restart, ftag, seq, est);
 }
 
 void launch_cycle_init(PoleState* st, const int* poles, int npoles_in, const double* part, int nblk, int first,

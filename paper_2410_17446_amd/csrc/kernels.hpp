@@ -84,8 +84,11 @@ int update_blocks(size_t total);
 
 // Hessenberg column, Givens rotation, residual estimate, convergence flag and
 // the least-squares solution at the end of a cycle.
+// ftag[k] = (seq << 8) | flag for every pole that takes the step (flag 0: going
+// on, 1: converged, 2: restart length reached, 3: the true residual decides),
+// stored with system scope to host-coherent memory.
 void launch_arnoldi(PoleState* st, const int* active, int nactive, const double* part, int nblk, int restart,
-                    int* flags, double* est, hipStream_t s);
+                    unsigned long long* ftag, unsigned long long seq, double* est, hipStream_t s);
 
 // Start a cycle: beta = sqrt(sum part), g = beta e1, sigma_0 = 1/beta.
 // Cycle tolerance on the estimate: max(tol * beta0, rtol_cycle * beta).
