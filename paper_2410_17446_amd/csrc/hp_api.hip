@@ -65,6 +65,7 @@ struct hp_plan_s {
   void** uptr_scratch = nullptr;
   int* active_d = nullptr;
   double* est_d = nullptr;
+  int* reduce_done = nullptr;  // per pole: finished reduction workgroups of the round (zeroed workspace)
   double2* part_dots = nullptr;
   double* part_norm = nullptr;
   double* part_misc = nullptr;
@@ -207,6 +208,7 @@ void layout(hp_plan p, Ws& w) {
   p->X = w.take<c128>((size_t)K * fn);
   p->tmp1 = w.take<c128>(fn);
   p->tmp2 = w.take<c128>(fn);
+  p->reduce_done = w.take<int>(HP_MAXPOLES);  // inside the range cleared at creation
   p->st = w.take<PoleState>(K);
   p->st_scratch = w.take<PoleState>(1);
   p->uptr = w.take<void*>((size_t)K * (HP_MAXM + 1));
@@ -623,7 +625,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     }
     {
       Prof pr(p, HP_K_SMALL, 0.0);
-      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->stream);
+      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->reduce_done, p->stream);
     }
     {
       Prof pr(p, HP_K_UPDATE, U1 * es * (sum_m + 3.0 * na));

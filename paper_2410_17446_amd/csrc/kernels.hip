@@ -579,47 +579,11 @@ __global__ __launch_bounds__(UPD_WG) void k_update(const cx<T>* __restrict__ pba
 // expressed as coefficients of the stored vectors for the update kernel.
 // <u_i, p> and <u_i, u_m>: one block per (i, slot) pair sums the row pass's
 // partials in a fixed order.
-__global__ __launch_bounds__(256) void k_reduce_pairs(const double2* __restrict__ part, int nparts,
-                                                      PoleState* __restrict__ st, const int* __restrict__ active) {
-  __shared__ double red[4];
-  const int k = active[blockIdx.y];
-  if (st[k].flag) return;
-  const int m = st[k].m;
-  const int i = blockIdx.x >> 1, slot = blockIdx.x & 1;
-  if (i > m) return;
-  const double2* src = part + (((size_t)k * (HP_MAXM + 1) + i) * 2 + slot) * nparts;
-  double re = 0.0, im = 0.0;
-  {
-    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    int b = threadIdx.x;
-    for (; b + 3 * 256 < nparts; b += 4 * 256) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 v = src[b + u * 256];
-        ar[u] += v.x;
-        ai[u] += v.y;
-      }
-    }
-    for (; b < nparts; b += 256) {
-      ar[0] += src[b].x;
-      ai[0] += src[b].y;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      re += ar[u];
-      im += ai[u];
-    }
-  }
-  re = block_sum<256>(re, red);
-  im = block_sum<256>(im, red);
-  if (threadIdx.x == 0) (slot ? st[k].Qd : st[k].Pd)[i] = mk(re, im);
-}
-
-__global__ __launch_bounds__(256) void k_prep(PoleState* __restrict__ st, const int* __restrict__ active) {
+// The correction algebra of pole k's step from its reduced inner products
+// (run by the last reduction workgroup of the pole, 256 threads).
+__device__ __forceinline__ void prep_pole(PoleState* __restrict__ st, int k) {
   __shared__ c128 P[HP_MAXM + 1], Q[HP_MAXM + 1];
   __shared__ c128 sv[HP_MAXM], cc[HP_MAXM + 1], h[HP_MAXM + 1];
-  const int k = active[blockIdx.x];
-  if (st[k].flag) return;
   const int m = st[k].m;
   for (int i = threadIdx.x; i <= m; i += 256) {
     P[i] = st[k].Pd[i];
@@ -693,6 +657,55 @@ __global__ __launch_bounds__(256) void k_prep(PoleState* __restrict__ st, const 
       S.correct = 1;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double2* __restrict__ part, int nparts,
+                                                      PoleState* __restrict__ st, const int* __restrict__ active,
+                                                      int* __restrict__ done) {
+  __shared__ double red[4];
+  __shared__ int last;
+  const int k = active[blockIdx.y];
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  const int i = blockIdx.x >> 1, slot = blockIdx.x & 1;
+  if (i > m) return;
+  const double2* src = part + (((size_t)k * (HP_MAXM + 1) + i) * 2 + slot) * nparts;
+  double re = 0.0, im = 0.0;
+  {
+    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    int b = threadIdx.x;
+    for (; b + 3 * 256 < nparts; b += 4 * 256) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 v = src[b + u * 256];
+        ar[u] += v.x;
+        ai[u] += v.y;
+      }
+    }
+    for (; b < nparts; b += 256) {
+      ar[0] += src[b].x;
+      ai[0] += src[b].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      re += ar[u];
+      im += ai[u];
+    }
+  }
+  re = block_sum<256>(re, red);
+  im = block_sum<256>(im, red);
+  // the last of the pole's 2 (m + 1) workgroups (counted in done[k], which it
+  // clears again) continues with the correction algebra
+  if (threadIdx.x == 0) {
+    (slot ? st[k].Qd : st[k].Pd)[i] = mk(re, im);
+    __threadfence();
+    last = atomicAdd(&done[k], 1) == 2 * (m + 1) - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  if (threadIdx.x == 0) done[k] = 0;
+  __threadfence();
+  prep_pole(st, k);
 }
 
 __device__ __forceinline__ void givens(c128 a, double b, double& c, c128& sn, c128& r) {
@@ -1309,9 +1322,8 @@ void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* d
 }
 
 void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int* active, int nactive, int maxm,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_pairs, dim3(2 * (maxm + 1), nactive), dim3(256), 0, s, part, nblk, st, active);
-  hipLaunchKernelGGL(k_prep, dim3(nactive), dim3(256), 0, s, st, active);
+                        int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(2 * (maxm + 1), nactive), dim3(256), 0, s, part, nblk, st, active, done);
 }
 
 int update_blocks(size_t total) {

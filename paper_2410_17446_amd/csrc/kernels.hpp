@@ -72,9 +72,11 @@ constexpr int tile_width() {
   return 128 / (int)sizeof(cx<T>);
 }
 
-// hc_i = sigma_i * sum of the partial inner products.
+// hc_i = sigma_i * sum of the partial inner products, then (in the same
+// launch, by each pole's last workgroup) the correction algebra that gives the
+// update coefficients.  done: HP_MAXPOLES device counters, zero between calls.
 void launch_reduce_dots(const double2* part, int nblk, PoleState* st, const int* active, int nactive, int maxm,
-                        hipStream_t s);
+                        int* done, hipStream_t s);
 
 // u_{m+1} = p - sum_i hc_i v_i and partial |u_{m+1}|^2.
 template <typename T>
