@@ -36,9 +36,12 @@
  * tensor's storage).  The caller owns inputs, outputs and (when given) the
  * workspace; the plan copies the pole/residue table and stencils at create.
  * All calls are asynchronous on the plan's stream except where stated; the
- * GMRES driver synchronises the stream once per Arnoldi step to read the
- * convergence flags.  A plan is not re-entrant; different plans may run on
- * different streams.  No call falls back to the CPU.
+ * GMRES driver keeps one Arnoldi step in flight ahead of the one whose
+ * convergence flags it reads (the flags are written by the device into
+ * host-coherent pinned memory and polled, no event per step), and
+ * synchronises the stream when cycles end to read FP64 true residuals.  A plan
+ * is not re-entrant; different plans may run on different streams.  No call
+ * falls back to the CPU.
  *
  * Errors: a negative return means nothing valid was written; a positive
  * return is a warning with the output written.  hp_last_error() gives a

@@ -273,6 +273,7 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
   // from row 0, so that every 16 threads touch one aligned run of rows:
   // thread tid takes column c = tid % GC, rows r0 + i NT (i = 0..7).
   const int c = tid % GC, r0 = tid / GC, q = col0 + c0 + c;
+  const double mq = mu_x[q] - b.re, li = -b.im;
   cx<C>* bc = lds + c * PL;
   const PStep<C, NT> at(r0);
   {
@@ -292,9 +293,8 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
         continue;
       }
       const cx<C> X = scale * bc[at(i)];
-      const double lr = mu_y[p] + mu_x[q] - b.re, li = -b.im;
-      const double den = lr * lr + li * li;
-      bc[at(i)] = X * mk<C>((C)(lr / den), (C)(-li / den));
+      const double lr = mu_y[p] + mq, inv = 1.0 / (lr * lr + li * li);  // one FP64 division
+      bc[at(i)] = X * mk<C>((C)(lr * inv), (C)(-li * inv));
     }
     __syncthreads();
     dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
