@@ -339,3 +339,72 @@ def test_largest_pole_count():
     _, rr = plan.stats()
     assert max(rr) <= 1e-10
     assert rel_l2(out.cpu().numpy(), ref) < 1e-8
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_z_dependent_rotated_sine_medium(ncomp):
+    """A medium that changes every step (the rotated sine product of Sec. 5, n0 = 1.2,
+    dn = 0.025, dz = lambda/4): hp_propagate with one n^2 plane per step (stride N^2) equals
+    set_medium + step per step bit for bit, and stepping with the oracle's per-step coefficients
+    (iteration counts replayed) agrees to 1e-10."""
+    torch = _cuda()
+    from oracle import fit, stencil
+    from paper_2410_17446_amd import hp
+    N, dx, dz, n0, S, W, npoles = 64, 0.25, 0.25, 1.2, 3, 8, 8
+    stack = np.stack([inputs.rotated_sine_n2(N, dx, s * dz, n0=n0) for s in range(S)])
+    c, d = stencil.stencils()
+    f = fit.fit_exp_sqrt(inputs.K0 * n0 * dz, npoles)
+    w0 = inputs.gaussian_beam(N, dx, 3.0, ncomp)
+    mk = lambda: hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=inputs.K0, n0=n0, dz=dz, ncomp=ncomp,
+                         poles=f["poles"], residues=f["residues"], r_inf=f["r_inf"], d2=c, d1=d,
+                         edge_width=W, edge_eta=0.25, tol=1e-10, restart=30, max_cycles=20)
+    plan = mk()
+    out_p = plan.propagate(to_gpu(w0), S, n2=to_gpu(stack), n2_step_stride=N * N)
+    wg = to_gpu(w0)
+    for s in range(S):
+        plan.set_medium(to_gpu(stack[s]))
+        wg = plan.step(wg)
+    assert bool((out_p == wg).all())
+    g = op.Grid(N=N, dx=dx, dy=dx, k0=inputs.K0, n0=n0, c=c, d=d, W=W, eta_max=0.25)
+    pf = st.PFTable(f["poles"], f["residues"], f["r_inf"])
+    plan = mk()
+    wo, wg = w0.copy(), to_gpu(w0)
+    for s in range(S):
+        co = op.coefficients(g, stack[s], ncomp == 2)
+        wo, stats = st.step(g, co, wo, pf, dz, 1e-10)
+        plan.set_fixed_iters([sum(cy) for cy in stats.cycle_iters])
+        plan.set_medium(to_gpu(stack[s]))
+        wg = plan.step(wg)
+    assert rel_l2(wg.cpu().numpy(), wo) < 1e-10
+
+
+def test_beam_converges_with_the_number_of_terms():
+    """Physics check with a closed form only: in a homogeneous, lossless medium the step is
+    diagonal in the DST basis, with the exact factor e^{-iK} exp(iK sqrt(1 + zeta)) on the
+    eigenvalues zeta = mu_p + mu_q of the discrete operator (the evanescent branch
+    exp(-K sqrt(-1 - zeta)) below -1; Sec. 3).  The GPU step's error against it falls as the
+    rational approximation gains terms (8, 12, 16, 20) and ends at the fit's accuracy."""
+    torch = _cuda()
+    from oracle import fit, stencil
+    from paper_2410_17446_amd import hp
+    N, dx, dz, W = 128, 0.25, 1.0, 8
+    K = inputs.K0 * dz
+    c, d = stencil.stencils()
+    g = op.Grid(N=N, dx=dx, dy=dx, k0=inputs.K0, n0=1.0, c=c, d=d, W=W, eta_max=0.0)
+    w = inputs.gaussian_beam(N, dx, 2.0)
+    zeta = precond.spectrum(g)
+    t = precond.dst2(w)
+    t[0, 1:, 1:] *= np.exp(-1j * K) * fit.target(zeta, K)
+    ref = precond.dst2(t)
+    errs = []
+    for npoles in (8, 12, 16, 20):
+        f = fit.fit_exp_sqrt(K, npoles)
+        plan = hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=inputs.K0, n0=1.0, dz=dz, ncomp=1, poles=f["poles"],
+                       residues=f["residues"], r_inf=f["r_inf"], d2=c, d1=d, edge_width=W, edge_eta=0.0,
+                       tol=1e-12, restart=30, max_cycles=20)
+        out = plan.step(to_gpu(w), to_gpu(np.ones((N, N))))
+        errs.append(rel_l2(out.cpu().numpy(), ref))
+        plan.close()
+    print("relative error by number of terms:", errs)
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-6
