@@ -17,6 +17,8 @@ precond   free-space preconditioner as a Sylvester solve diagonalised by DST-I
 gmres     right-preconditioned GMRES with Householder Arnoldi (Sec. 4.2)
 step      one propagation step and a propagation loop (Sec. 2 eqs. Wk_define,
           approx_prop, W_k_def)
+sqrt_form pseudo-differential form: Cauchy-integral partial fractions of
+          sqrt(1+z) (Sec. 3.2, Appendix A) and an RK4 integrator in z
 physics   closed forms used as pins (Sec. 3 eq. exp_prop_planewave,
           Sec. 5.2 eq. eq_ft_gaussian)
 """
