@@ -160,6 +160,38 @@ int hp_step_guess(hp_plan plan, const void* E_in, const double* n2, const void* 
 enum { HP_GUESS_ZERO = 0, HP_GUESS_PREV = 1 };
 int hp_set_guess(hp_plan plan, int mode);
 
+/* What a step does with the pole table.
+ *
+ * HP_FORM_EXP (default): the table is the partial-fraction form of a rational
+ * approximation of exp(iK sqrt(1+z)), K = k0 n0 dz, and a step is the
+ * exponential-operator step of Sec. 2 eq. approx_prop.
+ *
+ * HP_FORM_SQRT: the table approximates sqrt(1+z) (for example the
+ * Cauchy-integral / Gauss-Jacobi partial fractions of Sec. 3.2 and Appendix A,
+ * r_inf = c_alpha + sum wt_j, b_j = -(1 + i alpha sigma_j),
+ * a_j = -i alpha wt_j (1 + sigma_j)), and a step integrates the
+ * pseudo-differential form of the propagator, Sec. 2 eq. eq_barZfactor2,
+ *     dw/dz = i k0 n0 (r(Zbar) - 1) w,
+ * over dz with `substeps` (1..1024) classical fourth-order Runge-Kutta steps of
+ * h = dz / substeps.  Each RK stage is one solve of every pole (eq.
+ * Auxiliary_W) with the same GMRES, tolerance and restarts as the exponential
+ * form, so a step costs 4 * substeps lockstep solves.  The edge layer's loss is
+ * applied after every substep (factor exp(-k0 h eta / (2 n0))).  hp_get_stats
+ * then sums each pole's iterations over the step's stages.  The paper does not
+ * fix the z-integrator: RK4 is this library's choice.  The first call
+ * allocates three complex128 fields (hipMalloc), freed with the plan; the
+ * previous-step guesses of HP_GUESS_PREV are dropped, and hp_step_guess
+ * returns HP_ESTATE while the form is HP_FORM_SQRT.
+ *
+ * Returns HP_WARN_UNSTABLE (form still set) when one substep amplifies some
+ * free-space mode: max over the free-space spectrum of |P(h i k0 n0 (r(mu) - 1))|
+ * > 1 + 1e-6, P(z) = 1 + z + z^2/2 + z^3/6 + z^4/24.  hp_plan_create's own
+ * check measures |r| against 1, which a table of sqrt(1+z) exceeds by design,
+ * so for such a table its HP_WARN_UNSTABLE is expected and this check is the
+ * one that applies.  HP_EINVAL for an unknown form or substeps out of range. */
+enum { HP_FORM_EXP = 0, HP_FORM_SQRT = 1 };
+int hp_set_form(hp_plan plan, int form, int substeps);
+
 /* x_k of the last step, guess step or solve for pole k (Sec. 2 eq. W_k_def):
  * device [ncomp][ny][nx] complex128.  Synchronous. */
 int hp_get_solution(hp_plan plan, int pole, void* x);

@@ -105,6 +105,9 @@ struct hp_plan_s {
   std::vector<double> incons;  // eps kappa(M_k) per pole
   c128 phase{}, rinf_phase{};  // e^{-iK}, e^{-iK} r_inf
   double loss_coef = 0.0;      // k0 dz / (2 n0)
+  int form = HP_FORM_EXP;      // what the pole table approximates and how a step uses it
+  int substeps = 1;            // RK4 substeps per step (pseudo-differential form)
+  c128* rk = nullptr;          // stage result, stage input, running sum (allocated by hp_set_form)
   std::string err;
 };
 
@@ -515,7 +518,7 @@ int start_from_guesses(hp_plan p, const std::vector<int>& cand, const c128* w, c
 
 template <typename T, typename C>
 int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* noconv_out,
-              const c128* const* x0 = nullptr, bool use_prev = false) {
+              const c128* const* x0 = nullptr, bool use_prev = false, int first = 1) {
   const hp_plan_desc& d = p->d;
   const size_t fn = p->fieldn;
   const int K = d.npoles, M = d.restart;
@@ -546,7 +549,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   const int ns = (int)subset.size();
   for (int a = 0; a < ns; ++a) act0[a] = subset[a];
   HPCHK(hipMemcpyAsync(p->active_d, act0, ns * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, 1, d.tol, inner_rtol(p),
+  launch_cycle_init(p->st, p->active_d, ns, p->part_misc, p->nrowblk * d.ncomp, first, d.tol, inner_rtol(p),
                     p->stream);
   std::vector<char> live(K, 0);
   for (int k : subset) live[k] = 1;
@@ -731,15 +734,18 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   return HP_OK;
 }
 
+// All poles' solves (Zbar - b_k I) x_k = w, then
+// out = mask(loss_coef) * (phase sum_k a_k x_k + rinf_phase w).
 template <typename T, typename C>
-int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullptr) {
+int solve_and_sum(hp_plan p, const c128* w, c128* out, c128 phase, c128 rinf_phase, double loss_coef,
+                  const c128* const* x0, int first) {
   const hp_plan_desc& d = p->d;
   const int K = d.npoles;
   std::vector<int> all(K);
   for (int k = 0; k < K; ++k) all[k] = k;
   bool noconv = false;
   const bool use_prev = !x0 && p->guess_mode == HP_GUESS_PREV && p->prev_valid;
-  int rc = run_poles<T, C>(p, w, all, &noconv, x0, use_prev);
+  int rc = run_poles<T, C>(p, w, all, &noconv, x0, use_prev, first);
   if (rc) return rc;
   {
     const double es = (double)sizeof(cx<T>);
@@ -748,8 +754,8 @@ int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullpt
     for (int k = 0; k < K; ++k) terms += p->m_h[k];
     Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
     launch_final<T>(w, out, reinterpret_cast<cx<T>*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
-                    p->fieldn, p->st, K, p->phase, p->rinf_phase, p->loss_coef, d.edge_eta, d.edge_width, p->tw64_x,
-                    p->geo, p->stream);
+                    p->fieldn, p->st, K, phase, rinf_phase, loss_coef, d.edge_eta, d.edge_width, p->tw64_x, p->geo,
+                    p->stream);
   }
   if (p->guess_mode == HP_GUESS_PREV) {  // keep the solutions as the next step's guesses
     launch_accum_batch<T>(p->X, p->fieldn, fld<T>(p->Z, 0, p->fieldn), (size_t)d.restart * p->fieldn, p->fieldn,
@@ -759,6 +765,56 @@ int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullpt
   }
   HPCHK(hipGetLastError());
   return noconv ? HP_WARN_NOCONV : HP_OK;
+}
+
+// Pseudo-differential form (Sec. 2 eq. eq_barZfactor2 with the partial
+// fractions of sqrt(1+z) of Sec. 3.2): `substeps` classical RK4 steps of
+// h = dz / substeps for dw/dz = L(w), L(v) = i k0 n0 (r(Zbar) v - v).  Each
+// stage is one lockstep solve of all poles whose final kernel yields L(v)
+// directly (weights i k0 n0 on the solutions, i k0 n0 (r_inf - 1) on v, no
+// loss); k_rk4_stage then forms the next stage's input and the running sum.
+// The layer loss is applied after every substep.  Iteration counts run on
+// over the stages of the step; the reported residual is the worst of the
+// stages' true residuals where they were computed (else the last stage's
+// estimate, as for the exponential form).
+template <typename T, typename C>
+int run_step_sqrt(hp_plan p, const c128* w, c128* out) {
+  const hp_plan_desc& d = p->d;
+  const size_t fn = p->fieldn;
+  c128* Lb = p->rk;
+  c128* vb = p->rk + fn;
+  c128* acc = p->rk + 2 * fn;
+  const double h = d.dz / p->substeps, kk = d.k0 * d.n0;
+  const c128 ph = mk(0.0, kk);
+  const c128 cr = mk(-kk * d.r_inf.im, kk * (d.r_inf.re - 1.0));  // i kk (r_inf - 1)
+  const double lc = d.k0 * h / (2.0 * d.n0);
+  const double ca[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0}, cv[4] = {h / 2.0, h / 2.0, h, 0.0};
+  std::vector<double> worst(d.npoles, -1.0);
+  bool noconv = false;
+  const c128* u = w;
+  for (int sub = 0; sub < p->substeps; ++sub) {
+    for (int stg = 0; stg < 4; ++stg) {
+      const c128* v = stg == 0 ? u : vb;
+      int rc = solve_and_sum<T, C>(p, v, Lb, ph, cr, 0.0, nullptr, (sub == 0 && stg == 0) ? 1 : 2);
+      if (rc < 0) return rc;
+      if (rc == HP_WARN_NOCONV) noconv = true;
+      for (int k = 0; k < d.npoles && k < (int)p->relres.size(); ++k) worst[k] = std::max(worst[k], p->relres[k]);
+      const bool last = stg == 3;
+      // the last stage reads neither u nor v: out may be u (E_out aliasing E_in, or a later substep)
+      launch_rk4_stage(Lb, stg == 0 ? u : acc, last ? out : acc, u, last ? nullptr : vb, ca[stg], cv[stg],
+                       last ? lc : 0.0, d.edge_eta, d.edge_width, p->geo, p->stream);
+    }
+    u = out;
+  }
+  HPCHK(hipGetLastError());
+  p->relres = worst;
+  return noconv ? HP_WARN_NOCONV : HP_OK;
+}
+
+template <typename T, typename C>
+int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullptr) {
+  if (p->form == HP_FORM_SQRT) return run_step_sqrt<T, C>(p, w, out);
+  return solve_and_sum<T, C>(p, w, out, p->phase, p->rinf_phase, p->loss_coef, x0, 1);
 }
 
 // One shifted solve (Zbar - b_k I) x = rhs; x physical complex128.
@@ -975,6 +1031,7 @@ int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* con
     if (rc) return rc;
   }
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
+  if (p->form != HP_FORM_EXP) return fail(p, HP_ESTATE, "initial guesses apply to the exponential form only");
   const c128* w = reinterpret_cast<const c128*>(E_in);
   c128* out = reinterpret_cast<c128*>(E_out);
   std::vector<const c128*> g(p->d.npoles, nullptr);
@@ -993,6 +1050,41 @@ int hp_set_guess(hp_plan p, int mode) {
   p->guess_mode = mode;
   p->prev_valid = false;
   return HP_OK;
+}
+
+int hp_set_form(hp_plan p, int form, int substeps) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (form != HP_FORM_EXP && form != HP_FORM_SQRT) return fail(p, HP_EINVAL, "unknown form");
+  if (form == HP_FORM_EXP) {
+    p->form = form;
+    p->substeps = 1;
+    return HP_OK;
+  }
+  if (substeps < 1 || substeps > 1024) return fail(p, HP_EINVAL, "substeps must be in [1, 1024]");
+  if (!p->rk) {
+    hipError_t e = hipMalloc(&p->rk, 3 * p->fieldn * sizeof(c128));
+    if (e != hipSuccess) {
+      p->rk = nullptr;
+      return fail(p, HP_ENOMEM, std::string("hipMalloc stage fields: ") + hipGetErrorString(e));
+    }
+  }
+  p->form = form;
+  p->substeps = substeps;
+  p->prev_valid = false;
+  // one substep multiplies the free-space mode of eigenvalue mu by the RK4
+  // polynomial of h i k0 n0 (r(mu) - 1)
+  const hp_plan_desc& d = p->d;
+  const double s = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
+  auto mx = mu_table(d.nx, d.dx, p->c2, s), my = mu_table(d.ny, d.dy, p->c2, s);
+  const double lo = *std::min_element(mx.begin() + 1, mx.end()) + *std::min_element(my.begin() + 1, my.end());
+  const double hi = *std::max_element(mx.begin() + 1, mx.end()) + *std::max_element(my.begin() + 1, my.end());
+  const std::complex<double> hk(0.0, d.dz / substeps * d.k0 * d.n0);
+  double gmax = 0.0;
+  for (int i = 0; i <= 100000; ++i) {
+    const std::complex<double> z = hk * (rat(p, lo + (hi - lo) * i / 100000.0) - 1.0);
+    gmax = std::max(gmax, std::abs(1.0 + z * (1.0 + z * (0.5 + z * (1.0 / 6.0 + z / 24.0)))));
+  }
+  return gmax > 1.0 + 1e-6 ? HP_WARN_UNSTABLE : HP_OK;
 }
 
 int hp_get_solution(hp_plan p, int pole, void* x) {
@@ -1154,6 +1246,7 @@ void hp_plan_destroy(hp_plan p) {
   if (p->guess_x) (void)hipFree(p->guess_x);
   if (p->guess_rpart) (void)hipFree(p->guess_rpart);
   if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
+  if (p->rk) (void)hipFree(p->rk);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }

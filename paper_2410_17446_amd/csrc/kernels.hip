@@ -906,9 +906,9 @@ __global__ __launch_bounds__(64) void k_cycle_init(PoleState* __restrict__ st, c
   if (threadIdx.x != 0) return;
   PoleState& S = st[k];
   const double beta = sqrt(s);
-  if (first) {
+  if (first) {  // 1: a step's first solve; 2: a later solve of the same step (the count runs on)
     S.beta0 = beta;
-    S.total = 0;
+    if (first == 1) S.total = 0;
     S.cycle = 0;
     S.has_x = 0;
   } else {
@@ -1179,6 +1179,31 @@ __global__ void k_fill_zero(c128* p, size_t n) {
     p[i] = mk(0.0, 0.0);
 }
 
+// One stage of the classical fourth-order Runge-Kutta combination, over the
+// fields in physical layout [ncomp][ny][nx]: acc_out = acc_in + ca L and, when
+// v_out is given, v_out = u + cv L.  With loss_coef > 0, acc_out is multiplied
+// by the edge layer's loss factor.  Row 0 and column 0 are written as zero.
+// acc_in may alias acc_out (each element is read before it is written).
+__global__ __launch_bounds__(256) void k_rk4_stage(const c128* __restrict__ L, const c128* acc_in, c128* acc_out,
+                                                   const c128* __restrict__ u, c128* __restrict__ v_out, double ca,
+                                                   double cv, double loss_coef, double eta, int W, int nx, int ny,
+                                                   unsigned fsz, unsigned total) {
+  for (unsigned idx = blockIdx.x * 256u + threadIdx.x; idx < total; idx += gridDim.x * 256u) {
+    const unsigned e = idx % fsz;
+    const int i = (int)(e / (unsigned)nx), j = (int)(e % (unsigned)nx);
+    const bool inside = i > 0 && j > 0;
+    c128 a = mk(0.0, 0.0), v = mk(0.0, 0.0);
+    if (inside) {
+      const c128 l = L[idx];
+      a = acc_in[idx] + ca * l;
+      if (loss_coef > 0.0) a = edge_loss(i, j, nx, ny, W, eta, loss_coef) * a;
+      if (v_out) v = u[idx] + cv * l;
+    }
+    acc_out[idx] = a;
+    if (v_out) v_out[idx] = v;
+  }
+}
+
 }  // namespace
 
 // ====================================================================== launchers
@@ -1437,6 +1462,14 @@ void launch_to_float(const double* a, float* b, size_t n, hipStream_t s) {
 
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, p, n);
+}
+
+void launch_rk4_stage(const c128* L, const c128* acc_in, c128* acc_out, const c128* u, c128* v_out, double ca,
+                      double cv, double loss_coef, double eta, int W, const Geo& g, hipStream_t s) {
+  const unsigned total = (unsigned)(g.ncomp * g.fsz);
+  const unsigned nb = std::min(2048u, (total + 1023u) / 1024u);
+  hipLaunchKernelGGL(k_rk4_stage, dim3(nb), dim3(256), 0, s, L, acc_in, acc_out, u, v_out, ca, cv, loss_coef, eta, W,
+                     g.nx, g.ny, (unsigned)g.fsz, total);
 }
 
 // explicit instantiations

@@ -93,6 +93,9 @@ void launch_arnoldi(PoleState* st, const int* active, int nactive, const double*
                     unsigned long long* ftag, unsigned long long seq, double* est, hipStream_t s);
 
 // Start a cycle: beta = sqrt(sum part), g = beta e1, sigma_0 = 1/beta.
+// first: 0 a restart; 1 the first cycle of a step's solve (the iteration count
+// starts at 0); 2 the first cycle of a further solve in the same step (the
+// count runs on).
 // Cycle tolerance on the estimate: max(tol * beta0, rtol_cycle * beta).
 // part_bs: stride between the poles' partial sums (0: all read the same);
 // set_has_x: the poles' X accumulators hold a solution so far.
@@ -138,4 +141,10 @@ void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s);
 void launch_mark_list(PoleState* st, const int* poles, int n, hipStream_t s);
 
 void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);
+
+// Classical RK4 combination of one stage (physical fields, complex128):
+// acc_out = acc_in + ca L; v_out = u + cv L unless v_out is NULL; with
+// loss_coef > 0 acc_out is multiplied by the edge layer's loss factor.
+void launch_rk4_stage(const c128* L, const c128* acc_in, c128* acc_out, const c128* u, c128* v_out, double ca,
+                      double cv, double loss_coef, double eta, int W, const Geo& g, hipStream_t s);
 void launch_to_float(const double* a, float* b, size_t n, hipStream_t s);

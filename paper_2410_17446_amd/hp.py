@@ -19,9 +19,10 @@ _lib = None
 HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
 HP_FP64, HP_MIXED, HP_MIXED64 = 0, 1, 2
 HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
+HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_step_guess", "hp_set_guess", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_step_guess", "hp_set_guess", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_last_error", "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
@@ -176,6 +177,11 @@ class Plan:
 
     def set_guess(self, mode):
         return self._check(self.L.hp_set_guess(self.handle, int(mode)), "hp_set_guess")
+
+    def set_form(self, form, substeps=1):
+        """HP_FORM_EXP or HP_FORM_SQRT (pseudo-differential form, `substeps` RK4 substeps per
+        step); returns HP_OK or HP_WARN_UNSTABLE."""
+        return self._check(self.L.hp_set_form(self.handle, int(form), int(substeps)), "hp_set_form")
 
     def solution(self, pole, x=None):
         import torch

@@ -7,6 +7,8 @@
 * The (N,N) AAA-Lawson rational fit of exp(iK sqrt(1+z)) on Re z in [-4, 2]
   (Sec. 3.1) and its partial fractions r_inf + sum a_k/(z - b_k)
   (Sec. 2, eq. pf_expan_eq): the poles/residues hp_plan_create takes.
+* The Cauchy-integral partial fractions of sqrt(1+z) (Sec. 3.2, eq.
+  pf_sqrt_exp, Appendix A) for the pseudo-differential form (HP_FORM_SQRT).
 """
 from __future__ import annotations
 
@@ -143,3 +145,24 @@ def plan_tables(K: float, npoles: int):
     """(poles, residues, r_inf, d2, d1) for hp_plan_create."""
     f = RationalFit(K, npoles)
     return f.poles, f.residues, f.r_inf, stencil_d2(), stencil_d1()
+
+
+def cauchy_sqrt_table(N: int, alpha: float = 1.0):
+    """(poles, residues, r_inf) of sqrt(1+z) ~ r_inf + sum_j a_j/(z - b_j) from the Cauchy
+    integral over the cut w in [-1, 1] of the Moebius variable w = (z+1+i alpha)/(z+1-i alpha),
+    discretised by the N-point Gauss rule of the weight sqrt((1+eta)/(1-eta)).  That weight is
+    the Chebyshev weight of the third kind, whose Gauss rule is explicit: eta_j = cos(theta_j),
+    theta_j = (2j-1) pi/(2N+1), omega_j = 4 pi cos^2(theta_j/2)/(2N+1).  With
+    wt_j = (c_alpha/pi) omega_j/(1 - eta_j), sigma_j = (1+eta_j)/(1-eta_j), c_alpha = sqrt(alpha) e^{i pi/4}:
+    b_j = -(1 + i alpha sigma_j), a_j = -i alpha wt_j (1 + sigma_j), r_inf = c_alpha + sum_j wt_j."""
+    if N < 1 or not alpha > 0:
+        raise ValueError("N >= 1 and alpha > 0 required")
+    th = (2.0 * np.arange(1, N + 1) - 1.0) * np.pi / (2 * N + 1)
+    half = th / 2.0
+    # 1 - eta = 2 sin^2(theta/2), 1 + eta = 2 cos^2(theta/2): no cancellation near eta = +-1
+    one_m, one_p = 2.0 * np.sin(half) ** 2, 2.0 * np.cos(half) ** 2
+    omega = 2.0 * np.pi / (2 * N + 1) * one_p
+    c_alpha = np.sqrt(alpha) * np.exp(0.25j * np.pi)
+    wt = c_alpha / np.pi * omega / one_m
+    sigma = one_p / one_m
+    return -(1.0 + 1j * alpha * sigma), -1j * alpha * wt * (1.0 + sigma), complex(c_alpha + wt.sum())

@@ -1,0 +1,57 @@
+"""The library's host-side plan tables (paper_2410_17446_amd.tables) against the oracle.
+
+The two sides are written independently (the library's Gauss rule is the explicit
+Chebyshev third-kind rule, the oracle's a general Gauss-Jacobi routine; the fits share
+only their definition), so agreement checks both."""
+import numpy as np
+import pytest
+
+from oracle import fit, stencil
+from oracle import sqrt_form as sf
+from paper_2410_17446_amd import tables
+
+
+def _match(b1, a1, b2, a2):
+    i, j = np.argsort(b1.imag), np.argsort(b2.imag)
+    return np.abs(b1[i] / b2[j] - 1).max(), np.abs(a1[i] / a2[j] - 1).max()
+
+
+@pytest.mark.parametrize("N,alpha", [(1, 1.0), (25, 1.0), (45, 0.1), (60, 1.0)])
+def test_cauchy_table_matches_oracle(N, alpha):
+    b, a, r = tables.cauchy_sqrt_table(N, alpha)
+    o = sf.cauchy_sqrt_pf(N, alpha)
+    eb, ea = _match(b, a, o.poles, o.residues)
+    assert eb < 1e-12 and ea < 1e-10 and abs(r / o.r_inf - 1) < 1e-10
+    assert np.all(b.imag < 0)  # the cut's images lie below the real axis
+
+
+def test_cauchy_table_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        tables.cauchy_sqrt_table(0)
+    with pytest.raises(ValueError):
+        tables.cauchy_sqrt_table(5, 0.0)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_rational_fit_accuracy_matches_oracle(N):
+    """Both AAA-Lawson fits of exp(iK sqrt(1+z)), K = 2 pi, reach the same accuracy on the
+    uniform samples of [-4, 2] (the fits need not coincide term by term)."""
+    K = 2 * np.pi
+    lib = tables.RationalFit(K, N)
+    ora = fit.fit_exp_sqrt(K, N)
+    z = np.linspace(-4, 2, 4001)
+    e_lib = np.abs(lib(z) - fit.target(z, K)).max()
+    assert e_lib < 3 * ora["max_err"]
+    assert len(lib.poles) == N and np.all(lib.poles.imag < 0)
+
+
+def test_stencils_match_oracle_symbols():
+    """Both stencil designs solve the same minimax problem: their symbols agree."""
+    c_o, d_o = stencil.stencils()
+    c_l, d_l = tables.stencil_d2(), tables.stencil_d1()
+    th = np.linspace(0.01, 0.83 * np.pi, 500)
+    s_o, s_l = stencil.d2_symbol(c_o, th), stencil.d2_symbol(c_l, th)
+    assert np.abs(s_l / s_o - 1).max() < 1e-3
+    th = np.linspace(0.01, 0.70 * np.pi, 500)
+    s_o, s_l = stencil.d1_symbol(d_o, th), stencil.d1_symbol(d_l, th)
+    assert np.abs(s_l / s_o - 1).max() < 1e-3
