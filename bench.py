@@ -23,7 +23,11 @@ Other workloads (--config): batch64 (64 independent propagations of uneven
 sizes run concurrently), learned (a U-Net trained on the GPU from the
 propagator's own solves supplies GMRES starting points; timed against the plain
 method and the previous-step start on scalar1024), unet (training steps of that
-U-Net at its training shape) and copy (the HBM reference for the counters).
+U-Net at its training shape), copy (the HBM reference for the counters) and
+sqrt1024 (the scalar1024 workload through the pseudo-differential form: 25
+Cauchy-integral terms of sqrt(1+z), alpha = 1, eight RK4 substeps of lambda/8
+per lambda step, FP64; the field is compared with the exponential form's after
+the same number of steps).
 """
 from __future__ import annotations
 
@@ -37,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SQRT_TERMS, SQRT_ALPHA, SQRT_SUBSTEPS = 25, 1.0, 8
 KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "cplx.hpp", "state.hpp", "kernels.hpp")
 COUNTERS = os.path.join(ROOT, "profiles", "row_apply_scalar1024_fp64_hbm_counters.md")
 
@@ -73,6 +78,8 @@ def parse():
     ap.add_argument("--train-n", type=int, default=256, help="training grid (learned workload)")
     ap.add_argument("--train-draws", type=int, default=48, help="(medium, beam) draws for training")
     ap.add_argument("--train-seconds", type=float, default=90.0, help="training time budget")
+    ap.add_argument("--no-exp-compare", action="store_true",
+                    help="sqrt1024: skip the exponential-form run the field is compared with")
     ap.add_argument("--unet-precision", default="bf16", choices=["bf16", "f32"],
                     help="U-Net 3x3 convolutions: bf16 matrix cores or float32")
     return ap.parse_args()
@@ -314,13 +321,15 @@ def run_copy(args):
 EVENT_PERIOD = 4  # the timed steps bracket every 4th launch of the dominant kernel with events
 
 
-def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps):
+def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None):
     poles, residues, r_inf, d2, d1 = tables
     N = cfg["N"]
     plan = hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=hp_k0(), n0=1.0, dz=cfg["dz"], ncomp=cfg["ncomp"],
                    poles=poles, residues=residues, r_inf=r_inf, d2=d2, d1=d1, edge_width=cfg["W"],
                    edge_eta=cfg["eta_max"], tol=cfg["tol"], restart=cfg["restart"], max_cycles=20,
                    precision=precision)
+    if form is not None:
+        plan.set_form(*form)
     plan.set_medium(n2)
     a = w0.clone()
     b = torch.empty_like(a)
@@ -351,16 +360,24 @@ def hp_k0():
     return inputs.K0
 
 
-def cpu_baseline(cfg, npoles_sample):
-    """Oracle on a bounded sample: the first `npoles_sample` pole solves of step 1 (scaled to steps/s)."""
+def cpu_baseline(cfg, npoles_sample, sqrt_form=False):
+    """Oracle on a bounded sample: `npoles_sample` pole solves of step 1 (of its first RK stage for the
+    pseudo-differential form), scaled to steps/s."""
     import numpy as np
 
     from oracle import fit, stencil
     from oracle import operator as op
+    from oracle import sqrt_form as sf
     from oracle import step as st
     from paper_2410_17446_amd import inputs
     c, d = stencil.stencils()
-    f = fit.fit_exp_sqrt(inputs.K0 * cfg["dz"], cfg["npoles"])
+    if sqrt_form:
+        pf = sf.cauchy_sqrt_pf(cfg["npoles"], SQRT_ALPHA)
+        f = {"poles": pf.poles}
+        solves_per_pole = 4 * SQRT_SUBSTEPS
+    else:
+        f = fit.fit_exp_sqrt(inputs.K0 * cfg["dz"], cfg["npoles"])
+        solves_per_pole = 1
     g = op.Grid(N=cfg["N"], dx=cfg["dx"], dy=cfg["dx"], k0=inputs.K0, n0=1.0, c=c, d=d, W=cfg["W"],
                 eta_max=cfg["eta_max"])
     n2 = inputs.medium_n2(cfg)
@@ -375,11 +392,64 @@ def cpu_baseline(cfg, npoles_sample):
         r = st.solve_pole(g, co, w, f["poles"][j], cfg["tol"], cfg["restart"], workers=threads)
         iters.append(r.iters)
     dt = time.perf_counter() - t0
-    step_s = dt * cfg["npoles"] / k
+    step_s = dt * cfg["npoles"] * solves_per_pole / k
+    where = "the first RK stage of step 1" if sqrt_form else "step 1"
+    scale = f"{cfg['npoles']} x {solves_per_pole}/{k}" if sqrt_form else f"{cfg['npoles']}/{k}"
     return dict(value=1.0 / step_s, unit="steps/s", cores=threads, kind="oracle",
-                sample=f"GMRES solves of poles {picks} (of {cfg['npoles']}) in step 1 of the {cfg['N']}^2 "
+                sample=f"GMRES solves of poles {picks} (of {cfg['npoles']}) in {where} of the {cfg['N']}^2 "
                        f"workload ({dt:.1f} s, iterations {iters}); per-step time = sample time x "
-                       f"{cfg['npoles']}/{k}; scipy.fft uses {threads} threads, the rest of numpy one")
+                       f"{scale}; scipy.fft uses {threads} threads, the rest of numpy one")
+
+
+def run_sqrt(args):
+    """scalar1024 through the pseudo-differential form (FP64), compared with the exponential form."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, tables
+    cfg = dict(inputs.CONFIGS["scalar1024"], npoles=SQRT_TERMS)
+    b, a, r = tables.cauchy_sqrt_table(SQRT_TERMS, SQRT_ALPHA)
+    tab = (b, a, r, tables.stencil_d2(), tables.stencil_d1())
+    w0 = torch.from_numpy(inputs.beam(cfg)).cuda()
+    n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
+    res = run_mode(hp, torch, cfg, tab, hp.HP_FP64, w0, n2, args.warmup, args.steps,
+                   form=(hp.HP_FORM_SQRT, SQRT_SUBSTEPS))
+    value = args.steps / res["seconds"]
+    cmp = None
+    if not args.no_exp_compare:
+        ecfg = dict(inputs.CONFIGS["scalar1024"])
+        ex = run_mode(hp, torch, ecfg, tables.plan_tables(inputs.K0 * ecfg["dz"], ecfg["npoles"]), hp.HP_FP64, w0,
+                      n2, args.warmup, args.steps)
+        f, g = res["field"].cpu().numpy(), ex["field"].cpu().numpy()
+        cmp = {"steps_per_s": args.steps / ex["seconds"],
+               "rel_l2_difference": float(np.linalg.norm(f - g) / np.linalg.norm(g))}
+        print(f"# exponential form {cmp['steps_per_s']:.2f} steps/s; fields differ by "
+              f"{cmp['rel_l2_difference']:.3e} (relative L2) after {args.warmup + args.steps} steps", file=sys.stderr)
+    print(f"# sqrt form: {value:.3f} steps/s", file=sys.stderr)
+    prof, brk, dom = res["prof"], res["breakdown"], res["dom"]
+    n_l, ms, by = prof[dom]
+    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    line = {
+        "metric": (f"propagation steps/s ({cfg['N']}^2, pseudo-differential form: {SQRT_TERMS} Cauchy-integral terms "
+                   f"of sqrt(1+z), RK4 with {SQRT_SUBSTEPS} substeps per lambda step)"),
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["seconds"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "sqrt1024", "grid": cfg["N"], "terms": SQRT_TERMS, "alpha": SQRT_ALPHA,
+                   "substeps": SQRT_SUBSTEPS, "tol": cfg["tol"], "mode": "fp64"},
+        "last_step_iters_summed_over_stages": res["iters"],
+        "exponential_form": cmp,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": by / max(n_l, 1), "launches": n_l,
+                     "avg_launch_us": 1e3 * ms / max(n_l, 1),
+                     "timed": f"every {EVENT_PERIOD}th launch in the timed steps"},
+        "warmup_kernel_ms": {k: brk[k][1] for k in brk},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, 2, sqrt_form=True)
+    print(json.dumps(line))
+    return 0
 
 
 def main():
@@ -395,6 +465,8 @@ def main():
         return run_copy(args)
     if args.config == "unet":
         return run_unet(args)
+    if args.config == "sqrt1024":
+        return run_sqrt(args)
     import numpy as np
     import torch
 
