@@ -9,8 +9,13 @@
   (Sec. 2, eq. pf_expan_eq): the poles/residues hp_plan_create takes.
 * The Cauchy-integral partial fractions of sqrt(1+z) (Sec. 3.2, eq.
   pf_sqrt_exp, Appendix A) for the pseudo-differential form (HP_FORM_SQRT).
+* A lookup table of AAA-Lawson partial fractions for one reference index n0
+  and a list of k0 dz values (Sec. 3.1: the coefficients depend on K = k0 n0 dz
+  only, so a table over k0 dz at fixed n0 replaces the fit at plan set-up).
 """
 from __future__ import annotations
+
+import json
 
 import numpy as np
 import scipy.linalg as sla
@@ -166,3 +171,70 @@ def cauchy_sqrt_table(N: int, alpha: float = 1.0):
     wt = c_alpha / np.pi * omega / one_m
     sigma = one_p / one_m
     return -(1.0 + 1j * alpha * sigma), -1j * alpha * wt * (1.0 + sigma), complex(c_alpha + wt.sum())
+
+
+class PFLookup:
+    """AAA-Lawson partial fractions of exp(iK sqrt(1+z)) on [-4, 2] for a fixed reference index n0
+    and a list of k0 dz values, K = k0 n0 dz.  Entries are whole fits: poles and residues of fits
+    at neighbouring K do not interpolate (1 % apart in K, averaging them costs three orders of
+    magnitude in accuracy), so a lookup must hit a tabulated k0 dz."""
+
+    def __init__(self, n0: float, npoles: int, entries: list):
+        self.n0, self.npoles, self.entries = float(n0), int(npoles), entries
+
+    @classmethod
+    def build(cls, k0dz_values, npoles: int, n0: float = 1.0003):
+        entries = []
+        for k0dz in k0dz_values:
+            K = float(k0dz) * n0
+            f = RationalFit(K, npoles)
+            err = float(np.abs(f(f.Z) - exp_sqrt(f.Z, K)).max())            # on the fit's samples
+            zf = np.linspace(-4.0, 2.0, 100001)
+            fine = float(np.abs(f(zf) - exp_sqrt(zf, K)).max())           # between them (branch point)
+            entries.append(dict(k0dz=float(k0dz), K=K, poles=f.poles, residues=f.residues, r_inf=f.r_inf,
+                                max_err=err, fine_max_err=fine))
+        return cls(n0, npoles, entries)
+
+    def save(self, path: str):
+        def c(a):
+            a = np.asarray(a, dtype=complex)
+            return [[float(v.real), float(v.imag)] for v in np.atleast_1d(a)]
+        doc = dict(n0=self.n0, npoles=self.npoles, target="exp(iK sqrt(1+z)), K = k0 n0 dz, z in [-4, 2]; max_err on the 4001 fit samples, "
+                          "fine_max_err on 100001 points",
+                   entries=[dict(k0dz=e["k0dz"], K=e["K"], max_err=e["max_err"],
+                                 fine_max_err=e["fine_max_err"], poles=c(e["poles"]),
+                                 residues=c(e["residues"]), r_inf=c(e["r_inf"])[0]) for e in self.entries])
+        with open(path, "w") as fh:
+            json.dump(doc, fh, indent=1)
+
+    @classmethod
+    def load(cls, path: str):
+        with open(path) as fh:
+            doc = json.load(fh)
+        def c(a):
+            a = np.asarray(a, dtype=float)
+            return a[..., 0] + 1j * a[..., 1]
+        entries = [dict(k0dz=e["k0dz"], K=e["K"], max_err=e["max_err"], fine_max_err=e["fine_max_err"],
+                        poles=c(e["poles"]),
+                        residues=c(e["residues"]), r_inf=complex(c(e["r_inf"]))) for e in doc["entries"]]
+        return cls(doc["n0"], doc["npoles"], entries)
+
+    def get(self, k0: float, dz: float, n0: float, rtol: float = 1e-9):
+        """(poles, residues, r_inf) of the entry for k0 dz; KeyError when n0 differs from the
+        table's or k0 dz is not tabulated (to rtol)."""
+        if abs(n0 - self.n0) > rtol * self.n0:
+            raise KeyError(f"table is for n0 = {self.n0}, not {n0}")
+        want = k0 * dz
+        for e in self.entries:
+            if abs(e["k0dz"] - want) <= rtol * abs(want):
+                return e["poles"], e["residues"], e["r_inf"]
+        raise KeyError(f"k0 dz = {want} is not in the table ({[e['k0dz'] for e in self.entries]})")
+
+
+if __name__ == "__main__":
+    # python -m paper_2410_17446_amd.tables OUT.json N0 NPOLES DZ... (dz in wavelengths; k0 = 2 pi)
+    import sys
+    out, n0, npoles = sys.argv[1], float(sys.argv[2]), int(sys.argv[3])
+    dzs = [float(v) for v in sys.argv[4:]]
+    PFLookup.build([2.0 * np.pi * v for v in dzs], npoles, n0=n0).save(out)
+    print(f"wrote {out}: n0 = {n0}, {npoles} poles, dz = {dzs} wavelengths")

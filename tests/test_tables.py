@@ -55,3 +55,45 @@ def test_stencils_match_oracle_symbols():
     th = np.linspace(0.01, 0.70 * np.pi, 500)
     s_o, s_l = stencil.d1_symbol(d_o, th), stencil.d1_symbol(d_l, th)
     assert np.abs(s_l / s_o - 1).max() < 1e-3
+
+
+# ---------------------------------------------------------------- lookup table over k0 dz (Sec. 3.1)
+
+import glob
+import os
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_17446_amd", "data")
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(DATA, "pf_lookup_*.json"))))
+def test_shipped_lookup_tables_meet_their_errors(path):
+    """Every entry of a shipped table approximates the oracle's exp(iK sqrt(1+z)), K = k0 dz n0,
+    within its recorded errors: on the fit's 4001 uniform samples (below 2e-5 for the 16-term
+    tables up to dz = 2 lambda) and on a 100001-point grid, which sees the slow convergence at
+    the branch point z = -1 between the samples.  All poles lie below the real axis."""
+    t = tables.PFLookup.load(path)
+    assert len(t.entries) >= 4
+    for e in t.entries:
+        assert abs(e["K"] - e["k0dz"] * t.n0) < 1e-12 * e["K"]
+        for z, rec in ((np.linspace(-4, 2, 4001), e["max_err"]), (np.linspace(-4, 2, 100001), e["fine_max_err"])):
+            r = e["r_inf"] + (1.0 / np.subtract.outer(z, e["poles"])) @ e["residues"]
+            err = np.abs(r - fit.target(z, e["K"])).max()
+            assert err <= 1.01 * rec + 1e-15
+        assert e["max_err"] < 2e-5
+        assert len(e["poles"]) == t.npoles and np.all(e["poles"].imag < 0)
+
+
+def test_lookup_round_trip_and_misses(tmp_path):
+    k0 = 2 * np.pi
+    t = tables.PFLookup.build([k0 * 0.5, k0 * 1.0], 8, n0=1.0)
+    p = tmp_path / "t.json"
+    t.save(str(p))
+    u = tables.PFLookup.load(str(p))
+    b, a, r = u.get(k0, 1.0, 1.0)
+    f = tables.RationalFit(k0, 8)
+    assert np.allclose(np.sort_complex(b), np.sort_complex(f.poles), rtol=1e-12)
+    assert abs(r - f.r_inf) < 1e-12
+    with pytest.raises(KeyError):
+        u.get(k0, 0.75, 1.0)          # k0 dz not tabulated
+    with pytest.raises(KeyError):
+        u.get(k0, 1.0, 1.0003)        # other reference index
