@@ -170,3 +170,27 @@ def test_sqrt_form_agrees_with_exponential_form():
     err = rel_l2(a, b)
     print(f"sqrt form vs exponential form over 2 wavelengths: relative L2 {err:.3e}")
     assert err < 1e-3
+
+
+def test_sqrt_form_mixed_precision_and_previous_guesses():
+    """The pseudo-differential form in HP_MIXED64 (complex64 Krylov storage, FP64 arithmetic and
+    true-residual restarts) meets the FP64 result to 1e-6; with HP_GUESS_PREV every stage starts
+    from the previous stage's solutions (judged as in the exponential form): same field to the
+    tolerance, no more iterations."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp
+    wl = workload(N=128, W=16, eta=0.25, dz=0.25, medium=("sine", 0.05, 2.0), w0=6.0, tol=1e-10)
+    pf = sf.cauchy_sqrt_pf(16, 1.0)
+    w, n2 = to_gpu(wl["w"]), to_gpu(wl["n2"])
+    ref_plan, _ = _plan(wl, pf, 1e-10, 2)
+    ref = ref_plan.propagate(w, 2, n2=n2).cpu().numpy()
+    it_ref, _ = ref_plan.stats()
+    mixed, _ = _plan(wl, pf, 1e-8, 2, precision=hp.HP_MIXED64)
+    out = mixed.propagate(w, 2, n2=n2).cpu().numpy()
+    assert rel_l2(out, ref) < 1e-6
+    prev, _ = _plan(wl, pf, 1e-10, 2)
+    prev.set_guess(hp.HP_GUESS_PREV)
+    out = prev.propagate(w, 2, n2=n2).cpu().numpy()
+    it_prev, rr = prev.stats()
+    assert rel_l2(out, ref) < 1e-8 and max(rr) <= 1e-10
+    assert sum(it_prev) <= sum(it_ref), (it_prev, it_ref)
