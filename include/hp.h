@@ -83,7 +83,7 @@ enum {
 enum { HP_FP64 = 0, HP_MIXED = 1, HP_MIXED64 = 2 };
 
 typedef struct {
-  int nx, ny;                 /* cells per axis = array dims; 2^k or 3 * 2^k, 64 <= n <= 2048 */
+  int nx, ny;                 /* cells per axis = array dims: 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048 */
   double dx, dy;              /* grid spacing */
   double k0, n0, dz;          /* vacuum wavenumber, reference index, step; K = k0 n0 dz */
   int ncomp;                  /* 1 scalar, 2 vector */

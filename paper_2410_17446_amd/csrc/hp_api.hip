@@ -169,7 +169,7 @@ bool fft_size(int n) {
 
 std::string validate(const hp_plan_desc* d) {
   if (!d) return "desc is NULL";
-  if (!fft_size(d->nx) || !fft_size(d->ny)) return "nx, ny must be 2^k or 3 * 2^k in [64, 2048]";
+  if (!fft_size(d->nx) || !fft_size(d->ny)) return "nx, ny must be 64, 128, 192, 256, 384, 512, 768, 1024, 1536 or 2048";
   if (d->ncomp != 1 && d->ncomp != 2) return "ncomp must be 1 or 2";
   if (d->precision != HP_FP64 && d->precision != HP_MIXED && d->precision != HP_MIXED64)
     return "precision must be HP_FP64, HP_MIXED or HP_MIXED64";

@@ -70,3 +70,33 @@ def test_aperture_centerline_intensity_against_closed_form():
     # no worse than the paper's own propagator (measured here: 4.7e-3, 1.7e-3 beyond 20 lambda)
     assert err < PAPER["aperture_centerline_l2_propagator"]
     assert err_far < 3e-3
+
+
+@pytest.mark.parametrize("beam,N", [("narrow", 128), ("wide", 192)])
+def test_gaussian_beam_peaks_against_closed_form(beam, N):
+    """Sec. 5.2: Gaussian beams of 1/e spectral width k0 n0 (narrow, w = lambda/(pi n0)) and
+    0.5 k0 n0 (wide, w = 2 lambda/(pi n0)), n0 = 1.0003, 6 points per lambda, 25 terms, 8 steps
+    of lambda/20 to z = 0.4 lambda.  The on-axis amplitude has a closed form (the Fourier pair
+    of eq. eq_ft_gaussian propagated mode by mode): 0.527961 / 0.920087, the paper's reference
+    values.  The paper's propagator gave 0.529509 / 0.920729; ours must be as close, within a
+    factor 3, and within 1 %."""
+    torch = _cuda()
+    from oracle import physics
+    from paper_2410_17446_amd import hp
+    n0 = PAPER["n0_air"]
+    dx, dz = 1.0 / 6.0, 0.05
+    wb = (1.0 if beam == "narrow" else 2.0) / (np.pi * n0)
+    exact = abs(physics.gaussian_axis_field(wb, 0.4, K0, n0))
+    assert abs(exact - PAPER[f"{beam}_beam_peak_reference"]) < 1e-6
+    c, d = stencil.stencils()
+    f = fit.fit_exp_sqrt(K0 * n0 * dz, 25)
+    plan = hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=K0, n0=n0, dz=dz, ncomp=1, poles=f["poles"],
+                   residues=f["residues"], r_inf=f["r_inf"], d2=c, d1=d, edge_width=N // 8, edge_eta=0.25,
+                   tol=1e-10, restart=30, max_cycles=20)
+    w = inputs.gaussian_beam(N, dx, wb)
+    out = plan.propagate(to_gpu(w), 8, n2=to_gpu(np.full((N, N), n0 * n0))).cpu().numpy()
+    peak = np.abs(out[0]).max()
+    gap = abs(peak - exact) / exact
+    paper_gap = abs(PAPER[f"{beam}_beam_peak_propagator"] - exact) / exact
+    print(f"{beam} beam: peak {peak:.6f}, closed form {exact:.6f}, relative gap {gap:.2e} (paper {paper_gap:.2e})")
+    assert gap < 0.01 and gap < 3 * paper_gap
