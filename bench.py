@@ -27,7 +27,9 @@ U-Net at its training shape), copy (the HBM reference for the counters) and
 sqrt1024 (the scalar1024 workload through the pseudo-differential form: 25
 Cauchy-integral terms of sqrt(1+z), alpha = 1, eight RK4 substeps of lambda/8
 per lambda step, FP64; the field is compared with the exponential form's after
-the same number of steps).
+the same number of steps) and sineprod768 (the paper's beam study through the
+z-dependent rotated sine-product media, one n^2 plane per step, with the beam
+centroids after 240 lambda).
 """
 from __future__ import annotations
 
@@ -401,6 +403,78 @@ def cpu_baseline(cfg, npoles_sample, sqrt_form=False):
                        f"{scale}; scipy.fft uses {threads} threads, the rest of numpy one")
 
 
+def run_sineprod(args):
+    """The paper's beam study through the rotated sine-product media (Sec. 5.3): a Gaussian
+    beam (1/e radius 25 lambda) over 240 lambda, n0 = 1.2, dn = 0.025, steps of a quarter of the
+    medium's wavelength, q = 1 (medium wavenumber k0 n0) and q = 2 (0.5 k0 n0), 768^2 cells of
+    lambda/4 (192 lambda; edge layer 24 lambda), 16 poles, FP64, tol 1e-8.  Every step takes its
+    own n^2 plane (hp_propagate with a plane stride: coefficient refresh each step); the planes
+    are generated on the device before the timed region.  Reports steps/s over both runs and the
+    beam centroids."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, tables
+    N, dx, L, n0, dn, w0 = 768, 0.25, 240.0, 1.2, 0.025, 25.0
+    k0 = inputs.K0
+    R = inputs.rotation_matrix()
+    xs = torch.tensor(inputs.coords(N, dx), dtype=torch.float64, device="cuda")
+    Y, X = torch.meshgrid(xs, xs, indexing="ij")
+    d2, d1 = tables.stencil_d2(), tables.stencil_d1()
+    runs, total_steps, total_s = {}, 0, 0.0
+    for q in (1.0, 2.0):
+        dz = q / (4 * n0)
+        nsteps = int(round(L / dz))
+        ks = k0 * n0 / (np.sqrt(3.0) * q)
+        stack = torch.empty((nsteps, N, N), dtype=torch.float64, device="cuda")
+        for st in range(nsteps):
+            z = st * dz
+            xt = R[0, 0] * X + R[0, 1] * Y + R[0, 2] * z
+            yt = R[1, 0] * X + R[1, 1] * Y + R[1, 2] * z
+            zt = R[2, 0] * X + R[2, 1] * Y + R[2, 2] * z
+            n = n0 + dn * torch.sin(ks * xt) * torch.sin(ks * yt) * torch.sin(ks * zt)
+            stack[st] = n * n
+        for st in (0, nsteps // 2):   # the device planes are the input module's planes
+            ref = inputs.rotated_sine_n2(N, dx, st * dz, n0=n0, dn=dn, q=q)
+            assert np.abs(stack[st].cpu().numpy() - ref).max() < 1e-12
+        f = tables.RationalFit(k0 * n0 * dz, 16)
+        plan = hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=k0, n0=n0, dz=dz, ncomp=1, poles=f.poles, residues=f.residues,
+                       r_inf=f.r_inf, d2=d2, d1=d1, edge_width=N // 8, edge_eta=0.25, tol=1e-8, restart=30,
+                       max_cycles=20)
+        w = torch.from_numpy(inputs.gaussian_beam(N, dx, w0)).cuda()
+        out = torch.empty_like(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.propagate(w, nsteps, n2=stack, n2_step_stride=N * N, E_out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        iters, _ = plan.stats()
+        plan.close()
+        I = out[0].abs() ** 2
+        P = I.sum()
+        cx, cy = float((I * X).sum() / P), float((I * Y).sum() / P)
+        runs[f"q{q:g}"] = {"steps": nsteps, "dz": dz, "seconds": dt, "steps_per_s": nsteps / dt,
+                           "last_step_iters": int(sum(iters)),
+                           "centroid": [cx, cy], "centroid_over_dxdy": [cx / (dx * dx), cy / (dx * dx)]}
+        print(f"# q={q:g}: {nsteps} steps in {dt:.1f} s ({nsteps / dt:.1f} steps/s), centroid ({cx:.4f}, {cy:.4f}) "
+              f"lambda, / (dx dy): ({cx / dx / dx:.2f}, {cy / dx / dx:.2f})", file=sys.stderr, flush=True)
+        total_steps += nsteps
+        total_s += dt
+        del stack
+    line = {
+        "metric": "propagation steps/s (768^2, 16 poles, z-dependent rotated sine-product media, 240 lambda)",
+        "value": total_steps / total_s, "unit": "steps/s", "n_gpus": 1, "steps": total_steps, "warmup": 0,
+        "ms_per_step": 1e3 * total_s / total_steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "sineprod768", "grid": N, "poles": 16, "tol": 1e-8, "n0": n0, "dn": dn,
+                   "beam_radius": w0, "range": L},
+        "runs": runs,
+        "paper_centroids": {"q1": [9.96, -11.36], "q2": [0.217, -0.229]},
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def run_sqrt(args):
     """scalar1024 through the pseudo-differential form (FP64), compared with the exponential form."""
     import numpy as np
@@ -467,6 +541,8 @@ def main():
         return run_unet(args)
     if args.config == "sqrt1024":
         return run_sqrt(args)
+    if args.config == "sineprod768":
+        return run_sineprod(args)
     import numpy as np
     import torch
 

@@ -46,17 +46,22 @@ ROT_AXIS = (0.258, 0.312, 0.914)
 ROT_ANGLE = 0.128
 
 
-def rotated_sine_n2(N: int, dx: float, z: float, n0: float = 1.2, dn: float = 0.025, q: float = 1.0,
-                    k0: float = 2.0 * np.pi) -> np.ndarray:
-    """n^2 on the plane z of the rotated sine product of Sec. 5 (eq. sineprod):
-    n = n0 + dn sin(ks x~) sin(ks y~) sin(ks z~), ks = k0 n0 / (sqrt(3) q), with
-    (x~, y~, z~) = R (x, y, z) and R the rotation by ROT_ANGLE about the unit vector
-    along ROT_AXIS (axis-angle form); x, y on the grid's coordinates."""
+def rotation_matrix() -> np.ndarray:
+    """R of the rotated sine product: rotation by ROT_ANGLE about the unit vector along
+    ROT_AXIS (axis-angle / Rodrigues form)."""
     u = np.asarray(ROT_AXIS, dtype=float)
     u = u / np.linalg.norm(u)
     c, s = np.cos(ROT_ANGLE), np.sin(ROT_ANGLE)
     ux = np.array([[0.0, -u[2], u[1]], [u[2], 0.0, -u[0]], [-u[1], u[0], 0.0]])
-    R = c * np.eye(3) + s * ux + (1.0 - c) * np.outer(u, u)
+    return c * np.eye(3) + s * ux + (1.0 - c) * np.outer(u, u)
+
+
+def rotated_sine_n2(N: int, dx: float, z: float, n0: float = 1.2, dn: float = 0.025, q: float = 1.0,
+                    k0: float = 2.0 * np.pi) -> np.ndarray:
+    """n^2 on the plane z of the rotated sine product of Sec. 5 (eq. sineprod):
+    n = n0 + dn sin(ks x~) sin(ks y~) sin(ks z~), ks = k0 n0 / (sqrt(3) q), with
+    (x~, y~, z~) = R (x, y, z) (rotation_matrix()); x, y on the grid's coordinates."""
+    R = rotation_matrix()
     xs = coords(N, dx)
     X, Y = np.meshgrid(xs, xs)
     P = np.stack([X, Y, np.full_like(X, z)])
