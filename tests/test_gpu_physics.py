@@ -100,3 +100,39 @@ def test_gaussian_beam_peaks_against_closed_form(beam, N):
     paper_gap = abs(PAPER[f"{beam}_beam_peak_propagator"] - exact) / exact
     print(f"{beam} beam: peak {peak:.6f}, closed form {exact:.6f}, relative gap {gap:.2e} (paper {paper_gap:.2e})")
     assert gap < 0.01 and gap < 3 * paper_gap
+
+
+def test_aperture_with_the_pseudo_differential_form():
+    """The same aperture problem through the pseudo-differential form (25 Cauchy-integral
+    terms of sqrt(1+z), one RK4 substep per lambda/20 step: stable, since lambda/20 < lambda/8):
+    the centerline intensity also meets the paper's propagator's accuracy against eq.
+    eq_apersoln."""
+    torch = _cuda()
+    from oracle import sqrt_form as sf
+    from paper_2410_17446_amd import hp
+    N, dx, W, a, dz, L = 384, 0.25, 48, 10.0, 0.05, 120.0
+    nsteps = int(round(L / dz))
+    c, d = stencil.stencils()
+    pf = sf.cauchy_sqrt_pf(25, 1.0)
+    plan = hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=K0, n0=1.0, dz=dz, ncomp=1, poles=pf.poles,
+                   residues=pf.residues, r_inf=pf.r_inf, d2=c, d1=d, edge_width=W, edge_eta=0.25,
+                   tol=1e-10, restart=30, max_cycles=20)
+    assert plan.set_form(hp.HP_FORM_SQRT, 1) in (hp.HP_OK, hp.HP_WARN_UNSTABLE)
+    x = inputs.coords(N, dx)
+    X, Y = np.meshgrid(x, x)
+    w = (X ** 2 + Y ** 2 <= a * a).astype(complex)[None]
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    plan.set_medium(to_gpu(np.ones((N, N))))
+    A, B = to_gpu(w), torch.empty_like(to_gpu(w))
+    centre = torch.empty(nsteps, dtype=torch.complex128, device="cuda")
+    for s in range(nsteps):
+        plan.step(A, E_out=B)
+        centre[s] = B[0, N // 2, N // 2]
+        A, B = B, A
+    I = np.abs(centre.cpu().numpy()) ** 2
+    z = dz * np.arange(1, nsteps + 1)
+    ref = aperture_intensity(z, a, K0)
+    err = np.linalg.norm(I - ref) / np.linalg.norm(ref)
+    print(f"aperture, pseudo-differential form: centerline intensity relative L2 {err:.3e}")
+    assert err < PAPER["aperture_centerline_l2_propagator"]
