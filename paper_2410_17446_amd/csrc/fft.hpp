@@ -276,6 +276,27 @@ __device__ __forceinline__ cx<T> group_scan(cx<T> v, cx<T>* scr, int t) {
 // buf holds X_0 = 0, X_1..X_{n-1}.  tw: n FFT twiddles followed by
 // sin(pi j/n), j = 0..n/2, in the real parts.  NT = n/8 threads per transform,
 // t in [0, NT).  The caller synchronises before (buf written) and reads after.
+// Pre-processing of one pair (j, n - j), 0 < j < n/2, of the DST-I below: with
+// s = sin(pi j/n), y_j = s (x_j + x_{n-j}) + (x_j - x_{n-j})/2 and
+// y_{n-j} = s (x_j + x_{n-j}) - (x_j - x_{n-j})/2 (y_{n/2} = 2 x_{n/2}, y_0 = 0).
+template <typename T>
+__device__ __forceinline__ void dst1_pair(cx<T> a, cx<T> b, T sj, cx<T>& ya, cx<T>& yb) {
+  const cx<T> sum = sj * (a + b), dif = (T)0.5 * (a - b);
+  ya = sum + dif;
+  yb = sum - dif;
+}
+
+// The DST-I below from its pre-processed input y (in buf): the length-n FFT
+// and the post-processing, which stores op(p, X_p) for p = 1..n-1 (X_0 = 0
+// stays).  Same calling rules as dst1.
+template <typename T, int N, typename Op>
+__device__ __forceinline__ void dst1_core_op(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t, Op op);
+
+template <typename T, int N>
+__device__ __forceinline__ void dst1_core(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t) {
+  dst1_core_op<T, N>(buf, tw, scr, t, [](int, cx<T> v) { return v; });
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t) {
   constexpr int NT = N / 8;
@@ -288,14 +309,20 @@ __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, c
     if (j == N / 2) {
       buf[pidx<T>(j)] = (T)2 * sj * a;
     } else {
-      const cx<T> b = buf[pidx<T>(N - j)];
-      const cx<T> sum = sj * (a + b), dif = (T)0.5 * (a - b);
-      buf[pidx<T>(j)] = sum + dif;
-      buf[pidx<T>(N - j)] = sum - dif;
+      cx<T> ya, yb;
+      dst1_pair(a, buf[pidx<T>(N - j)], sj, ya, yb);
+      buf[pidx<T>(j)] = ya;
+      buf[pidx<T>(N - j)] = yb;
     }
   }
   if (t == 0) buf[pidx<T>(0)] = mk<T>(0, 0);
   __syncthreads();
+  dst1_core<T, N>(buf, tw, scr, t);
+}
+
+template <typename T, int N, typename Op>
+__device__ __forceinline__ void dst1_core_op(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* scr, int t, Op op) {
+  constexpr int NT = N / 8;
   fft<T, N>(buf, tw, t);
   // post-processing: thread t owns k = 4t+1 .. 4t+4 (k <= n/2 - 1)
   const cx<T> f0 = buf[pidx<T>(0)];
@@ -318,13 +345,13 @@ __device__ __forceinline__ void dst1(cx<T>* buf, const cx<T>* __restrict__ tw, c
   for (int i = 0; i < 4; ++i) {
     const int k = 4 * t + 1 + i;
     if (k < N / 2) {
-      buf[pidx<T>(2 * k)] = ev[i];
-      buf[pidx<T>(2 * k + 1)] = base + od[i];
+      buf[pidx<T>(2 * k)] = op(2 * k, ev[i]);
+      buf[pidx<T>(2 * k + 1)] = op(2 * k + 1, base + od[i]);
     }
   }
   if (t == 0) {
     buf[pidx<T>(0)] = mk<T>(0, 0);
-    buf[pidx<T>(1)] = (T)0.5 * f0;
+    buf[pidx<T>(1)] = op(1, (T)0.5 * f0);
   }
   __syncthreads();
 }

@@ -276,28 +276,47 @@ __global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_
   const double mq = mu_x[q] - b.re, li = -b.im;
   cx<C>* bc = lds + c * PL;
   const PStep<C, NT> at(r0);
+  const cx<C>* sintab = tw + N;
+  // divide by mu_y[p] + mu_x[q] - b (one FP64 division)
+  auto divide = [&](cx<C> X, int p) {
+    const double lr = mu_y[p] + mq, inv = 1.0 / (lr * lr + li * li);
+    return (scale * X) * mk<C>((C)(lr * inv), (C)(-li * inv));
+  };
   {
+    // load fused with the first transform's pre-processing: thread (c, r0) takes the
+    // row pairs (j, N - j), j = r0 + i NT < N/2, of its column, and row N/2 when r0 = 0
 #pragma unroll 2
-    for (int i = 0; i < N / NT; ++i) {
-      const int r = r0 + i * NT;
-      bc[at(i)] = r == 0 ? czero<C>() : cvt<C>(u[(size_t)r * TW + c0 + c]);
-    }
-    __syncthreads();
-    dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
-    // divide by mu_y[p] + mu_x[q] - b (each (p, c) read and written by one thread)
-#pragma unroll 2
-    for (int i = 0; i < N / NT; ++i) {
-      const int p = r0 + i * NT;
-      if (p == 0) {
-        bc[at(i)] = czero<C>();
+    for (int i = 0; i < N / (2 * NT); ++i) {
+      const int j = r0 + i * NT;
+      if (j == 0) {
+        bc[pidx<C>(0)] = czero<C>();
+        bc[pidx<C>(N / 2)] = (C)2 * cvt<C>(u[(size_t)(N / 2) * TW + c0 + c]);
         continue;
       }
-      const cx<C> X = scale * bc[at(i)];
-      const double lr = mu_y[p] + mq, inv = 1.0 / (lr * lr + li * li);  // one FP64 division
-      bc[at(i)] = X * mk<C>((C)(lr * inv), (C)(-li * inv));
+      cx<C> ya, yb;
+      dst1_pair(cvt<C>(u[(size_t)j * TW + c0 + c]), cvt<C>(u[(size_t)(N - j) * TW + c0 + c]), sintab[j].re, ya,
+                yb);
+      bc[at(i)] = ya;
+      bc[pidx<C>(N - j)] = yb;
     }
     __syncthreads();
-    dst1<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    dst1_core<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
+    // the divide fused with the inverse transform's pre-processing, same pairs
+#pragma unroll 1
+    for (int i = 0; i < N / (2 * NT); ++i) {
+      const int j = r0 + i * NT;
+      if (j == 0) {
+        bc[pidx<C>(0)] = czero<C>();
+        bc[pidx<C>(N / 2)] = (C)2 * divide(bc[pidx<C>(N / 2)], N / 2);
+        continue;
+      }
+      cx<C> ya, yb;
+      dst1_pair(divide(bc[at(i)], j), divide(bc[pidx<C>(N - j)], N - j), sintab[j].re, ya, yb);
+      bc[at(i)] = ya;
+      bc[pidx<C>(N - j)] = yb;
+    }
+    __syncthreads();
+    dst1_core<C, N>(lds + g * PL, tw, scr + g * CC::SCR, t);
 #pragma unroll 2
     for (int i = 0; i < N / NT; ++i) {
       const int p = r0 + i * NT;
@@ -369,23 +388,38 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
   const PStep<C, NT> at(t);                                    // LDS index of point t + s NT
 
   const cx<T>* z = zbase + k * zsp + m * zsi;
-#pragma unroll
-  for (int s = 0; s < PT; ++s) {
-    const int j = t + s * NT;
-    buf[at(s)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
-  }
-  __syncthreads();
-  dst1<C, N>(buf, tw, sg, t);
-  cx<C> pz[PT];  // P z at the thread's points j = t + s * NT
+  cx<C> pz[PT];  // P z at the thread's points j = t + s * NT (vector fields)
   if constexpr (NC == 1) {
+    // load fused with the inverse transform's pre-processing: thread t takes the point
+    // pairs (j, N - j), j = t + s NT < N/2, of its row, and point N/2 when t = 0
+    const cx<C>* sintab = tw + N;
+    const size_t rbase = cbase + tix<TW>(valid ? row : 0, 0, ny);
+#pragma unroll 2
+    for (int s = 0; s < PT / 2; ++s) {
+      const int j = t + s * NT;
+      if (j == 0) {
+        buf[pidx<C>(0)] = czero<C>();
+        buf[pidx<C>(N / 2)] = valid ? (C)2 * cvt<C>(z[rbase + tix<TW>(0, N / 2, ny)]) : czero<C>();
+        continue;
+      }
+      cx<C> ya = czero<C>(), yb = czero<C>();
+      if (valid) dst1_pair(cvt<C>(z[toff.at(s)]), cvt<C>(z[rbase + tix<TW>(0, N - j, ny)]), sintab[j].re, ya, yb);
+      buf[at(s)] = ya;
+      buf[pidx<C>(N - j)] = yb;
+    }
+    __syncthreads();
+    // the inverse transform's outputs leave multiplied by the medium: P z = V z
+    dst1_core_op<C, N>(buf, tw, sg, t, [&](int p, cx<C> X) {
+      return (valid ? coef[ci0 + p] : (C)0) * (scale * X);
+    });
+  } else {
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
-      const cx<C> zj = (j == 0) ? czero<C>() : scale * buf[at(s)];
-      const C v = valid ? coef[ci0 + j] : (C)0;
-      pz[s] = v * zj;
+      buf[at(s)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
     }
-  } else {
+    __syncthreads();
+    dst1<C, N>(buf, tw, sg, t);
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
@@ -442,13 +476,15 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     }
     __syncthreads();
   }
-  // forward transform of P z
+  // forward transform of P z (already in buf for scalar fields)
+  if constexpr (NC == 2) {
 #pragma unroll
-  for (int s = 0; s < PT; ++s) {
-    const int j = t + s * NT;
-    buf[at(s)] = (j == 0) ? czero<C>() : pz[s];
+    for (int s = 0; s < PT; ++s) {
+      const int j = t + s * NT;
+      buf[at(s)] = (j == 0) ? czero<C>() : pz[s];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   dst1<C, N>(buf, tw, sg, t);
   cx<T> pv[PT];  // p as stored: the inner products use exactly what the update reads
   cx<T>* p = pbase + k * psp;
