@@ -229,7 +229,7 @@ __device__ __forceinline__ void col_block(int bid, int ntiles, int S, int& tile,
 }
 
 // Waves per SIMD for the column pass (as for the row pass: the most that
-// compile without spilling).
+// compile without spilling, but for 12 bytes at n = 128).
 template <typename C, int N>
 struct ColWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
@@ -349,10 +349,10 @@ struct ApplyCfg {
 };
 
 // Waves per SIMD the register allocation must allow, the most that compile
-// without spilling: scalar fields four (128 VGPRs) for 2^k up to 1024, else
-// three (complex128 at 2048: two); vector fields complex128 two, complex64
-// three, and four at 2048, where a workgroup is 512 threads and only four
-// waves per SIMD fit two of them per CU (at the cost of a 24-byte spill).
+// without spilling: scalar fields four (128 VGPRs; 12 bytes spill at n = 128)
+// for 2^k up to 1024, else three (complex128 at 2048: two); vector fields: two
+// complex128, three complex64, and four at 2048, where a workgroup is 512 threads
+// and only four waves per SIMD fit two of them per CU (a 48-byte spill).
 template <typename C, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
