@@ -165,10 +165,12 @@ def run_learned(args):
     Xv, Tv = learn.generate(net, fit, d2, d1, args.train_n, 1, count=8, seed=2, tol=1e-10, poles_per_field=8)
     t_gen = time.perf_counter() - t0
     print(f"# training pairs: {X.shape[0]} at {args.train_n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    learn.train(net, X, T, steps=10, batch=8, lr=1e-3)
+    learn.train(net, X, T, steps=3, batch=8, lr=1e-3)   # first calls allocate; not timed
     torch.cuda.synchronize()
-    per = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    learn.train(net, X, T, steps=20, batch=8, lr=1e-3)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / 20
     nsteps = max(10, int(args.train_seconds / per))
     net = UNet(levels, base, 7, 2, seed=0, precision=prec)
     t0 = time.perf_counter()
