@@ -80,8 +80,25 @@ def test_invalid_descriptors_are_rejected_on_the_host(bad):
 
 
 def test_null_arguments():
+    """Every entry point that takes a plan rejects a NULL plan with HP_EINVAL (-1) on the host,
+    before any device work, and records a thread-local message."""
     L = hp.lib()
     assert L.hp_plan_create(None, None, None, None) == -1
     assert L.hp_step(None, None, None, None) == -1
     assert L.hp_set_medium(None, None) == -1
+    assert L.hp_propagate(None, None, None, 0, 1, None) == -1
+    assert L.hp_solve(None, 0, None, None) == -1
+    assert L.hp_step_guess(None, None, None, None, None, None) == -1
+    assert L.hp_set_guess(None, 0) == -1
+    assert L.hp_set_form(None, 1, 8) == -1
+    assert L.hp_get_solution(None, 0, None) == -1
+    assert L.hp_apply_medium(None, None, None) == -1
+    assert L.hp_get_stats(None, None, None) == -1
+    assert L.hp_set_fixed_iters(None, None) == -1
+    assert L.hp_apply_operator(None, 0, None, None) == -1
+    assert L.hp_apply_preconditioner(None, 0, None, None) == -1
+    assert L.hp_profile(None, 0) == -1
+    assert L.hp_profile_sample(None, 1) == -1
+    assert L.hp_profile_read(None, None, None, None) == -1
+    assert b"NULL" in L.hp_last_error(None)
     L.hp_plan_destroy(None)
