@@ -434,3 +434,20 @@ def test_headline_accuracy_after_200_steps():
         err = rel_l2(run(prec, cfg["tol"]), truth)
         print(f"precision {prec}: relative L2 vs the tol 1e-12 field after {cfg['steps']} steps {err:.3e}")
         assert err < 1e-6, (prec, err)
+
+
+def test_full_step_scalar1024_matches_oracle():
+    """The benchmark's launch configuration at full size (1024^2, 16 poles in one lockstep plan,
+    sine medium of period lambda and amplitude 0.02, beam waist 32 lambda): one whole step
+    against the oracle's step at tol 1e-10, with the oracle's per-pole iteration counts replayed
+    (every solve takes one cycle), to 1e-10 relative L2."""
+    torch = _cuda()
+    wl = workload(N=1024, W=128, npoles=16, medium=("sine", 0.02, 1.0), w0=32.0, tol=1e-10)
+    ref, stats = _oracle_step(wl)
+    assert all(len(c) == 1 for c in stats.cycle_iters), stats.cycle_iters
+    plan = gpu_plan(wl)
+    plan.set_fixed_iters(_replay(stats.cycle_iters))
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"])).cpu().numpy()
+    err = rel_l2(out, ref)
+    print(f"1024^2 step vs oracle: relative L2 {err:.3e}, iterations {stats.iters}")
+    assert err < 1e-10
