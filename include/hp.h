@@ -184,8 +184,12 @@ int hp_set_guess(hp_plan plan, int mode);
  * returns HP_ESTATE while the form is HP_FORM_SQRT.
  *
  * Returns HP_WARN_UNSTABLE (form still set) when one substep amplifies some
- * free-space mode: max over the free-space spectrum of |P(h i k0 n0 (r(mu) - 1))|
- * > 1 + 1e-6, P(z) = 1 + z + z^2/2 + z^3/6 + z^4/24.  hp_plan_create's own
+ * free-space mode: the maximum of |P(h i k0 n0 (r(mu) - 1))| over the interval
+ * the free-space eigenvalues mu span exceeds 1 + 1e-6, P(z) = 1 + z + z^2/2 +
+ * z^3/6 + z^4/24.  Too long a substep fails it by orders of magnitude (the
+ * evanescent modes below mu = -1); the error of r next to mu = -1 alone can
+ * fail it slightly (about 1e-4 per lambda/8 substep for 25 Cauchy terms, a
+ * slow growth of the modes at grazing angles).  hp_plan_create's own
  * check measures |r| against 1, which a table of sqrt(1+z) exceeds by design,
  * so for such a table its HP_WARN_UNSTABLE is expected and this check is the
  * one that applies.  HP_EINVAL for an unknown form or substeps out of range. */
