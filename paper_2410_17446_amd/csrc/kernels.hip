@@ -1210,10 +1210,6 @@ __global__ void k_mark_list(PoleState* __restrict__ st, const PoleList sel) {
   }
 }
 
-__global__ void k_fill_zero(c128* p, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = mk(0.0, 0.0);
-}
 
 // One stage of the classical fourth-order Runge-Kutta combination, over the
 // fields in physical layout [ncomp][ny][nx]: acc_out = acc_in + ca L and, when
@@ -1496,9 +1492,6 @@ void launch_to_float(const double* a, float* b, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_to_float, dim3(2048), dim3(256), 0, s, a, b, n);
 }
 
-void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, p, n);
-}
 
 void launch_rk4_stage(const c128* L, const c128* acc_in, c128* acc_out, const c128* u, c128* v_out, double ca,
                       double cv, double loss_coef, double eta, int W, const Geo& g, hipStream_t s) {

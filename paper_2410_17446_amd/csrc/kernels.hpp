@@ -140,7 +140,6 @@ void launch_mark_folded(PoleState* st, int first, int count, hipStream_t s);
 // The same for the poles poles[0..n) (host array, n <= HP_MAXPOLES).
 void launch_mark_list(PoleState* st, const int* poles, int n, hipStream_t s);
 
-void launch_fill_zero_c128(c128* p, size_t n, hipStream_t s);
 
 // Classical RK4 combination of one stage (physical fields, complex128):
 // acc_out = acc_in + ca L; v_out = u + cv L unless v_out is NULL; with
