@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--train-n", type=int, default=256, help="training grid (learned workload)")
     ap.add_argument("--train-draws", type=int, default=48, help="(medium, beam) draws for training")
     ap.add_argument("--train-seconds", type=float, default=90.0, help="training time budget")
+    ap.add_argument("--event-period", type=int, default=EVENT_PERIOD,
+                    help="time every n-th launch of the dominant kernel in the timed steps")
     ap.add_argument("--no-exp-compare", action="store_true",
                     help="sqrt1024: skip the exponential-form run the field is compared with")
     ap.add_argument("--unet-precision", default="bf16", choices=["bf16", "f32"],
@@ -325,7 +327,7 @@ def run_copy(args):
 EVENT_PERIOD = 4  # the timed steps bracket every 4th launch of the dominant kernel with events
 
 
-def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None):
+def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None, event_period=EVENT_PERIOD):
     poles, residues, r_inf, d2, d1 = tables
     N = cfg["N"]
     plan = hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=hp_k0(), n0=1.0, dz=cfg["dz"], ncomp=cfg["ncomp"],
@@ -344,9 +346,9 @@ def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None
         a, b = b, a
     breakdown = plan.profile_read()
     dom = max(breakdown, key=lambda k: breakdown[k][1]) if warmup else "row_apply"
-    # timed steps: events around every EVENT_PERIOD-th launch of the dominant class only
+    # timed steps: events around every event_period-th launch of the dominant class only
     plan.profile(True, classes=[dom])
-    plan.profile_sample(EVENT_PERIOD)
+    plan.profile_sample(event_period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.propagate(a, steps, E_out=b)
@@ -489,7 +491,7 @@ def run_sqrt(args):
     w0 = torch.from_numpy(inputs.beam(cfg)).cuda()
     n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
     res = run_mode(hp, torch, cfg, tab, hp.HP_FP64, w0, n2, args.warmup, args.steps,
-                   form=(hp.HP_FORM_SQRT, SQRT_SUBSTEPS))
+                   form=(hp.HP_FORM_SQRT, SQRT_SUBSTEPS), event_period=args.event_period)
     value = args.steps / res["seconds"]
     cmp = None
     if not args.no_exp_compare:
@@ -519,7 +521,7 @@ def run_sqrt(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": by / max(n_l, 1), "launches": n_l,
                      "avg_launch_us": 1e3 * ms / max(n_l, 1),
-                     "timed": f"every {EVENT_PERIOD}th launch in the timed steps"},
+                     "timed": f"every {args.event_period}th launch in the timed steps"},
         "warmup_kernel_ms": {k: brk[k][1] for k in brk},
     }
     if not args.no_cpu_baseline:
@@ -558,7 +560,8 @@ def main():
     modes = args.modes.split(",")
     for mode in modes:
         prec = {"mixed": hp.HP_MIXED, "mixed64": hp.HP_MIXED64}.get(mode, hp.HP_FP64)
-        res[mode] = run_mode(hp, torch, cfg, tab, prec, w0, n2, args.warmup, args.steps)
+        res[mode] = run_mode(hp, torch, cfg, tab, prec, w0, n2, args.warmup, args.steps,
+                             event_period=args.event_period)
         print(f"# {mode}: {args.steps / res[mode]['seconds']:.2f} steps/s, last-step iterations "
               f"{res[mode]['iters']}", file=sys.stderr, flush=True)
     errs = {}
@@ -604,7 +607,7 @@ def main():
                      "traffic": counter_traffic(dom) if best == "fp64" else None,
                      "algorithmic_bytes_per_launch": by / max(n_l, 1),
                      "launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
-                     "timed": f"every {EVENT_PERIOD}th launch in the timed steps"},
+                     "timed": f"every {args.event_period}th launch in the timed steps"},
         "inner_loop_roofline": {"kernels": ["col", "row_apply"], "steps": "warmup",
                                 "achieved": inner_b / (inner_ms * 1e-3) / 1e9 if inner_ms > 0 else 0.0,
                                 "frac": (inner_b / (inner_ms * 1e-3) / 1e9) / HBM_PEAK_GBS if inner_ms > 0 else 0.0},
