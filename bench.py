@@ -48,9 +48,10 @@ KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "cplx.hpp", "state.hpp", "kernels.hp
 COUNTERS = os.path.join(ROOT, "profiles", "row_apply_scalar1024_fp64_hbm_counters.md")
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary, or None
-    when there is none for it or the kernel sources changed since it was taken."""
+def counter_traffic(kernel, workload="scalar1024"):
+    """HBM bytes per launch of `kernel` on `workload` (FP64) from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when there is none for that pair or the kernel sources changed since it was
+    taken."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -61,7 +62,8 @@ def counter_traffic(kernel):
             kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
     except OSError:
         return None
-    if kv.get("source_sha256", "").strip() != h.hexdigest() or kv.get("traffic_kernel", "").strip() != kernel:
+    if (kv.get("source_sha256", "").strip() != h.hexdigest() or kv.get("traffic_kernel", "").strip() != kernel
+            or kv.get("traffic_workload", "").strip() != workload):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -604,7 +606,7 @@ def main():
                   for m in res},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(dom) if best == "fp64" else None,
+                     "traffic": counter_traffic(dom, args.config) if best == "fp64" else None,
                      "algorithmic_bytes_per_launch": by / max(n_l, 1),
                      "launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
                      "timed": f"every {args.event_period}th launch in the timed steps"},

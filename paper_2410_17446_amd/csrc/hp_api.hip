@@ -173,7 +173,6 @@ std::string validate(const hp_plan_desc* d) {
   if (d->ncomp != 1 && d->ncomp != 2) return "ncomp must be 1 or 2";
   if (d->precision != HP_FP64 && d->precision != HP_MIXED && d->precision != HP_MIXED64)
     return "precision must be HP_FP64, HP_MIXED or HP_MIXED64";
-  if (d->ncomp == 2 && d->precision == HP_FP64 && d->nx > 1024) return "FP64 vector plans support n <= 1024";
   if (!(d->dx > 0) || !(d->dy > 0) || !(d->k0 > 0) || !(d->n0 > 0) || !(d->dz > 0)) return "dx, dy, k0, n0, dz must be > 0";
   if (d->npoles < 1 || d->npoles > HP_MAXPOLES - 4) return "npoles must be in [1, 60]";
   if (!d->poles || !d->residues) return "poles/residues are NULL";

@@ -67,7 +67,7 @@ def test_workspace_bytes_scales_with_problem():
 
 @pytest.mark.parametrize("bad", [dict(nx=100), dict(nx=32), dict(ncomp=3), dict(edge_width=5),
                                  dict(tol=0.0), dict(restart=0), dict(restart=65), dict(npoles=0),
-                                 dict(precision=7), dict(dz=-1.0), dict(nx=2048, ny=2048, ncomp=2),
+                                 dict(precision=7), dict(dz=-1.0), dict(nx=4096, ny=4096),
                                  dict(edge_width=30)])
 def test_invalid_descriptors_are_rejected_on_the_host(bad):
     L = hp.lib()

@@ -19,3 +19,4 @@ def test_counter_record_matches_the_kernel_sources():
     sys.path.insert(0, ROOT)
     import bench
     assert bench.counter_traffic("row_apply") is not None
+    assert bench.counter_traffic("row_apply", "vector2048") is None   # taken on scalar1024 only
