@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--config", default="scalar1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="mixed,mixed64,fp64")
+    ap.add_argument("--autotune", type=int, default=4,
+                    help="timed steps per column-pass variant before the warmup (0: the default variant)")
     ap.add_argument("--cpu-poles", type=int, default=8, help="poles of one oracle step in the CPU sample")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (batch64 workload)")
     ap.add_argument("--unet-base", type=int, default=32, help="U-Net base channels (learned workload)")
@@ -329,7 +331,8 @@ def run_copy(args):
 EVENT_PERIOD = 4  # the timed steps bracket every 4th launch of the dominant kernel with events
 
 
-def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None, event_period=EVENT_PERIOD):
+def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None, event_period=EVENT_PERIOD,
+             autotune=0):
     poles, residues, r_inf, d2, d1 = tables
     N = cfg["N"]
     plan = hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=hp_k0(), n0=1.0, dz=cfg["dz"], ncomp=cfg["ncomp"],
@@ -341,6 +344,9 @@ def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None
     plan.set_medium(n2)
     a = w0.clone()
     b = torch.empty_like(a)
+    # launch-shape autotuner (before the warmup, outside the timed region): `autotune` timed steps
+    # per column-pass variant, the plan keeps the fastest
+    variant = plan.autotune(a, reps=autotune, E_out=b)[1] if autotune else 1
     # warmup: every kernel class timed (the per-class breakdown, and which class dominates)
     plan.profile(True)
     if warmup:
@@ -360,7 +366,8 @@ def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None
     iters, relres = plan.stats()
     plan.profile(False)
     plan.close()
-    return dict(seconds=dt, field=b, prof=prof, dom=dom, breakdown=breakdown, iters=iters, relres=relres)
+    return dict(seconds=dt, field=b, prof=prof, dom=dom, breakdown=breakdown, iters=iters, relres=relres,
+                variant=variant)
 
 
 def hp_k0():
@@ -562,7 +569,7 @@ def main():
     modes = args.modes.split(",")
     for mode in modes:
         prec = {"mixed": hp.HP_MIXED, "mixed64": hp.HP_MIXED64}.get(mode, hp.HP_FP64)
-        res[mode] = run_mode(hp, torch, cfg, tab, prec, w0, n2, args.warmup, args.steps,
+        res[mode] = run_mode(hp, torch, cfg, tab, prec, w0, n2, args.warmup, args.steps, autotune=args.autotune,
                              event_period=args.event_period)
         print(f"# {mode}: {args.steps / res[mode]['seconds']:.2f} steps/s, last-step iterations "
               f"{res[mode]['iters']}", file=sys.stderr, flush=True)
@@ -599,7 +606,7 @@ def main():
         "dtype": {"mixed": "c64+f64", "mixed64": "c64 storage, f64 arithmetic"}.get(best, "c128"),
         "data": "synthetic",
         "config": {"workload": args.config, "grid": cfg["N"], "poles": cfg["npoles"], "tol": cfg["tol"],
-                   "mode": best, "method": "plain (zero initial guess)"},
+                   "mode": best, "method": "plain (zero initial guess)", "column_variant": r["variant"]},
         "err_vs_fp64": errs.get(best, 0.0 if best == "fp64" else None),
         "err_vs_fp64_by_mode": errs,
         "modes": {m: {"steps_per_s": args.steps / res[m]["seconds"], "last_step_iters": res[m]["iters"]}

@@ -163,6 +163,26 @@ int hp_step_guess(hp_plan plan, const void* E_in, const double* n2, const void* 
 enum { HP_GUESS_ZERO = 0, HP_GUESS_PREV = 1 };
 int hp_set_guess(hp_plan plan, int mode);
 
+/* Autotuner of the launch shape (not an operation of the method: it changes
+ * no arithmetic, only how the shifted solves are launched).  The column
+ * pass of the preconditioner is built for three LDS budgets per workgroup (20,
+ * 40 and 80 KB: one to four complex128 columns of 1024 at once, more for
+ * complex64 or shorter columns); which is fastest depends on the grid, the
+ * precision and the number of poles.  hp_autotune takes one step E_in -> E_out
+ * with each variant untimed, then `reps` (1..100) timed steps each from the
+ * same E_in, keeps the fastest variant in the plan for every later call, and
+ * ends with one step by it, so E_out and hp_get_stats are that variant's.
+ * E_in, E_out: device [ncomp][ny][nx] complex128, E_out must not alias E_in;
+ * n2 as for hp_step (NULL keeps the medium).  variant (may be NULL) receives
+ * 0, 1 or 2.  Synchronises the plan's stream; returns the last step's code
+ * (HP_EINVAL on bad arguments, the plan unchanged).  A new plan uses variant 1. */
+int hp_autotune(hp_plan plan, const void* E_in, const double* n2, int reps, void* E_out, int* variant);
+
+/* Set the column-pass variant (0, 1 or 2, as hp_autotune reports it) directly,
+ * e.g. to reuse a choice measured once for plans of the same shape.  HP_EINVAL
+ * for another value. */
+int hp_set_launch(hp_plan plan, int col_variant);
+
 /* What a step does with the pole table.
  *
  * HP_FORM_EXP (default): the table is the partial-fraction form of a rational

@@ -1043,6 +1043,55 @@ int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* con
   return rc;
 }
 
+int hp_set_launch(hp_plan p, int col_variant) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (col_variant < 0 || col_variant > 2) return fail(p, HP_EINVAL, "col_variant must be 0, 1 or 2");
+  p->geo.col_variant = col_variant;
+  return HP_OK;
+}
+
+int hp_autotune(hp_plan p, const void* E_in, const double* n2, int reps, void* E_out, int* variant) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!E_in || !E_out) return fail(p, HP_EINVAL, "E_in/E_out is NULL");
+  if (E_in == E_out) return fail(p, HP_EINVAL, "E_out must not alias E_in (every timed step starts from E_in)");
+  if (reps < 1 || reps > 100) return fail(p, HP_EINVAL, "reps must be in [1, 100]");
+  if (n2) {
+    int rc = hp_set_medium(p, n2);
+    if (rc) return rc;
+  }
+  if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
+  const int keep = p->geo.col_variant;
+  double best = 0.0;
+  int bestv = keep;
+  for (int v = 0; v < 3; ++v) {
+    p->geo.col_variant = v;
+    int rc = hp_step(p, E_in, nullptr, E_out);  // untimed: first use of this variant's kernels
+    if (rc < 0) {
+      p->geo.col_variant = keep;
+      return rc;
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+      p->geo.col_variant = keep;
+      return fail(p, HP_EHIP, "hipStreamSynchronize failed while timing");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps && rc >= 0; ++r) {
+      p->prev_valid = false;  // every timed step starts from the same state
+      rc = hp_step(p, E_in, nullptr, E_out);
+    }
+    if (rc < 0 || hipStreamSynchronize(p->stream) != hipSuccess) {
+      p->geo.col_variant = keep;
+      return rc < 0 ? rc : fail(p, HP_EHIP, "hipStreamSynchronize failed while timing");
+    }
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (v == 0 || dt < best) best = dt, bestv = v;
+  }
+  p->geo.col_variant = bestv;
+  if (variant) *variant = bestv;
+  p->prev_valid = false;
+  return hp_step(p, E_in, nullptr, E_out);  // E_out and the statistics from the chosen variant
+}
+
 int hp_set_guess(hp_plan p, int mode) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
   if (mode != HP_GUESS_ZERO && mode != HP_GUESS_PREV) return fail(p, HP_EINVAL, "unknown guess mode");

@@ -64,14 +64,18 @@ struct RowCfg {
   static constexpr int SCR = ScanScratch<NT>::SIZE;          // scan scratch per transform
 };
 
-constexpr int kColLdsBytes = 40960;  // several column workgroups per CU
+// LDS budget of a column workgroup's transform buffers, which sets how many
+// columns it transforms at once.  Three budgets are built; the plan uses the
+// middle one (two complex128 columns of 1024 per workgroup, four workgroups per
+// CU) unless hp_autotune measured another to be faster for its shape.
+constexpr int kColLds[3] = {20480, 40960, 81920};
 
-template <typename T, typename C, int N>
+template <typename T, typename C, int N, int LB = 40960>
 struct ColCfg {
   static constexpr int TW = Tile<T>::W;
   static constexpr int NT = N / 8;
   static constexpr int PB = plen<C>(N) * (int)sizeof(cx<C>);
-  static constexpr int G0 = kColLdsBytes / PB;
+  static constexpr int G0 = LB / PB;
   static constexpr int G1 = G0 < 1 ? 1 : (G0 > TW ? TW : G0);
   static constexpr int G2 = (G1 * NT > 1024) ? 1024 / NT : G1;
   // columns transformed at once: a power of two, so that it divides the tile width
@@ -236,13 +240,13 @@ struct ColWaves {
   static constexpr int V = (N <= 1024 && POW2) ? 4 : 2;
 };
 
-template <typename T, typename C, int N, int NC>
-__global__ __launch_bounds__((ColCfg<T, C, N>::WG), (ColWaves<C, N>::V)) void k_col(
+template <typename T, typename C, int N, int NC, int LB>
+__global__ __launch_bounds__((ColCfg<T, C, N, LB>::WG), (ColWaves<C, N>::V)) void k_col(
     const cx<T>* const* __restrict__ uptr, cx<T>* __restrict__ zbase, size_t zsp, size_t zsi,
     cx<T>* __restrict__ dzbase, size_t dzsp, const PoleState* __restrict__ st, const PoleList list,
     int* __restrict__ active_out, const double* __restrict__ mu_x, const double* __restrict__ mu_y,
     const cx<C>* __restrict__ tw, size_t fsz, StencilCoef sc) {
-  using CC = ColCfg<T, C, N>;
+  using CC = ColCfg<T, C, N, LB>;
   constexpr int NT = CC::NT, TW = CC::TW, GC = CC::GC, WG = CC::WG, S = TW / GC;
   constexpr int PL = CC::PLC;  // padded per-column stride
   __shared__ cx<C> lds[GC * PL];
@@ -1327,18 +1331,28 @@ void launch_col(const cx<T>* const* uptr, cx<T>* zbase, size_t zsp, size_t zsi, 
   PoleList list;
   list.n = nactive;
   for (int a = 0; a < HP_MAXPOLES; ++a) list.k[a] = a < nactive ? poles[a] : 0;
+#define COLV_(NN, LB)                                                                                          \
+  {                                                                                                            \
+    dim3 grid(g.nx / ColCfg<T, C, NN, LB>::GC, g.ncomp * nactive);                                             \
+    if (g.ncomp == 1)                                                                                          \
+      hipLaunchKernelGGL((k_col<T, C, NN, 1, LB>), grid, dim3(ColCfg<T, C, NN, LB>::WG), 0, s, uptr, zbase,    \
+                         zsp, zsi, dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);             \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_col<T, C, NN, 2, LB>), grid, dim3(ColCfg<T, C, NN, LB>::WG), 0, s, uptr, zbase,    \
+                         zsp, zsi, dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);             \
+  }
 #define L_(NN)                                                                                                 \
   {                                                                                                            \
-    dim3 grid(g.nx / ColCfg<T, C, NN>::GC, g.ncomp * nactive);                                                 \
-    if (g.ncomp == 1)                                                                                          \
-      hipLaunchKernelGGL((k_col<T, C, NN, 1>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
-                         dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);                       \
+    if (g.col_variant == 0)                                                                                    \
+      COLV_(NN, kColLds[0])                                                                                    \
+    else if (g.col_variant == 2)                                                                               \
+      COLV_(NN, kColLds[2])                                                                                    \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_col<T, C, NN, 2>), grid, dim3(ColCfg<T, C, NN>::WG), 0, s, uptr, zbase, zsp, zsi,   \
-                         dzbase, dzsp, st, list, active_out, mu_x, mu_y, tw, g.fsz, sc);                       \
+      COLV_(NN, kColLds[1])                                                                                    \
   }
   HP_DISPATCH_N(g.ny, L_)
 #undef L_
+#undef COLV_
 }
 
 static int apply_groups(const Geo& g) {

@@ -15,7 +15,8 @@ struct StencilCoef {
 
 struct Geo {
   int nx, ny, ncomp;
-  size_t fsz;  // nx * ny
+  size_t fsz;           // nx * ny
+  int col_variant = 1;  // column-pass LDS budget: 0, 1, 2 = 20, 40, 80 KB per workgroup
 };
 
 // Row DST-I of the unknowns of a complex128 field (physical, row-major): out

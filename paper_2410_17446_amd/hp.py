@@ -22,7 +22,7 @@ HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
 HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_step_guess", "hp_set_guess", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_last_error", "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
@@ -63,6 +63,8 @@ def lib():
         L.hp_solve.argtypes = [vp, C.c_int, vp, vp]
         L.hp_step_guess.argtypes = [vp, vp, vp, C.POINTER(vp), ip, vp]
         L.hp_set_guess.argtypes = [vp, C.c_int]
+        L.hp_autotune.argtypes = [vp, vp, vp, C.c_int, vp, ip]
+        L.hp_set_launch.argtypes = [vp, C.c_int]
         L.hp_get_solution.argtypes = [vp, C.c_int, vp]
         L.hp_apply_medium.argtypes = [vp, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
@@ -174,6 +176,20 @@ class Plan:
         rc = self.L.hp_step_guess(self.handle, _ptr(E_in), _ptr(n2), arr, acc, _ptr(E_out))
         self._check(rc, "hp_step_guess")
         return E_out, list(acc)
+
+    def autotune(self, E_in, n2=None, reps=3, E_out=None):
+        """Time the column-pass variants on steps from E_in, keep the fastest; returns
+        (E_out, variant)."""
+        import torch
+        if E_out is None:
+            E_out = torch.empty_like(E_in)
+        v = C.c_int(-1)
+        rc = self.L.hp_autotune(self.handle, _ptr(E_in), _ptr(n2), int(reps), _ptr(E_out), C.byref(v))
+        self._check(rc, "hp_autotune")
+        return E_out, v.value
+
+    def set_launch(self, col_variant):
+        return self._check(self.L.hp_set_launch(self.handle, int(col_variant)), "hp_set_launch")
 
     def set_guess(self, mode):
         return self._check(self.L.hp_set_guess(self.handle, int(mode)), "hp_set_guess")

@@ -281,6 +281,36 @@ def test_vector2048_properties(precision):
     assert float(out[1].abs().max()) > 0.0   # cross-polarisation appears in the random medium
 
 
+@pytest.mark.parametrize("N,ncomp,precision", [(256, 1, 0), (128, 2, 0), (256, 1, 1), (1024, 1, 0)])
+def test_column_variants_and_autotune(N, ncomp, precision):
+    """The three column-pass launch shapes transform every column with the same arithmetic: the
+    step's field and iteration counts agree across them (the oracle parity tests run the
+    default one); hp_autotune returns one of them and the step it ends with."""
+    _cuda()
+    wl = workload(N=N, ncomp=ncomp, W=N // 8, npoles=16 if N == 1024 else 8, medium=("sine", 0.02, 1.0),
+                  w0=N * 0.25 / 8, tol=1e-8)
+    plan = gpu_plan(wl, precision=precision)
+    w, n2 = to_gpu(wl["w"]), to_gpu(wl["n2"])
+    outs, its = [], []
+    for v in range(3):
+        plan.set_launch(v)
+        outs.append(plan.step(w, n2).cpu().numpy())
+        its.append(plan.stats()[0])
+    tol = 1e-13 if precision == 0 else 1e-6
+    for v in (0, 2):
+        assert rel_l2(outs[v], outs[1]) <= tol, v
+        if precision == 0:
+            assert its[v] == its[1], v
+    out, chosen = plan.autotune(w, reps=2)
+    assert chosen in (0, 1, 2)
+    assert rel_l2(out.cpu().numpy(), outs[chosen]) <= tol
+    with pytest.raises(Exception):
+        plan.set_launch(3)
+    with pytest.raises(Exception):
+        plan.autotune(w, E_out=w)   # the timed steps need E_in intact
+    plan.close()
+
+
 @pytest.mark.parametrize("N,precision", [(192, 0), (384, 0), (768, 1)])
 def test_radix3_sizes(N, precision):
     """3 * 2^k grids (radix-3 stage): preconditioner and one step against the oracle."""
