@@ -283,6 +283,10 @@ int hp_batch_propagate(hp_batch batch, const void* const* E_in, const double* co
                        void* const* E_out);
 /* Per problem: GMRES iterations summed over poles and steps, wall seconds. */
 int hp_batch_stats(hp_batch batch, long* iters, double* seconds);
+/* Column-pass launch variant per problem (nprob values, each 0, 1 or 2, as
+ * hp_autotune reports them for a plan of that problem's shape; 1 until set).
+ * HP_EINVAL for a NULL argument or a value out of range (nothing changed). */
+int hp_batch_set_launch(hp_batch batch, const int* variants);
 void hp_batch_destroy(hp_batch batch);
 
 #ifdef __cplusplus

@@ -1312,9 +1312,20 @@ struct hp_batch_s {
   std::vector<void*> worker_ws;        // one workspace per worker, kept across calls
   std::vector<long> iters;
   std::vector<double> seconds;
+  std::vector<int> variant;            // column-pass launch variant per problem
 };
 
 extern "C" {
+
+int hp_batch_set_launch(hp_batch b, const int* variants) {
+  if (!b) return fail(nullptr, HP_EINVAL, "batch is NULL");
+  if (!variants) return fail(nullptr, HP_EINVAL, "variants is NULL");
+  for (size_t i = 0; i < b->variant.size(); ++i)
+    if (variants[i] < 0 || variants[i] > 2)
+      return fail(nullptr, HP_EINVAL, "problem " + std::to_string(i) + ": column variant must be 0, 1 or 2");
+  b->variant.assign(variants, variants + b->variant.size());
+  return HP_OK;
+}
 
 int hp_batch_create(const hp_plan_desc* descs, int nprob, int nworkers, hp_batch* out) {
   if (!out) return fail(nullptr, HP_EINVAL, "out is NULL");
@@ -1346,6 +1357,7 @@ int hp_batch_create(const hp_plan_desc* descs, int nprob, int nworkers, hp_batch
   }
   b->iters.assign(nprob, 0);
   b->seconds.assign(nprob, 0.0);
+  b->variant.assign(nprob, 1);
   for (int i = 0; i < nprob; ++i) b->ws_bytes = std::max(b->ws_bytes, hp_workspace_bytes(&b->descs[i]));
   b->worker_ws.assign(nworkers, nullptr);
   *out = b;
@@ -1397,6 +1409,7 @@ int hp_batch_propagate(hp_batch b, const void* const* E_in, const double* const*
       hp_plan p = nullptr;
       int rc = hp_plan_create(&b->descs[i], s, b->worker_ws[me], &p);
       if (rc >= 0) {
+        p->geo.col_variant = b->variant[i];
         const int mrc = hp_set_medium(p, n2[i]);
         if (mrc < 0) rc = mrc;
       }

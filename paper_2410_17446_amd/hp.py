@@ -22,7 +22,7 @@ HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
 HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_last_error", "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
@@ -65,6 +65,7 @@ def lib():
         L.hp_set_guess.argtypes = [vp, C.c_int]
         L.hp_autotune.argtypes = [vp, vp, vp, C.c_int, vp, ip]
         L.hp_set_launch.argtypes = [vp, C.c_int]
+        L.hp_batch_set_launch.argtypes = [vp, ip]
         L.hp_get_solution.argtypes = [vp, C.c_int, vp]
         L.hp_apply_medium.argtypes = [vp, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
@@ -293,6 +294,15 @@ class Batch:
         if rc < 0:
             raise HPError(f"hp_batch_create: {rc}: {self.L.hp_last_error(None).decode()}")
         self.shapes = [(pr["ncomp"], pr["ny"], pr["nx"]) for pr in problems]
+
+    def set_launch(self, variants):
+        """Column-pass launch variant per problem (0, 1 or 2; see Plan.autotune)."""
+        if len(variants) != self.n:
+            raise HPError("one variant per problem")
+        arr = (C.c_int * self.n)(*[int(v) for v in variants])
+        rc = self.L.hp_batch_set_launch(self.handle, arr)
+        if rc < 0:
+            raise HPError(f"hp_batch_set_launch: {rc}: {self.L.hp_last_error(None).decode()}")
 
     def propagate(self, E_in, n2, nsteps, E_out=None):
         import torch

@@ -92,6 +92,7 @@ def test_null_arguments():
     assert L.hp_set_guess(None, 0) == -1
     assert L.hp_autotune(None, None, None, 1, None, None) == -1
     assert L.hp_set_launch(None, 1) == -1
+    assert L.hp_batch_set_launch(None, None) == -1
     assert L.hp_set_form(None, 1, 8) == -1
     assert L.hp_get_solution(None, 0, None) == -1
     assert L.hp_apply_medium(None, None, None) == -1

@@ -222,6 +222,14 @@ def test_batch_equals_single_plans():
     for o, ref in zip(outs, singles):
         assert np.array_equal(o.cpu().numpy(), ref)
     assert all(i > 0 for i in it)
+    # per-problem column-pass launch variants change no arithmetic
+    b.set_launch([0, 2, 1, 0, 2, 1])
+    outs = b.propagate(ins, meds, [3] * len(specs))
+    torch.cuda.synchronize()
+    for o, ref in zip(outs, singles):
+        assert rel_l2(o.cpu().numpy(), ref) <= 1e-13
+    with pytest.raises(Exception):
+        b.set_launch([0, 1, 2, 3, 1, 1])
 
 
 def test_solve_full_size_scalar1024():
