@@ -341,6 +341,28 @@ __global__ __launch_bounds__((ColCfg<T, C, N, LB>::WG), (ColWaves<C, N>::V)) voi
 
 // ------------------------------------------------------------------ row pass (medium part + inner products)
 
+// Load of one row of an R-domain field fused with the DST-I pre-processing:
+// thread t takes the point pairs (j, N - j), j = t + s NT < N/2, and point N/2
+// when t = 0; an invalid row loads zeros.
+template <typename T, typename C, int N, int NT, int TW>
+__device__ __forceinline__ void load_pre_row(cx<C>* buf, const cx<T>* __restrict__ src, const RowWalk<TW, NT>& toff,
+                                             size_t rbase, int ny, bool valid, int t, const PStep<C, NT>& at,
+                                             const cx<C>* __restrict__ sintab) {
+#pragma unroll 2
+  for (int s = 0; s < N / (2 * NT); ++s) {
+    const int j = t + s * NT;
+    if (j == 0) {
+      buf[pidx<C>(0)] = czero<C>();
+      buf[pidx<C>(N / 2)] = valid ? (C)2 * cvt<C>(src[rbase + tix<TW>(0, N / 2, ny)]) : czero<C>();
+      continue;
+    }
+    cx<C> ya = czero<C>(), yb = czero<C>();
+    if (valid) dst1_pair(cvt<C>(src[toff.at(s)]), cvt<C>(src[rbase + tix<TW>(0, N - j, ny)]), sintab[j].re, ya, yb);
+    buf[at(s)] = ya;
+    buf[pidx<C>(N - j)] = yb;
+  }
+}
+
 template <int N, int NC>
 struct ApplyCfg {
   static constexpr int NT = N / 8;
@@ -417,13 +439,11 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
       return (valid ? coef[ci0 + p] : (C)0) * (scale * X);
     });
   } else {
-#pragma unroll
-    for (int s = 0; s < PT; ++s) {
-      const int j = t + s * NT;
-      buf[at(s)] = (valid && j > 0) ? cvt<C>(z[toff.at(s)]) : czero<C>();
-    }
+    // both loads fused with their transforms' pre-processing, as for scalar fields
+    const size_t rbase = cbase + tix<TW>(valid ? row : 0, 0, ny);
+    load_pre_row<T, C, N, NT, TW>(buf, z, toff, rbase, ny, valid, t, at, tw + N);
     __syncthreads();
-    dst1<C, N>(buf, tw, sg, t);
+    dst1_core<C, N>(buf, tw, sg, t);
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
@@ -462,13 +482,9 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     }
     // D1y of both components (the column pass's second output), row-transformed
     const cx<T>* dz = dzbase + k * dzsp;
-#pragma unroll
-    for (int s = 0; s < PT; ++s) {
-      const int j = t + s * NT;
-      buf[at(s)] = (valid && j > 0) ? cvt<C>(dz[toff.at(s)]) : czero<C>();
-    }
+    load_pre_row<T, C, N, NT, TW>(buf, dz, toff, rbase, ny, valid, t, at, tw + N);
     __syncthreads();
-    dst1<C, N>(buf, tw, sg, t);
+    dst1_core<C, N>(buf, tw, sg, t);
     if (comp == 1 && valid) {
 #pragma unroll
       for (int s = 0; s < PT; ++s) {
