@@ -71,14 +71,16 @@ def aaa(Z: np.ndarray, F: np.ndarray, mmax: int):
 
 
 def lawson(Z: np.ndarray, F: np.ndarray, zj: np.ndarray, alpha: np.ndarray, beta: np.ndarray,
-           iters: int = 40):
+           iters: int = 40, score=None):
     """Lawson IRLS on separate numerator/denominator barycentric weights.
 
     With the support points fixed, minimise sum_i lam_i |F_i d(Z_i) - n(Z_i)|^2
     with n(z) = sum alpha_j/(z - z_j), d(z) = sum beta_j/(z - z_j) and
     ||(alpha, beta)|| = 1 (smallest singular vector), then set
     lam_i <- lam_i |F_i - r(Z_i)| and renormalise.  The iterate with the
-    smallest maximum error is returned.
+    smallest score is returned; score(alpha, beta) defaults to the maximum
+    barycentric error over the rows, and a non-finite score counts as +inf
+    (so a NaN never blocks the comparison).
 
     Once alpha != f_j beta, r no longer interpolates at a support point z_j,
     where r(z_j) = alpha_j/beta_j.  Each support point therefore keeps a row of
@@ -100,24 +102,35 @@ def lawson(Z: np.ndarray, F: np.ndarray, zj: np.ndarray, alpha: np.ndarray, beta
     Fa = np.concatenate([Fs, fj])
 
     def errors(a, b):
-        return np.abs(Fa - (C @ a) / (C @ b))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.abs(Fa - (C @ a) / (C @ b))
 
-    e0 = errors(alpha, beta)
-    best = (e0.max(), alpha, beta)
+    def worst(e):
+        # a row where d vanishes (r has a pole on a sample) counts as an infinite error
+        return np.inf if not np.all(np.isfinite(e)) else float(e.max())
+
+    def scored(a, b, e):
+        v = worst(e) if score is None else float(score(a, b))
+        return v if np.isfinite(v) else np.inf
+
+    best = (scored(alpha, beta, errors(alpha, beta)), alpha, beta)
     lam = np.full(len(Fa), 1.0 / len(Fa))
     for _ in range(iters):
         s = np.sqrt(lam)[:, None]
         A = np.hstack([-s * C, s * (Fa[:, None] * C)])
-        if not np.all(np.isfinite(A)):
-            break
         _, _, vh = np.linalg.svd(A, full_matrices=False)
         v = vh[-1].conj()
         a, b = v[:m], v[m:]
         e = errors(a, b)
-        if not np.all(np.isfinite(e)):
+        sc = scored(a, b, e)
+        if sc < best[0]:
+            best = (sc, a, b)
+        # such an iterate is not kept, but the iteration goes on: its rows with no finite
+        # error are reweighted as the worst finite row (the iteration pushes them down next)
+        fin = np.isfinite(e)
+        if not fin.any():
             break
-        if e.max() < best[0]:
-            best = (e.max(), a, b)
+        e = np.where(fin, e, e[fin].max())
         lam = lam * np.maximum(e, 1e-300)
         lam = lam / lam.sum()
     return best[1], best[2]
@@ -162,34 +175,62 @@ def eval_pf(z, poles, residues, r_inf):
     return r_inf + (1.0 / (z.ravel()[:, None] - poles[None, :])) @ residues
 
 
+def samples(zlo: float, zhi: float, nsamp: int, grade: int = 0) -> np.ndarray:
+    """nsamp uniform samples of [zlo, zhi]; with grade > 0 also -1 -+ 10^t for grade values of t
+    evenly spaced in [-10, 0] on each side of the branch point (those inside the interval)."""
+    Z = np.linspace(zlo, zhi, nsamp)
+    if grade > 0:
+        t = 10.0 ** np.linspace(-10.0, 0.0, grade)
+        Z = np.unique(np.concatenate([Z, -1.0 - t, -1.0 + t]))
+        Z = Z[(Z >= zlo) & (Z <= zhi)]
+    return Z
+
+
 def fit_exp_sqrt(K: float, N: int, zlo: float = -4.0, zhi: float = 2.0, nsamp: int = 4001,
-                 lawson_iters: int = 40) -> dict:
-    """(N,N) AAA-Lawson fit of exp(iK sqrt(1+z)) on uniform samples of [zlo, zhi].
+                 lawson_iters: int = 40, grade: int = 0) -> dict:
+    """(N,N) AAA-Lawson fit of exp(iK sqrt(1+z)) on uniform samples of [zlo, zhi]
+    (plus, with grade > 0, samples graded toward the branch point z = -1, see samples()).
+
+    Of the Lawson iterates (AAA's own weights included) the one whose partial
+    fractions have the smallest maximum error on the samples is kept.
 
     The default interval is the paper's Re z in [-4, 2] (Sec. 3).  The "average
     error" the paper quotes in Sec. 3.1 is read as the mean of |r - f| over the
     uniform samples; the report also gives the maximum on a 10^5-point grid,
     which sees the slow convergence at the branch point z = -1.
 
-    Returns a dict with poles, residues, r_inf and a fit report (mean and max
-    error on the samples, max error on a fine grid, min Im(-b_k)).
+    Returns a dict with poles, residues, r_inf and a fit report: mean and max
+    error on the uniform samples, max error and max |r| on a fine grid that
+    also approaches z = -1 to 1e-14, min Im(-b_k).
     """
-    Z = np.linspace(zlo, zhi, nsamp)
+    Z = samples(zlo, zhi, nsamp, grade)
     F = target(Z, K)
     zj, fj, w = aaa(Z.astype(complex), F, N + 1)
     alpha, beta = w * fj, w
+
+    def pf_max_err(a, b):
+        # what a plan consumes is the partial-fraction form: judge each iterate by it
+        with np.errstate(all="ignore"):
+            p, r, ri = poles_residues(zj, a, b)
+            return np.max(np.abs(eval_pf(Z, p, r, ri) - F)) if len(p) == N else np.inf
+
     if lawson_iters:
-        alpha, beta = lawson(Z, F, zj, alpha, beta, lawson_iters)
+        alpha, beta = lawson(Z, F, zj, alpha, beta, lawson_iters, score=pf_max_err)
     poles, residues, r_inf = poles_residues(zj, alpha, beta)
-    rs = eval_pf(Z, poles, residues, r_inf)
-    zf = np.linspace(zlo, zhi, 100001)
+    Zu = np.linspace(zlo, zhi, nsamp)
+    eu = np.abs(eval_pf(Zu, poles, residues, r_inf) - target(Zu, K))
+    # fine grid: 10^5 uniform points and points approaching the branch point from both sides
+    near = 10.0 ** np.linspace(-14.0, 0.0, 2001)
+    zf = np.unique(np.concatenate([np.linspace(zlo, zhi, 100001), -1.0 - near, -1.0 + near]))
+    zf = zf[(zf >= zlo) & (zf <= zhi)]
     rf = eval_pf(zf, poles, residues, r_inf)
     return {
         "K": K, "N": N, "zlo": zlo, "zhi": zhi,
         "poles": poles, "residues": residues, "r_inf": r_inf,
         "support": zj, "alpha": alpha, "beta": beta,
-        "mean_err": float(np.mean(np.abs(rs - F))),
-        "max_err": float(np.max(np.abs(rs - F))),
+        "mean_err": float(np.mean(eu)),
+        "max_err": float(np.max(eu)),
         "fine_max_err": float(np.max(np.abs(rf - target(zf, K)))),
+        "fine_max_abs_r": float(np.max(np.abs(rf))),
         "min_im_neg_pole": float(np.min(-poles.imag)),
     }

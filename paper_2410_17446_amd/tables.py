@@ -67,9 +67,17 @@ class RationalFit:
     """AAA followed by Lawson reweighting; barycentric numerator/denominator weights a, b."""
 
     def __init__(self, K: float, degree: int, lo: float = -4.0, hi: float = 2.0, samples: int = 4001,
-                 lawson_steps: int = 40):
+                 lawson_steps: int = 40, grade: int = 0):
+        """grade > 0 adds 2 grade samples at -1 -+ 10^s, s = -10..0 (evenly spaced), to the
+        uniform ones: the fit then sees the branch point z = -1 closely (smaller error and
+        overshoot |r| > 1 there) at the price of poles closer to the real axis."""
         self.K, self.degree = K, degree
-        self.Z = np.linspace(lo, hi, samples)
+        Z = np.linspace(lo, hi, samples)
+        if grade > 0:
+            off = np.logspace(-10.0, 0.0, grade)
+            Z = np.union1d(Z, np.concatenate([-1.0 - off, -1.0 + off]))
+            Z = Z[(Z >= lo) & (Z <= hi)]
+        self.Z = Z
         self.F = exp_sqrt(self.Z, K)
         self._aaa(degree + 1)
         if lawson_steps:
@@ -100,46 +108,67 @@ class RationalFit:
         off = np.ones(len(Z), dtype=bool)
         idx = [int(np.argmin(np.abs(Z - t))) for t in self.t]
         off[idx] = False
-        h = np.abs(self.Z[1] - self.Z[0])
-        # sample rows: Cauchy matrix; support rows: the residue of F d - n at t_j, over h
-        C = np.vstack([1.0 / np.subtract.outer(Z[off], self.t), np.eye(len(self.t)) / h])
+        # local sample spacing at each support point (the samples may be graded)
+        h = np.array([np.partition(np.abs(self.Z - t.real), 1)[1] for t in self.t])
+        # sample rows: Cauchy matrix; support rows: the residue of F d - n at t_j, over h_j
+        C = np.vstack([1.0 / np.subtract.outer(Z[off], self.t), np.diag(1.0 / h)])
         return C, np.concatenate([F[off], F[idx]])
 
     def _lawson(self, steps: int):
         C, F = self._rows()
         n = len(self.t)
-        worst = lambda a, b: np.max(np.abs(F - (C @ a) / (C @ b)))
-        best_err, best = worst(self.a, self.b), (self.a, self.b)
+
+        def err(a, b):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                e = np.abs(F - (C @ a) / (C @ b))
+            # NaN (0/0) and inf (d = 0 on a sample row) both mean "no finite value there"
+            return np.where(np.isnan(e), np.inf, e)
+
+        Zs = self.Z.astype(complex)
+
+        def pf_err(a, b):
+            # the iterate is judged by the form the plan receives: its partial fractions
+            with np.errstate(all="ignore"):
+                poles, res, rinf = self._pf_of(a, b)
+                if len(poles) != self.degree:
+                    return np.inf
+                v = np.max(np.abs(rinf + (1.0 / np.subtract.outer(Zs, poles)) @ res - self.F))
+            return v if np.isfinite(v) else np.inf
+
+        best_err, best = pf_err(self.a, self.b), (self.a, self.b)
         wts = np.full(len(F), 1.0 / len(F))
         for _ in range(steps):
             sq = np.sqrt(wts)[:, None]
             M = np.hstack([sq * (F[:, None] * C), -sq * C])      # unknowns (b, a)
-            if not np.isfinite(M).all():
-                break
             v = sla.svd(M, full_matrices=False)[2][-1].conj()
             b, a = v[:n], v[n:]
-            e = np.abs(F - (C @ a) / (C @ b))
-            if not np.isfinite(e).all():
+            e = err(a, b)
+            score = pf_err(a, b)
+            if score < best_err:
+                best_err, best = score, (a, b)
+            finite = e < np.inf
+            if not finite.any():
                 break
-            if e.max() < best_err:
-                best_err, best = e.max(), (a, b)
-            wts = wts * np.maximum(e, 1e-300)
+            # an unbounded row takes the largest finite error as its weight factor
+            wts = wts * np.maximum(np.minimum(e, e[finite].max()), 1e-300)
             wts /= wts.sum()
         self.a, self.b = best
 
-    def _partial_fractions(self):
+    def _pf_of(self, a, b):
+        """Poles, residues and value at infinity of the barycentric form with weights a, b."""
         n = len(self.t)
         E = np.zeros((n + 1, n + 1), dtype=complex)
-        E[0, 1:] = self.b
+        E[0, 1:] = b
         E[1:, 0] = 1.0
         E[1:, 1:] = np.diag(self.t)
         B = np.diag(np.concatenate([[0.0], np.ones(n)])).astype(complex)
         ev = sla.eigvals(E, B)
         poles = ev[np.isfinite(ev) & (np.abs(ev) < 1e12)]
         d = 1.0 / np.subtract.outer(poles, self.t)
-        self.poles = poles
-        self.residues = (d @ self.a) / (-(d ** 2) @ self.b)
-        self.r_inf = complex(self.a.sum() / self.b.sum())
+        return poles, (d @ a) / (-(d ** 2) @ b), complex(a.sum() / b.sum())
+
+    def _partial_fractions(self):
+        self.poles, self.residues, self.r_inf = self._pf_of(self.a, self.b)
 
     def __call__(self, z):
         z = np.asarray(z, dtype=complex)

@@ -81,6 +81,62 @@ def test_partial_fractions_equal_rational_function(N):
     assert np.all(f["poles"].imag < 0)
 
 
+def test_lawson_moves_the_fit_toward_minimax():
+    """Sec. 3.1: the Lawson stage of AAA-Lawson reweights toward minimax.  At (28,28), dz = 5
+    lambda, n0 = 1.0003 the paper's average error is 1.19e-8; the oracle's Lawson fit lands within
+    2x of it, while plain AAA (no Lawson step) is 4x off, and Lawson's maximum error on the
+    samples is well below plain AAA's."""
+    K = K2PI * PAPER["n0_air"] * 5.0
+    law = fit.fit_exp_sqrt(K, 28)
+    plain = fit.fit_exp_sqrt(K, 28, lawson_iters=0)
+    paper = PAPER["aaa_mean_error_28_dz5"]
+    assert paper / 2 < law["mean_err"] < 2 * paper
+    assert not paper / 2 < plain["mean_err"] < 2 * paper
+    assert law["max_err"] < 0.5 * plain["max_err"]
+
+
+def test_lawson_keeps_a_finite_iterate_past_a_nan():
+    """A Lawson iterate whose error is not finite (r with a pole on a sample row) must neither be
+    returned nor stop the comparison: starting from weights with beta_j = 0 at a support point
+    (its row divides by zero) the iteration still returns finite weights better than AAA's."""
+    K = K2PI
+    Z = np.linspace(-4, 2, 801)
+    F = fit.target(Z, K)
+    zj, fj, w = fit.aaa(Z.astype(complex), F, 9)
+    a0, b0 = w * fj, w.copy()
+    b0[3] = 0.0                                   # a support row with d = 0
+    a, b = fit.lawson(Z, F, zj, a0, b0, iters=10)
+    assert not np.array_equal(b, b0) and np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+    Zm = 0.5 * (Z[1:] + Z[:-1])                   # midpoints: off the support points
+    Fm = fit.target(Zm, K)
+    r = fit.eval_barycentric(Zm, zj, a, b)
+    assert np.all(np.isfinite(r))
+    assert np.max(np.abs(r - Fm)) < 1e-1
+    # the same through a score that is NaN on the start: the start is never kept
+    calls = []
+    def score(aa, bb):
+        calls.append(1)
+        return np.nan if len(calls) == 1 else np.max(np.abs(fit.eval_barycentric(Zm, zj, aa, bb) - Fm))
+    a, b = fit.lawson(Z, F, zj, w * fj, w, iters=5, score=score)
+    assert not np.array_equal(b, w) and len(calls) == 6
+
+
+def test_graded_samples_trade_branch_point_error_for_pole_distance():
+    """Root-exponential convergence at the branch point z = -1: with uniform samples the fit's
+    error between the samples next to z = -1 is orders above its error on them, and |r| exceeds 1
+    there.  Samples graded toward z = -1 cut that error and overshoot by over 10x at 16 poles, but
+    the best rational approximant then places poles much closer to the real axis (nearly singular
+    shifted systems), so neither sampling gives |r| <= 1 + 1e-6 at the workloads' degrees."""
+    uni = fit.fit_exp_sqrt(K2PI, 16)
+    gra = fit.fit_exp_sqrt(K2PI, 16, grade=300)
+    assert uni["fine_max_err"] > 1e3 * uni["max_err"]
+    assert gra["fine_max_err"] < uni["fine_max_err"] / 10
+    assert gra["fine_max_abs_r"] - 1 < (uni["fine_max_abs_r"] - 1) / 10
+    assert gra["fine_max_abs_r"] > 1 + 1e-6
+    assert gra["min_im_neg_pole"] < uni["min_im_neg_pole"] / 100
+    assert np.all(gra["poles"].imag < 0)
+
+
 def test_fit_converges_with_degree():
     errs = [fit.fit_exp_sqrt(K2PI, N)["max_err"] for N in (8, 12, 16, 24)]
     assert all(b < a for a, b in zip(errs, errs[1:]))
@@ -413,6 +469,60 @@ def test_layer_loss_profile():
     assert np.isclose(m[1, 16], np.exp(-K2PI * 0.25 / 2))
     assert np.isclose(m[16, 8], np.exp(-K2PI * 0.25 * (1 / 8) ** 2 / 2))
     assert m[16, 9] == 1.0
+
+
+def test_layer_loss_is_the_lossy_medium_step_factor():
+    """Sec. 2 eq. expop_prop for a homogeneous medium n^2 = n0^2 + i eta at normal incidence
+    (zeta = i eta / n0^2, no transverse variation): one step multiplies the field by
+    exp(iK(-1 + sqrt(1 + i eta/n0^2))), K = k0 n0 dz, whose modulus the layer's loss factor must
+    equal to first order in eta.  n0 != 1 and dz != 1 so that a dropped n0 or dz shows."""
+    N, W, n0, dz, k0 = 40, 9, 1.3, 0.7, K2PI
+    c, d = stencil.stencils()
+    for eta_max, rtol in ((1e-4, 1e-8), (1e-2, 1e-4)):
+        g = op.Grid(N=N, dx=0.25, dy=0.25, k0=k0, n0=n0, c=c, d=d, W=W, eta_max=eta_max)
+        m = op.absorber_mask(g, dz)
+        i = np.arange(N)
+        dist = np.minimum(np.minimum(i, N - i)[:, None], np.minimum(i, N - i)[None, :])
+        layer = (dist >= 1) & (dist <= W)
+        # the layer's profile falls from eta_max next to the Dirichlet nodes to 0 past d = W
+        eta = np.where(layer, eta_max * ((W + 1 - dist) / W) ** 2, 0.0)
+        exact = np.abs(np.exp(1j * k0 * n0 * dz * (-1 + np.sqrt(1 + 1j * eta / n0 ** 2))))
+        inner = dist >= 1
+        assert np.allclose(np.log(m[inner]), np.log(exact[inner]), rtol=rtol, atol=0)
+        assert np.all(m[dist > W] == 1.0) and np.all(m[dist == 0] == 0.0)
+        # strongest loss next to the Dirichlet nodes, monotone toward the interior
+        row = m[N // 2, 1:W + 2]
+        assert np.all(np.diff(row) > 0) and row[-1] == 1.0
+
+
+def test_step_with_edge_layer_does_not_amplify():
+    """The AAA fit's overshoot |e^{-iK} r| > 1 sits next to the branch point (grazing waves), whose
+    free-space modes reach into the lossy edge layer.  Power iteration of the whole homogeneous
+    step, w -> m * S[e^{-iK} r(mu_p + mu_q) (S w S)]S (m the layer's loss factor), at 256^2 with 16
+    poles shows a largest growth per step below 1, although max |e^{-iK} r| on the free-space
+    spectrum is about 1.019."""
+    import scipy.fft as sfft
+    N, W = 256, 32
+    c, d = stencil.stencils()
+    g = op.Grid(N=N, dx=0.25, dy=0.25, k0=K2PI, n0=1.0, c=c, d=d, W=W, eta_max=0.25)
+    f = fit.fit_exp_sqrt(K2PI, 16)
+    q = np.arange(1, N)
+    kap = -(c[0] + 2 * sum(c[j] * np.cos(j * np.pi * q / N) for j in range(1, 7)))
+    mu = -kap / (g.k0 * g.n0 * g.dx) ** 2
+    lam = mu[:, None] + mu[None, :]
+    rl = (np.exp(-1j * K2PI) * fit.eval_pf(lam, f["poles"], f["residues"], f["r_inf"])).reshape(lam.shape)
+    assert np.abs(rl).max() > 1.01
+    m = op.absorber_mask(g, 1.0)[1:, 1:]
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((N - 1, N - 1)) + 1j * rng.standard_normal((N - 1, N - 1))
+    growth = []
+    for _ in range(300):
+        s = sfft.dstn(w, type=1, norm="ortho", workers=-1)
+        w = m * sfft.idstn(s * rl, type=1, norm="ortho", workers=-1)
+        n = np.linalg.norm(w)
+        w /= n
+        growth.append(n)
+    assert max(growth[-50:]) < 1.0
 
 
 def test_step_guesses_fallback_and_exact():

@@ -45,6 +45,36 @@ def test_rational_fit_accuracy_matches_oracle(N):
     assert len(lib.poles) == N and np.all(lib.poles.imag < 0)
 
 
+def test_rational_fit_at_the_beam_step_matches_oracle():
+    """The 25-term fit at dz = lambda/20, n0 = 1.0003 (the beam runs of Sec. 5.2): both fits sit
+    near 1e-11..1e-10 on the samples, where the conversion from barycentric weights to poles and
+    residues (residues of size ~30, so cancellation) decides the last digit, and the library's
+    Lawson stage never ends worse than its own AAA start (a non-finite Lawson iterate no longer
+    stops the iteration at the AAA weights)."""
+    K = 2 * np.pi * 1.0003 * 0.05
+    z = np.linspace(-4, 2, 4001)
+    lib = tables.RationalFit(K, 25)
+    start = tables.RationalFit(K, 25, lawson_steps=0)
+    ora = fit.fit_exp_sqrt(K, 25)
+    e_lib = np.abs(lib(z) - fit.target(z, K)).max()
+    e_start = np.abs(start(z) - fit.target(z, K)).max()
+    assert e_lib <= e_start
+    assert e_lib < 3e-10 and ora["max_err"] < 3e-10
+    assert e_lib < 15 * ora["max_err"]
+    assert len(lib.poles) == 25 and np.all(lib.poles.imag < 0)
+
+
+def test_graded_rational_fit_matches_oracle():
+    """With samples graded toward z = -1 both fits reach the same branch-point accuracy."""
+    K = 2 * np.pi
+    lib = tables.RationalFit(K, 16, grade=300)
+    ora = fit.fit_exp_sqrt(K, 16, grade=300)
+    near = 10.0 ** np.linspace(-14, 0, 2001)
+    z = np.concatenate([np.linspace(-4, 2, 100001), -1 - near, -1 + near])
+    e_lib = np.abs(lib(z) - fit.target(z, K)).max()
+    assert e_lib < 3 * ora["fine_max_err"] and ora["fine_max_err"] < 1e-3
+
+
 def test_stencils_match_oracle_symbols():
     """Both stencil designs solve the same minimax problem: their symbols agree."""
     c_o, d_o = stencil.stencils()
