@@ -124,11 +124,20 @@ int hp_set_medium(hp_plan plan, const double* n2);
 
 /* One step (Sec. 2 eq. approx_prop).  E_in, E_out: device [ncomp][ny][nx]
  * complex128; E_out may equal E_in.  n2: device [ny][nx] or NULL to keep the
- * medium of the last call. */
+ * medium of the last call.  Returns HP_WARN_NOCONV (output written, each solve
+ * at its best iterate) when some solve missed tol within max_cycles cycles, and
+ * HP_EINVAL (output undefined) when a NaN or Inf reached a solve: a non-finite
+ * E_in or n2, or n2 <= 0 where the vector operator takes ln n2. */
 int hp_step(hp_plan plan, const void* E_in, const double* n2, void* E_out);
 
-/* nsteps steps.  n2 may be NULL (keep), or n2 + s * n2_step_stride is the
- * medium of step s (stride 0: one z-independent medium). */
+/* The propagation loop of Sec. 2 (after eq. expop_prop: the field is advanced
+ * step by step in z, n and psi refreshed for every new step): nsteps calls of
+ * hp_step, E_in -> E_out, each step's output the next step's input.  n2 may be
+ * NULL (keep the plan's medium), or n2 + s * n2_step_stride is the medium of
+ * step s (stride 0: one z-independent medium); n2 is device memory of
+ * nsteps planes when the stride is not 0.  E_out may equal E_in; nsteps = 0
+ * copies E_in to E_out.  Returns the most severe step status (a negative one
+ * stops the loop, E_out then undefined). */
 int hp_propagate(hp_plan plan, const void* E_in, const double* n2, long n2_step_stride,
                  int nsteps, void* E_out);
 
@@ -263,6 +272,13 @@ int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
  * A period above 1 takes the event pairs out of most launches, so the step
  * keeps its untimed rate while the timed launches sample the class. */
 int hp_profile_sample(hp_plan plan, int period);
+/* Per kernel class: launches and algorithmic bytes of EVERY launch of every
+ * class since the last hp_profile call that enabled profiling, timed or not
+ * (untimed classes and, with a sampling period above 1, untimed launches
+ * included), so that the bytes of a run can be paired with a profiler's
+ * per-dispatch counters over the same launches.  Host-side counts, no
+ * synchronisation. */
+int hp_profile_totals(hp_plan plan, long* launches, double* bytes);
 
 const char* hp_last_error(hp_plan plan);
 void hp_plan_destroy(hp_plan plan);

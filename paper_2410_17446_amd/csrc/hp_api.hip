@@ -101,6 +101,8 @@ struct hp_plan_s {
   std::vector<double> ev_bytes;
   long prof_n[HP_K_COUNT]{};
   double prof_ms[HP_K_COUNT]{}, prof_b[HP_K_COUNT]{};
+  long prof_nall[HP_K_COUNT]{};     // every launch of an enabled class, timed or not
+  double prof_ball[HP_K_COUNT]{};   // ... and its algorithmic bytes
   std::vector<int> m_h;  // Arnoldi columns per pole (host mirror)
   std::vector<double> incons;  // eps kappa(M_k) per pole
   c128 phase{}, rinf_phase{};  // e^{-iK}, e^{-iK} r_inf
@@ -110,6 +112,7 @@ struct hp_plan_s {
   c128* rk = nullptr;          // stage result, stage input, running sum (allocated by hp_set_form)
   std::string err;
 };
+
 
 namespace {
 
@@ -132,12 +135,22 @@ int hip_fail(hp_plan p, hipError_t e, const char* where) {
   } while (0)
 
 // Bracket a launch with events when timing is on.
+// bytes < 0: the launch's bytes are not known yet (a round's kernels skip the
+// poles that turn out to have finished in the round before); *slot receives the
+// timed launch's index (-1 if untimed) and prof_settle() adds the bytes later.
 struct Prof {
   hp_plan p;
   int cls;
   double bytes;
   bool on;
-  Prof(hp_plan p_, int c, double b) : p(p_), cls(c), bytes(b), on(((p_->prof >> c) & 1) != 0) {
+  long* slot;
+  Prof(hp_plan p_, int c, double b, long* slot_ = nullptr)
+      : p(p_), cls(c), bytes(b), on(((p_->prof >> c) & 1) != 0), slot(slot_) {
+    if (slot) *slot = -1;
+    if (p->prof) {  // while profiling, every class's launches and bytes are counted
+      p->prof_nall[c] += 1;
+      if (b >= 0) p->prof_ball[c] += b;
+    }
     if (!on) return;
     on = (p->prof_seen[c]++ % p->prof_every) == 0;
     if (!on) return;
@@ -155,9 +168,17 @@ struct Prof {
     (void)hipEventRecord(p->ev_pool[p->ev_used + 1], p->stream);
     p->ev_used += 2;
     p->ev_cls.push_back(cls);
-    p->ev_bytes.push_back(bytes);
+    if (slot) *slot = (long)p->ev_bytes.size();
+    p->ev_bytes.push_back(bytes >= 0 ? bytes : 0.0);
   }
 };
+
+// The bytes of a launch made with deferred bytes (Prof with b < 0).
+void prof_settle(hp_plan p, int cls, long slot, double bytes) {
+  if (!p->prof) return;
+  p->prof_ball[cls] += bytes;
+  if (slot >= 0 && slot < (long)p->ev_bytes.size()) p->ev_bytes[slot] = bytes;
+}
 
 // grid sizes with a compiled transform: 2^k (64..2048) and 3 * 2^k (192..1536)
 bool fft_size(int n) {
@@ -557,6 +578,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   p->relres.assign(K, -1.0);
   double beta0 = -1.0;
   bool noconv = false;
+  int nonfinite = -1;  // a pole whose Krylov space met a NaN or Inf
   const size_t zsp = (size_t)M * fn, zsi = fn, psp = fn, dzsp = (d.ncomp == 2) ? fn : 0;
   cx<T>* Zb = reinterpret_cast<cx<T>*>(p->Z);
   cx<T>* Pb = reinterpret_cast<cx<T>*>(p->P);
@@ -567,6 +589,35 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     int slot;
     long iter;
     unsigned long long seq;  // tag of the round's flags
+    std::vector<int> ms;     // per pole: its Arnoldi index in the round
+    std::vector<char> sh;    // per pole: its first basis vector is the shared S_x w
+    long pslot[3];           // timed-launch slots of the column pass, row pass and update
+  };
+  // Algorithmic bytes of a round's column pass, row pass and update over the
+  // poles that did the step (the others skipped themselves on the device), each
+  // distinct field counted once per launch: poles in the first cycle of the step
+  // share one first basis vector (S_x w), which a launch must read once.
+  auto settle = [&](const Flight& f, const std::vector<char>& worked) {
+    if (!p->prof) return;
+    double col = 0.0, row = 0.0, upd = 0.0;
+    int shared = 0, shared_m0 = 0, nw = 0;
+    const double outs = d.ncomp == 2 ? 2.0 : 1.0;  // z (and D1y z)
+    for (size_t a = 0; a < f.poles.size(); ++a) {
+      if (!worked[a]) continue;
+      const int mm = f.ms[a];
+      ++nw;
+      col += 1.0 + outs;                                         // u_m read, z (+ D1y z) written
+      row += (d.ncomp == 2 ? 3.0 : 2.0) + (mm + 1.0);           // z (+ D1y z), p, u_0..u_m
+      upd += 1.0 + (mm + 1.0) + 1.0 + (mm > 0 ? 1.0 : 0.0);     // p, u_0..u_m, u_{m+1}, rewritten u_m
+      if (f.sh[a]) {
+        ++shared;
+        if (mm == 0) ++shared_m0;
+      }
+    }
+    const double dup = shared > 0 ? shared - 1.0 : 0.0, dup0 = shared_m0 > 0 ? shared_m0 - 1.0 : 0.0;
+    prof_settle(p, HP_K_COL, f.pslot[0], U1 * es * (col - dup0));
+    prof_settle(p, HP_K_ROW_APPLY, f.pslot[1], nw ? U1 * es * (row - dup) + (U1 / d.ncomp) * 8.0 * planes : 0.0);
+    prof_settle(p, HP_K_UPDATE, f.pslot[2], U1 * es * (upd - dup));
   };
   // initial guesses (explicit, or the previous step's solutions held in X)
   p->accepted.assign(K, 0);
@@ -604,23 +655,22 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     const int na = (int)poles.size();
     int* ad = p->active_d + slot * HP_MAXPOLES;
     int maxm = 0;
-    double sum_m = 0.0;
+    Flight fl{poles, slot, next_iter, 0, std::vector<int>(na), std::vector<char>(na), {-1, -1, -1}};
     for (int a = 0; a < na; ++a) {
       const int mk_ = (int)std::min<long>(next_iter - since[poles[a]], M - 1);
       maxm = std::max(maxm, mk_);
-      sum_m += mk_;
+      fl.ms[a] = mk_;
+      fl.sh[a] = p->uptr_h[(size_t)poles[a] * (HP_MAXM + 1)] == (void*)bR;
     }
     {
       // the column pass takes the list in its arguments and stores it to ad
       // for the kernels after it (no host-to-device copy per round)
-      const double outs = (d.ncomp == 2 ? 2.0 : 1.0) * na;  // z (and D1y z) per pole
-      Prof pr(p, HP_K_COL, U1 * es * (na + outs));
+      Prof pr(p, HP_K_COL, -1.0, &fl.pslot[0]);
       launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, poles.data(), na, ad, p->mu_x, p->mu_y, twy, p->geo,
                        p->sc, p->stream);
     }
     {
-      const double per_pole = (d.ncomp == 2 ? 3.0 : 2.0) * na + (sum_m + na);  // z (+dz), p, u_0..u_m
-      Prof pr(p, HP_K_ROW_APPLY, U1 * es * per_pole + (U1 / d.ncomp) * 8.0 * planes);
+      Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
       launch_row_apply<T, C>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<C>(p), p->st, ad, na, p->part_dots, twx,
                              p->geo,
                           p->sc, p->stream);
@@ -630,7 +680,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->reduce_done, p->stream);
     }
     {
-      Prof pr(p, HP_K_UPDATE, U1 * es * (sum_m + 3.0 * na));
+      Prof pr(p, HP_K_UPDATE, -1.0, &fl.pslot[2]);
       launch_update<T>(Pb, psp, reinterpret_cast<cx<T>* const*>(p->uptr), p->st, ad, na, p->part_norm, p->nupdblk,
                        p->geo, p->stream);
     }
@@ -640,7 +690,8 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       launch_arnoldi(p->st, ad, na, p->part_norm, p->nupdblk, M, p->ftag_hd + slot * HP_MAXPOLES, ++p->seq,
                      p->est_d, p->stream);
     }
-    q.push_back(Flight{poles, slot, next_iter, p->seq});
+    fl.seq = p->seq;
+    q.push_back(std::move(fl));
     ++next_iter;
     return HP_OK;
   };
@@ -685,6 +736,12 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
         }
       }
     }
+    {
+      // the poles that did this round's step: live then and in their current cycle
+      std::vector<char> worked(f.poles.size());
+      for (size_t a = 0; a < f.poles.size(); ++a) worked[a] = live[f.poles[a]] && f.iter >= since[f.poles[a]];
+      settle(f, worked);
+    }
     std::vector<int> chk;  // poles whose cycle ended and whose true residual decides
     for (int k : f.poles) {
       if (!live[k] || f.iter < since[k]) continue;
@@ -692,6 +749,10 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       if (flag == 0) continue;
       live[k] = 0;
       done_m[k] = (int)(f.iter - since[k] + 1);
+      if (flag == 4) {  // the pole stopped itself; the other poles drain normally
+        if (nonfinite < 0) nonfinite = k;
+        continue;
+      }
       const bool fixed = !p->fixed.empty() && p->fixed[k] > 0;
       if (fixed || (flag == 1 && !p->mixed)) {  // converged on the FP64 estimate
         p->relres[k] = -1.0;
@@ -730,6 +791,10 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   p->m_h = done_m;
   *noconv_out = noconv;
   HPCHK(hipGetLastError());
+  if (nonfinite >= 0)
+    return fail(p, HP_EINVAL, "pole " + std::to_string(nonfinite) +
+                                  ": a NaN or Inf reached the GMRES solve (non-finite n2 or E_in, or n2 <= 0 "
+                                  "for the vector operator)");
   return HP_OK;
 }
 
@@ -1245,6 +1310,17 @@ int hp_profile(hp_plan p, int enable) {
     p->prof_ms[c] = 0.0;
     p->prof_b[c] = 0.0;
     p->prof_seen[c] = 0;
+    p->prof_nall[c] = 0;
+    p->prof_ball[c] = 0.0;
+  }
+  return HP_OK;
+}
+
+int hp_profile_totals(hp_plan p, long* launches, double* bytes) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  for (int c = 0; c < HP_K_COUNT; ++c) {
+    if (launches) launches[c] = p->prof_nall[c];
+    if (bytes) bytes[c] = p->prof_ball[c];
   }
   return HP_OK;
 }
@@ -1476,3 +1552,4 @@ void hp_batch_destroy(hp_batch b) {
 }
 
 }  // extern "C"
+

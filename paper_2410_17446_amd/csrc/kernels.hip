@@ -891,7 +891,9 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
     S.m = m + 1;
     S.total = total + 1;
     int flag = 0;
-    if (fixed > 0) {
+    if (!isfinite(h) || !isfinite(est)) {
+      flag = 4;  // a NaN or Inf reached the Krylov space (n^2 or the right-hand side): stop the pole
+    } else if (fixed > 0) {
       if (m + 1 >= fixed) flag = 1;
     } else if (est <= tol || h == 0.0) {
       flag = 1;
@@ -914,7 +916,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
     S.sn[m] = sn[m];
   }
   int flag = flag_s;
-  if (flag) {
+  if (flag && flag != 4) {
     // least squares R y = g, then y~ = Rc^{-1} y (the coefficients of the stored Z~);
     // both triangles go through LDS, packed (one parallel load each)
     __shared__ c128 tri[HP_MAXM * (HP_MAXM + 1) / 2];

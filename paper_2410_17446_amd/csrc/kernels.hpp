@@ -88,8 +88,9 @@ int update_blocks(size_t total);
 // Hessenberg column, Givens rotation, residual estimate, convergence flag and
 // the least-squares solution at the end of a cycle.
 // ftag[k] = (seq << 8) | flag for every pole that takes the step (flag 0: going
-// on, 1: converged, 2: restart length reached, 3: the true residual decides),
-// stored with system scope to host-coherent memory.
+// on, 1: converged, 2: restart length reached, 3: the true residual decides,
+// 4: a non-finite value reached the Krylov space), stored with system scope to
+// host-coherent memory.
 void launch_arnoldi(PoleState* st, const int* active, int nactive, const double* part, int nblk, int restart,
                     unsigned long long* ftag, unsigned long long seq, double* est, hipStream_t s);
 

@@ -17,7 +17,8 @@
 struct PoleState {
   int m;          // Arnoldi columns completed in the current cycle
   int flag;       // 0 running, 1 converged / fixed count reached, 2 cycle ended unconverged,
-                  // 3 converged on the estimate but the true residual must decide
+                  // 3 converged on the estimate but the true residual must decide,
+                  // 4 stopped: a non-finite value (NaN/Inf in n^2 or the right-hand side)
   int total;      // Arnoldi steps over all cycles
   int fixed;      // > 0: force exactly this many steps in one cycle
   int has_x;      // 1 once an earlier cycle's solution sits in the X accumulator

@@ -24,7 +24,8 @@ HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
            "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
-           "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_last_error", "hp_plan_destroy",
+           "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_profile_totals", "hp_last_error",
+           "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
 KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
 
@@ -75,6 +76,7 @@ def lib():
         L.hp_profile.argtypes = [vp, C.c_int]
         L.hp_profile_read.argtypes = [vp, C.POINTER(C.c_long), dp, dp]
         L.hp_profile_sample.argtypes = [vp, C.c_int]
+        L.hp_profile_totals.argtypes = [vp, C.POINTER(C.c_long), dp]
         L.hp_last_error.argtypes = [vp]
         L.hp_last_error.restype = C.c_char_p
         L.hp_plan_destroy.argtypes = [vp]
@@ -143,7 +145,7 @@ class Plan:
         import torch
         if E_out is None:
             E_out = torch.empty_like(E_in)
-        self._check(self.L.hp_step(self.handle, _ptr(E_in), _ptr(n2), _ptr(E_out)), "hp_step")
+        self.last_status = self._check(self.L.hp_step(self.handle, _ptr(E_in), _ptr(n2), _ptr(E_out)), "hp_step")
         return E_out
 
     def propagate(self, E_in, nsteps, n2=None, n2_step_stride=0, E_out=None):
@@ -151,14 +153,14 @@ class Plan:
         if E_out is None:
             E_out = torch.empty_like(E_in)
         rc = self.L.hp_propagate(self.handle, _ptr(E_in), _ptr(n2), n2_step_stride, nsteps, _ptr(E_out))
-        self._check(rc, "hp_propagate")
+        self.last_status = self._check(rc, "hp_propagate")
         return E_out
 
     def solve(self, pole, rhs, x=None):
         import torch
         if x is None:
             x = torch.empty_like(rhs)
-        self._check(self.L.hp_solve(self.handle, pole, _ptr(rhs), _ptr(x)), "hp_solve")
+        self.last_status = self._check(self.L.hp_solve(self.handle, pole, _ptr(rhs), _ptr(x)), "hp_solve")
         return x
 
     def step_guess(self, E_in, x0, n2=None, E_out=None):
@@ -244,6 +246,14 @@ class Plan:
         la, ms, by = (C.c_long * n)(), (C.c_double * n)(), (C.c_double * n)()
         self._check(self.L.hp_profile_read(self.handle, la, ms, by), "hp_profile_read")
         return {k: (la[i], ms[i], by[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def profile_totals(self):
+        """{kernel class: (launches, algorithmic bytes)} over every launch of the enabled classes
+        since profile(True), timed or not."""
+        n = len(KERNEL_CLASSES)
+        la, by = (C.c_long * n)(), (C.c_double * n)()
+        self._check(self.L.hp_profile_totals(self.handle, la, by), "hp_profile_totals")
+        return {k: (la[i], by[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
     def workspace_bytes(self):
         return self.L.hp_workspace_bytes(C.byref(self.desc))

@@ -103,5 +103,32 @@ def test_null_arguments():
     assert L.hp_profile(None, 0) == -1
     assert L.hp_profile_sample(None, 1) == -1
     assert L.hp_profile_read(None, None, None, None) == -1
+    assert L.hp_profile_totals(None, None, None) == -1
     assert b"NULL" in L.hp_last_error(None)
     L.hp_plan_destroy(None)
+
+
+def test_pole_on_the_free_space_spectrum_is_rejected_on_the_host():
+    """A pole equal to an eigenvalue mu_p + mu_q of the free-space operator makes the preconditioner
+    singular; hp_plan_create rejects it with HP_EINVAL before allocating anything.  The eigenvalue
+    is formed as the library documents it: mu_q = s [c0 + 2 sum_m c_m cos(m pi q / n)] / h^2,
+    s = 1/(k0 n0)^2, summed in that order."""
+    import math
+    L = hp.lib()
+    d0 = _desc()
+    c = [d0.d2[i] for i in range(7)]
+    n, h, s = 64, 0.25, 1.0 / (2 * np.pi) ** 2
+
+    def mu(q):
+        sym = c[0]
+        for m in range(1, 7):
+            sym += 2.0 * c[m] * math.cos(m * math.pi * q / n)
+        return s * sym / (h * h)
+
+    lam = mu(3) + mu(5)
+    poles = (hp.hp_c128 * 2)(hp.hp_c128(-1.0, -0.1), hp.hp_c128(lam, 0.0))
+    d = _desc(poles=poles)
+    d._keep = d._keep + (poles,)
+    out = C.c_void_p()
+    assert L.hp_plan_create(C.byref(d), None, None, C.byref(out)) == -1 and not out.value
+    assert b"spectrum" in L.hp_last_error(None)
