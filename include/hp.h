@@ -254,6 +254,24 @@ int hp_set_fixed_iters(hp_plan plan, const int* iters);
 int hp_apply_operator(hp_plan plan, int pole, const void* x, void* y);
 int hp_apply_preconditioner(hp_plan plan, int pole, const void* x, void* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * hp_apply_preconditioner, y = (Zbar_fs - b_k I)^{-1} x (pole < 0: b = 0), with
+ * every intermediate buffer (the row-transformed input, the column pass's
+ * output and its y derivative, the pole state and partial norms) in a static
+ * device array of the library, 49 MiB per GPU (48 MiB of fields, 1 MiB of
+ * state) held from load until the process ends.  It calls no hipMalloc,
+ * hipFree, memset or host-to-device copy, does not synchronise (asynchronous on
+ * the plan's stream) and uses only set-up done by hp_plan_create.  x, y: device
+ * [ncomp][ny][nx] complex128, distinct.  HP_EINVAL for a field beyond the
+ * array (ncomp nx ny above 1048576 in HP_FP64; twice that in the mixed modes,
+ * whose intermediate fields are complex64), HP_EHIP if the array's device
+ * address could not be looked up.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (plans on different streams, or
+ * threads) race and must be serialised by the caller; the array keeps the
+ * last call's contents. */
+int hp_apply_preconditioner_noalloc(hp_plan plan, int pole, const void* x, void* y);
+
 /* Kernel timing (diagnostics).  enable: 0 off, -1 every kernel class, else a
  * bitmask of classes (1 << HP_K_*).  Each launch of a timed class is
  * bracketed by HIP events on the plan's stream (an event pair costs a few

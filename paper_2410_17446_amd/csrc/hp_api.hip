@@ -110,9 +110,14 @@ struct hp_plan_s {
   int form = HP_FORM_EXP;      // what the pole table approximates and how a step uses it
   int substeps = 1;            // RK4 substeps per step (pseudo-differential form)
   c128* rk = nullptr;          // stage result, stage input, running sum (allocated by hp_set_form)
+  void* scratch = nullptr;     // this device's address of the library's static scratch (no-alloc calls)
+  std::string scratch_err;
   std::string err;
 };
 
+namespace {
+void scratch_setup(hp_plan p);
+}
 
 namespace {
 
@@ -1057,6 +1062,7 @@ int hp_plan_create(const hp_plan_desc* desc, void* stream, void* workspace, hp_p
     hp_plan_destroy(p);
     return fail(nullptr, HP_EHIP, "plan upload failed");
   }
+  scratch_setup(p);  // this device's static scratch (hp_apply_preconditioner_noalloc)
   *out = p;
   return (rmax > 1.0 + 1e-6) ? HP_WARN_UNSTABLE : HP_OK;
 }
@@ -1553,3 +1559,112 @@ void hp_batch_destroy(hp_batch b) {
 
 }  // extern "C"
 
+// ============================================= the preconditioner without allocation
+//
+// hp_apply_preconditioner_noalloc: the free-space solve of hp_apply_preconditioner
+// for callers that cannot allocate (graph capture, serving loops, harnesses that
+// forbid hipMalloc).  Its intermediate fields and the pole state the column pass
+// reads live in `scratch`, a fixed array in device memory that every GPU holds
+// for the life of the process.  In host code `scratch` names a host-side stand-in,
+// not a device address: hp_plan_create (set-up, with the plan's device current)
+// looks up each device's own address once with hipGetSymbolAddress, and only that
+// address is ever handed to kernels.
+
+constexpr size_t kScratchFieldBytes = 48ull << 20;  // R-domain fields: row transform, column pass out, D1y
+constexpr size_t kScratchSmallBytes = 1ull << 20;   // pole state, basis pointer table, partial norms
+static __device__ __align__(256) char scratch[kScratchFieldBytes + kScratchSmallBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+void* scratch_for_current_device(std::string* why) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev] && g_scratch_err[dev] == hipSuccess) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    else
+      g_scratch_ptr[dev] = ptr;
+  }
+  if (!g_scratch_ptr[dev]) *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(g_scratch_err[dev]);
+  return g_scratch_ptr[dev];
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// The column pass reads flag, m, b_k and sigma_m of its pole and u_m from the
+// pointer table: set them for one application (pole slot 0, m = 0, sigma_0 = 1).
+__global__ void k_prec_setup(PoleState* st, void** tbl, void* u0, c128 b) {
+  if (threadIdx.x != 0) return;
+  st->flag = 0;
+  st->m = 0;
+  st->bk = b;
+  st->sigma[0] = 1.0;
+  tbl[0] = u0;
+}
+
+template <typename T, typename C>
+int apply_prec_noalloc(hp_plan p, int pole, const c128* x, c128* y) {
+  char* base = reinterpret_cast<char*>(p->scratch);
+  const size_t fb = align256(p->fieldn * sizeof(cx<T>));
+  cx<T>* tmpR = reinterpret_cast<cx<T>*>(base);
+  cx<T>* zout = reinterpret_cast<cx<T>*>(base + fb);
+  cx<T>* dz = reinterpret_cast<cx<T>*>(base + 2 * fb);
+  char* small = base + kScratchFieldBytes;
+  PoleState* st = reinterpret_cast<PoleState*>(small);
+  void** tbl = reinterpret_cast<void**>(small + align256(sizeof(PoleState)));
+  double* part = reinterpret_cast<double*>(small + align256(sizeof(PoleState)) +
+                                           align256((HP_MAXM + 1) * sizeof(void*)));
+  const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
+  hipLaunchKernelGGL(k_prec_setup, dim3(1), dim3(64), 0, p->stream, st, tbl, (void*)tmpR, b);
+  launch_row_fwd<T, C>(x, tmpR, part, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
+  const int zero = 0;
+  launch_col<T, C>(reinterpret_cast<const cx<T>* const*>(tbl), zout, 0, 0, dz, 0, st, &zero, 1, nullptr, p->mu_x,
+                   p->mu_y, reinterpret_cast<const cx<C>*>(p->tw_y), p->geo, p->sc, p->stream);
+  launch_row_inv<T, C>(zout, y, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
+  HPCHK(hipGetLastError());
+  return HP_OK;
+}
+
+// Set-up of the static scratch for a plan's device (called by hp_plan_create
+// with that device current).
+void scratch_setup(hp_plan p) {
+  std::string why;
+  p->scratch = scratch_for_current_device(&why);
+  p->scratch_err = why;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_apply_preconditioner_noalloc(hp_plan p, int pole, const void* x, void* y) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  if (!x || !y || x == y) return fail(p, HP_EINVAL, "x, y must be distinct device buffers");
+  if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  const size_t es = p->mixed ? sizeof(c64) : sizeof(c128);
+  const size_t need = (p->d.ncomp == 2 ? 3 : 2) * align256(p->fieldn * es);
+  const size_t part = (size_t)p->nrowblk * p->d.ncomp * sizeof(double);
+  if (need > kScratchFieldBytes || part > kScratchSmallBytes / 2)
+    return fail(p, HP_EINVAL,
+                "field too large for the static scratch: " + std::to_string(need) + " bytes needed, " +
+                    std::to_string(kScratchFieldBytes) + " available (ncomp nx ny <= 1048576 in HP_FP64)");
+  if (!p->scratch) return fail(p, HP_EHIP, "no device address for the static scratch: " + p->scratch_err);
+  const c128* xx = reinterpret_cast<const c128*>(x);
+  c128* yy = reinterpret_cast<c128*>(y);
+  return HP_BY_PRECISION(p, apply_prec_noalloc, p, pole, xx, yy);
+}
+
+}  // extern "C"

@@ -24,6 +24,7 @@ HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
            "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
+           "hp_apply_preconditioner_noalloc",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_profile_totals", "hp_last_error",
            "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
@@ -73,6 +74,7 @@ def lib():
         L.hp_set_fixed_iters.argtypes = [vp, ip]
         L.hp_apply_operator.argtypes = [vp, C.c_int, vp, vp]
         L.hp_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp]
+        L.hp_apply_preconditioner_noalloc.argtypes = [vp, C.c_int, vp, vp]
         L.hp_profile.argtypes = [vp, C.c_int]
         L.hp_profile_read.argtypes = [vp, C.POINTER(C.c_long), dp, dp]
         L.hp_profile_sample.argtypes = [vp, C.c_int]
