@@ -139,6 +139,32 @@ def run_batch(args):
     it, sec = b.stats()
     total_steps = args.steps * len(problems)
     finite = all(bool(torch.isfinite(torch.view_as_real(o)).all()) for o in outs)
+    b.close()
+    # what the concurrency buys: the same problems and steps with 1 worker (one problem at a time,
+    # one stream) and with 2 and 4 workers; the library's workers share the box's hardware queues
+    sweep = {}
+    for nw in sorted({1, 2, 4} - {args.workers}):
+        bw = hp.Batch(problems, nworkers=nw)
+        if variants:
+            bw.set_launch([variants[pr["nx"]] for pr in problems])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bw.propagate(ins, meds, [args.steps] * len(problems))
+        torch.cuda.synchronize()
+        sweep[nw] = total_steps / (time.perf_counter() - t1)
+        bw.close()
+        print(f"# {nw} workers: {sweep[nw]:.1f} steps/s", file=sys.stderr, flush=True)
+    sweep[args.workers] = total_steps / dt
+    # spot check: three problems (smallest, middle, largest) stepped by single plans equal the batch
+    order = sorted(range(len(problems)), key=lambda i: problems[i]["nx"])
+    spot = {}
+    for i in (order[0], order[len(order) // 2], order[-1]):
+        plan = hp.Plan(**problems[i], max_cycles=20)
+        if variants:
+            plan.set_launch(variants[problems[i]["nx"]])
+        ref = plan.propagate(ins[i], args.steps, n2=meds[i])
+        plan.close()
+        spot[i] = bool(torch.equal(ref, outs[i]))
     line = {"metric": "batch propagation steps/s (64 problems, N 256..1024, 8-16 poles)",
             "value": total_steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": 1e3 * dt / total_steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -147,7 +173,10 @@ def run_batch(args):
                        "sizes": sorted({p["nx"] for p in problems}),
                        "column_variant_by_size": {str(k): v for k, v in sorted(variants.items())}},
             "gmres_iterations": int(sum(it)), "all_finite": finite,
-            "busiest_problem_s": max(sec)}
+            "busiest_problem_s": max(sec),
+            "steps_per_s_by_workers": {str(k): v for k, v in sorted(sweep.items())},
+            "speedup_vs_one_worker": (total_steps / dt) / sweep[1],
+            "single_plan_equal": {str(k): v for k, v in spot.items()}}
     print(json.dumps(line))
     return 0
 
@@ -218,23 +247,22 @@ def run_learned(args):
         if mode == "prev":
             plan.set_guess(hp.HP_GUESS_PREV)
             plan.step(start)           # the first step has no previous solutions; untimed
-        lg = learn.LearnedGuess(plan, net, poles, 1.0, cfg["W"]) if mode == "learned" else None
+        # the learned mode: the library computes every pole's guess from the net at the start of
+        # each step (hp_set_guess_net + HP_GUESS_LEARNED); its time is the "guess" kernel class
+        lg = learn.LearnedGuess(plan, net, chunk=8) if mode == "learned" else None
         if lg is not None:
-            lg.step(start, n2)         # allocate activations; untimed
+            lg.step(start)             # allocate activations; untimed
+            plan.profile(True, classes=["guess"])
         a = start.clone()
         b = torch.empty_like(a)
-        its, acc_total, t_guess = [], 0, 0.0
+        its, acc_total = [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(args.steps):
             if lg is None:
                 plan.step(a, E_out=b)
             else:
-                tg = time.perf_counter()
-                X0 = lg.guesses(a, n2)
-                torch.cuda.synchronize()
-                t_guess += time.perf_counter() - tg
-                _, acc = plan.step_guess(a, [X0[k] for k in range(plan.npoles)], E_out=b)
+                _, acc = lg.step(a, E_out=b)
                 acc_total += sum(acc)
             its.append(sum(plan.stats()[0]))
             a, b = b, a
@@ -242,8 +270,9 @@ def run_learned(args):
         dt = time.perf_counter() - t0
         res[mode] = dict(steps_per_s=args.steps / dt, iters_per_step=float(np.mean(its)), field=a)
         if lg is not None:
-            res[mode]["guess_ms_per_step"] = 1e3 * t_guess / args.steps
+            res[mode]["guess_ms_per_step"] = plan.profile_read()["guess"][1] / args.steps
             res[mode]["accepted_frac"] = acc_total / (args.steps * plan.npoles)
+            plan.profile(False)
         plan.close()
         print(f"# {mode}: {res[mode]['steps_per_s']:.2f} steps/s, {res[mode]['iters_per_step']:.1f} iterations "
               f"per step", file=sys.stderr, flush=True)

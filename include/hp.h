@@ -164,12 +164,19 @@ int hp_solve(hp_plan plan, int pole, const void* rhs, void* x);
 int hp_step_guess(hp_plan plan, const void* E_in, const double* n2, const void* const* x0, int* accepted,
                   void* E_out);
 
-/* Start of every pole's GMRES in hp_step / hp_propagate: HP_GUESS_ZERO
- * (default) or HP_GUESS_PREV, the same pole's solution of the previous step on
- * this plan, judged as in hp_step_guess (the first step after the call starts
- * from zero).  HP_GUESS_PREV keeps each pole's solution in the workspace after
- * the step (one extra pass over each pole's Krylov basis). */
-enum { HP_GUESS_ZERO = 0, HP_GUESS_PREV = 1 };
+/* Start of every pole's GMRES in hp_step / hp_propagate (and in
+ * hp_step_guess when its x0 is NULL): HP_GUESS_ZERO (default); HP_GUESS_PREV,
+ * the same pole's solution of the previous step on this plan (the first step
+ * after the call starts from zero), which keeps each pole's solution in the
+ * workspace after the step (one extra pass over each pole's Krylov basis); or
+ * HP_GUESS_LEARNED, starting points from the U-Net attached by
+ * hp_set_guess_net (hp_unet.h), computed by the library at the start of every
+ * step: y_k = M_k^{-1} w, the net's correction from (w, y_k, the medium, the
+ * pole), x0_k = M_k^{-1}(w + sigma_k net_k).  Every guess is judged as in
+ * hp_step_guess (used only when its FP64 residual is below ||w||), so the
+ * solves end on the same test with any mode.  HP_ESTATE for HP_GUESS_LEARNED
+ * without a net.  Guesses apply to the exponential form only. */
+enum { HP_GUESS_ZERO = 0, HP_GUESS_PREV = 1, HP_GUESS_LEARNED = 2 };
 int hp_set_guess(hp_plan plan, int mode);
 
 /* Autotuner of the launch shape (not an operation of the method: it changes
@@ -282,7 +289,7 @@ int hp_apply_preconditioner_noalloc(hp_plan plan, int pole, const void* x, void*
  * milliseconds and summed algorithmic bytes since the last hp_profile call;
  * arrays have HP_K_COUNT entries (NULL to skip). */
 enum { HP_K_ROW_FWD = 0, HP_K_COL = 1, HP_K_ROW_APPLY = 2, HP_K_UPDATE = 3, HP_K_SMALL = 4,
-       HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_COUNT = 7 };
+       HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_GUESS = 7, HP_K_COUNT = 8 };
 int hp_profile(hp_plan plan, int enable);
 int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
 /* Time only every period-th launch of each timed class (period >= 1, counted

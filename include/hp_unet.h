@@ -115,6 +115,19 @@ int hp_guess_unpack(hp_unet net, int ncomp, int nx, int ny, const void* w, const
 int hp_guess_target(hp_unet net, int ncomp, int nx, int ny, const void* px, const double* scal, int B,
                     float* target);
 
+/* Attach a trained net to a plan for HP_GUESS_LEARNED (hp_set_guess, hp.h):
+ * the plan then computes every pole's starting point at the start of each step
+ * itself (preconditioner solves, hp_guess_stats / pack, hp_unet_forward on
+ * `chunk` poles at a time, hp_guess_unpack, preconditioner solves), on the
+ * plan's stream, which must be the net's.  The net needs cin = 4 ncomp + 3,
+ * cout = 2 ncomp, and nx, ny multiples of 2^(levels-1).  Allocates the guess
+ * buffers (2 npoles + chunk complex128 fields and the network's input and
+ * output for chunk poles; the net's activations are allocated by its first
+ * forward pass at that shape), freed by hp_set_guess_net(plan, NULL, 0) or
+ * with the plan.  The plan does not own the net: keep it alive while
+ * attached.  chunk 1..64 (capped at npoles). */
+int hp_set_guess_net(hp_plan plan, hp_unet net, int chunk);
+
 const char* hp_unet_last_error(hp_unet net);
 void hp_unet_destroy(hp_unet net);
 

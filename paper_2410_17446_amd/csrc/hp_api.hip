@@ -14,7 +14,12 @@
 #include <vector>
 
 #include "../../include/hp.h"
+#include "../../include/hp_unet.h"
 #include "kernels.hpp"
+
+// the learned guess needs the net's stream and channel counts (unet.hip)
+hipStream_t unet_stream(hp_unet n);
+void unet_shape(hp_unet n, int* levels, int* cin, int* cout);
 
 namespace {
 
@@ -110,6 +115,15 @@ struct hp_plan_s {
   int form = HP_FORM_EXP;      // what the pole table approximates and how a step uses it
   int substeps = 1;            // RK4 substeps per step (pseudo-differential form)
   c128* rk = nullptr;          // stage result, stage input, running sum (allocated by hp_set_form)
+  // learned initial guesses (HP_GUESS_LEARNED): the net, poles per forward pass, and the
+  // buffers of one step's guesses (set-up by hp_set_guess_net)
+  hp_unet net = nullptr;
+  int net_chunk = 0;
+  c128* lg_fields = nullptr;   // y_k = M_k^-1 w [K], guesses x0_k [K], net corrections t [chunk]
+  float *lg_in = nullptr, *lg_out = nullptr;
+  double* lg_scal = nullptr;
+  std::vector<double> lg_feat;  // per pole: asinh(Re b_k), asinh(Im b_k)
+  double* n2copy = nullptr;    // the medium of the last hp_set_medium (the net's V plane reads it)
   void* scratch = nullptr;     // this device's address of the library's static scratch (no-alloc calls)
   std::string scratch_err;
   std::string err;
@@ -162,7 +176,8 @@ struct Prof {
     if (p->ev_used + 2 > p->ev_pool.size()) {
       for (int i = 0; i < 256; ++i) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
+        // timing only: no system-scope fence (the events order nothing the host reads)
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return;
         p->ev_pool.push_back(e);
       }
     }
@@ -227,6 +242,7 @@ void layout(hp_plan p, Ws& w) {
   p->coef = w.take<double>((d.ncomp == 2 ? 6 : 1) * p->geo.fsz);
   p->coef_scratch = w.take<double>((d.ncomp == 2 ? 2 : 1) * p->geo.fsz);
   p->coef_f = w.take<float>((p->mixed && !p->mixed64) ? (d.ncomp == 2 ? 6 : 1) * p->geo.fsz : 1);
+  p->n2copy = w.take<double>(p->geo.fsz);
   p->U = w.take<char>((size_t)K * (M + 1) * fn * es);
   p->Z = w.take<char>((size_t)K * M * fn * es);
   p->P = w.take<char>((size_t)K * fn * es);
@@ -880,9 +896,86 @@ int run_step_sqrt(hp_plan p, const c128* w, c128* out) {
   return noconv ? HP_WARN_NOCONV : HP_OK;
 }
 
+// The column pass reads flag, m, b_k and sigma_m of its pole and u_m from the
+// pointer table: set them for one free-space solve (pole slot 0, m = 0,
+// sigma_0 = 1), by a kernel, so that no host copy is needed.
+__global__ void k_prec_setup(PoleState* st, void** tbl, void* u0, c128 b) {
+  if (threadIdx.x != 0) return;
+  st->flag = 0;
+  st->m = 0;
+  st->bk = b;
+  st->sigma[0] = 1.0;
+  tbl[0] = u0;
+}
+
+// y = (Zbar_fs - b_k I)^{-1} x (pole < 0: b = 0), asynchronous, with the given
+// intermediate buffers: tmpR, zout (and dz for vector fields) R-domain fields,
+// st one pole state, tbl one basis pointer table, part the row pass's partial norms.
+template <typename T, typename C>
+void prec_into(hp_plan p, int pole, const c128* x, c128* y, cx<T>* tmpR, cx<T>* zout, cx<T>* dz, PoleState* st,
+               void** tbl, double* part) {
+  const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
+  hipLaunchKernelGGL(k_prec_setup, dim3(1), dim3(64), 0, p->stream, st, tbl, (void*)tmpR, b);
+  launch_row_fwd<T, C>(x, tmpR, part, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
+  const int zero = 0;
+  launch_col<T, C>(reinterpret_cast<const cx<T>* const*>(tbl), zout, 0, 0, dz, 0, st, &zero, 1, nullptr, p->mu_x,
+                   p->mu_y, reinterpret_cast<const cx<C>*>(p->tw_y), p->geo, p->sc, p->stream);
+  launch_row_inv<T, C>(zout, y, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
+}
+
+// The same with the plan's own workspace as scratch (before or between steps).
+template <typename T, typename C>
+void prec_ws(hp_plan p, int pole, const c128* x, c128* y) {
+  prec_into<T, C>(p, pole, x, y, reinterpret_cast<cx<T>*>(p->tmpR), reinterpret_cast<cx<T>*>(p->P),
+                  reinterpret_cast<cx<T>*>(p->DZ), p->st_scratch, p->uptr_scratch, p->part_misc);
+}
+
+// Learned starting points of every pole for right-hand side w (HP_GUESS_LEARNED):
+// y_k = M_k^-1 w, the net's correction from (w, y_k, V, pole) in chunks of
+// net_chunk poles, t_k = w + sigma_k net_k, x0_k = M_k^-1 t_k; the guesses land in
+// the plan's guess fields and the step judges them like any other (hp_step_guess).
+template <typename T, typename C>
+int learned_guesses(hp_plan p, const c128* w, std::vector<const c128*>& x0) {
+  const hp_plan_desc& d = p->d;
+  const int K = d.npoles, B = p->net_chunk;
+  const size_t fn = p->fieldn;
+  c128* Y = p->lg_fields;
+  c128* X0 = Y + (size_t)K * fn;
+  c128* Tt = X0 + (size_t)K * fn;
+  Prof pr(p, HP_K_GUESS, 0.0);
+  for (int k = 0; k < K; ++k) prec_ws<T, C>(p, k, w, Y + (size_t)k * fn);
+  auto net_fail = [&](int rc, const char* what) {
+    return fail(p, rc, std::string("learned guess, ") + what + ": " + hp_unet_last_error(p->net));
+  };
+  for (int k0 = 0; k0 < K; k0 += B) {
+    const int nb = std::min(B, K - k0);
+    int rc = hp_guess_stats(p->net, d.ncomp, d.nx, d.ny, d.n0, d.edge_width, w, Y + (size_t)k0 * fn, p->n2copy, nb,
+                            p->lg_scal);
+    if (rc) return net_fail(rc, "hp_guess_stats");
+    rc = hp_guess_pack(p->net, d.ncomp, d.nx, d.ny, d.n0, d.edge_width, w, Y + (size_t)k0 * fn, p->n2copy, p->lg_scal,
+                       p->lg_feat.data() + 2 * k0, nb, p->lg_in);
+    if (rc) return net_fail(rc, "hp_guess_pack");
+    rc = hp_unet_forward(p->net, p->lg_in, nb, d.ny, d.nx, p->lg_out);
+    if (rc) return net_fail(rc, "hp_unet_forward");
+    rc = hp_guess_unpack(p->net, d.ncomp, d.nx, d.ny, w, p->lg_out, p->lg_scal, nb, Tt);
+    if (rc) return net_fail(rc, "hp_guess_unpack");
+    for (int j = 0; j < nb; ++j) prec_ws<T, C>(p, k0 + j, Tt + (size_t)j * fn, X0 + (size_t)(k0 + j) * fn);
+  }
+  HPCHK(hipGetLastError());
+  x0.resize(K);
+  for (int k = 0; k < K; ++k) x0[k] = X0 + (size_t)k * fn;
+  return HP_OK;
+}
+
 template <typename T, typename C>
 int run_step(hp_plan p, const c128* w, c128* out, const c128* const* x0 = nullptr) {
   if (p->form == HP_FORM_SQRT) return run_step_sqrt<T, C>(p, w, out);
+  std::vector<const c128*> lg;
+  if (!x0 && p->guess_mode == HP_GUESS_LEARNED) {
+    int rc = learned_guesses<T, C>(p, w, lg);
+    if (rc) return rc;
+    x0 = lg.data();
+  }
   return solve_and_sum<T, C>(p, w, out, p->phase, p->rinf_phase, p->loss_coef, x0, 1);
 }
 
@@ -1072,6 +1165,7 @@ int hp_set_medium(hp_plan p, const double* n2) {
   if (!n2) return fail(p, HP_EINVAL, "n2 is NULL");
   const double s = 1.0 / ((p->d.k0 * p->d.n0) * (p->d.k0 * p->d.n0));
   launch_coef(n2, p->coef, p->coef_scratch, p->d.n0, s, p->d.edge_width, p->sc, p->geo, p->stream);
+  HPCHK(hipMemcpyAsync(p->n2copy, n2, p->geo.fsz * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   if (p->mixed && !p->mixed64)
     launch_to_float(p->coef, p->coef_f, (p->d.ncomp == 2 ? 6 : 1) * p->geo.fsz, p->stream);
   HPCHK(hipGetLastError());
@@ -1165,9 +1259,60 @@ int hp_autotune(hp_plan p, const void* E_in, const double* n2, int reps, void* E
 
 int hp_set_guess(hp_plan p, int mode) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
-  if (mode != HP_GUESS_ZERO && mode != HP_GUESS_PREV) return fail(p, HP_EINVAL, "unknown guess mode");
+  if (mode != HP_GUESS_ZERO && mode != HP_GUESS_PREV && mode != HP_GUESS_LEARNED)
+    return fail(p, HP_EINVAL, "unknown guess mode");
+  if (mode == HP_GUESS_LEARNED && !p->net)
+    return fail(p, HP_ESTATE, "HP_GUESS_LEARNED needs a net: call hp_set_guess_net first");
   p->guess_mode = mode;
   p->prev_valid = false;
+  return HP_OK;
+}
+
+static void free_guess_net(hp_plan p) {
+  for (void* b : {(void*)p->lg_fields, (void*)p->lg_in, (void*)p->lg_out, (void*)p->lg_scal})
+    if (b) (void)hipFree(b);
+  p->lg_fields = nullptr;
+  p->lg_in = p->lg_out = nullptr;
+  p->lg_scal = nullptr;
+  p->net = nullptr;
+  p->net_chunk = 0;
+}
+
+int hp_set_guess_net(hp_plan p, hp_unet net, int chunk) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  HPCHK(hipStreamSynchronize(p->stream));
+  if (!net) {
+    free_guess_net(p);
+    if (p->guess_mode == HP_GUESS_LEARNED) p->guess_mode = HP_GUESS_ZERO;
+    return HP_OK;
+  }
+  const hp_plan_desc& d = p->d;
+  int levels = 0, cin = 0, cout = 0;
+  unet_shape(net, &levels, &cin, &cout);
+  if (cin != 4 * d.ncomp + 3 || cout != 2 * d.ncomp)
+    return fail(p, HP_EINVAL, "the net needs cin = 4 ncomp + 3 and cout = 2 ncomp inputs/outputs for this plan");
+  const int mult = 1 << (levels - 1);
+  if (d.nx % mult || d.ny % mult) return fail(p, HP_EINVAL, "nx, ny must be multiples of 2^(levels - 1)");
+  if (unet_stream(net) != p->stream) return fail(p, HP_EINVAL, "the net must run on the plan's stream");
+  if (chunk < 1 || chunk > 64) return fail(p, HP_EINVAL, "chunk must be in [1, 64]");
+  chunk = std::min(chunk, d.npoles);
+  free_guess_net(p);
+  const size_t fn = p->fieldn, px = (size_t)d.nx * d.ny;
+  hipError_t e = hipMalloc(&p->lg_fields, (2 * (size_t)d.npoles + chunk) * fn * sizeof(c128));
+  if (e == hipSuccess) e = hipMalloc(&p->lg_in, (size_t)chunk * cin * px * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&p->lg_out, (size_t)chunk * cout * px * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&p->lg_scal, (chunk + 2) * sizeof(double));
+  if (e != hipSuccess) {
+    free_guess_net(p);
+    return fail(p, HP_ENOMEM, std::string("learned-guess buffers: ") + hipGetErrorString(e));
+  }
+  p->net = net;
+  p->net_chunk = chunk;
+  p->lg_feat.resize(2 * (size_t)d.npoles);
+  for (int k = 0; k < d.npoles; ++k) {
+    p->lg_feat[2 * k] = std::asinh(p->poles[k].re);
+    p->lg_feat[2 * k + 1] = std::asinh(p->poles[k].im);
+  }
   return HP_OK;
 }
 
@@ -1377,6 +1522,7 @@ void hp_plan_destroy(hp_plan p) {
   if (p->guess_rpart) (void)hipFree(p->guess_rpart);
   if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
   if (p->rk) (void)hipFree(p->rk);
+  free_guess_net(p);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -1604,17 +1750,6 @@ void* scratch_for_current_device(std::string* why) {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// The column pass reads flag, m, b_k and sigma_m of its pole and u_m from the
-// pointer table: set them for one application (pole slot 0, m = 0, sigma_0 = 1).
-__global__ void k_prec_setup(PoleState* st, void** tbl, void* u0, c128 b) {
-  if (threadIdx.x != 0) return;
-  st->flag = 0;
-  st->m = 0;
-  st->bk = b;
-  st->sigma[0] = 1.0;
-  tbl[0] = u0;
-}
-
 template <typename T, typename C>
 int apply_prec_noalloc(hp_plan p, int pole, const c128* x, c128* y) {
   char* base = reinterpret_cast<char*>(p->scratch);
@@ -1627,13 +1762,7 @@ int apply_prec_noalloc(hp_plan p, int pole, const c128* x, c128* y) {
   void** tbl = reinterpret_cast<void**>(small + align256(sizeof(PoleState)));
   double* part = reinterpret_cast<double*>(small + align256(sizeof(PoleState)) +
                                            align256((HP_MAXM + 1) * sizeof(void*)));
-  const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
-  hipLaunchKernelGGL(k_prec_setup, dim3(1), dim3(64), 0, p->stream, st, tbl, (void*)tmpR, b);
-  launch_row_fwd<T, C>(x, tmpR, part, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
-  const int zero = 0;
-  launch_col<T, C>(reinterpret_cast<const cx<T>* const*>(tbl), zout, 0, 0, dz, 0, st, &zero, 1, nullptr, p->mu_x,
-                   p->mu_y, reinterpret_cast<const cx<C>*>(p->tw_y), p->geo, p->sc, p->stream);
-  launch_row_inv<T, C>(zout, y, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, tile_width<T>(), p->stream);
+  prec_into<T, C>(p, pole, x, y, tmpR, zout, dz, st, tbl, part);
   HPCHK(hipGetLastError());
   return HP_OK;
 }

@@ -1025,6 +1025,14 @@ int check_fields(hp_unet n, int ncomp, int nx, int ny, int B) {
 
 }  // namespace
 
+// For the plan's learned-guess mode (hp_api.hip): the net's stream and shape.
+hipStream_t unet_stream(hp_unet n) { return n ? n->stream : nullptr; }
+void unet_shape(hp_unet n, int* levels, int* cin, int* cout) {
+  *levels = n ? n->levels : 0;
+  *cin = n ? n->cin : 0;
+  *cout = n ? n->cout : 0;
+}
+
 extern "C" {
 
 int hp_unet_create(int levels, int base, int cin, int cout, unsigned long long seed, void* stream, hp_unet* out) {

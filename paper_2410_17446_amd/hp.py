@@ -18,7 +18,7 @@ _lib = None
 
 HP_OK, HP_WARN_NOCONV, HP_WARN_UNSTABLE = 0, 1, 2
 HP_FP64, HP_MIXED, HP_MIXED64 = 0, 1, 2
-HP_GUESS_ZERO, HP_GUESS_PREV = 0, 1
+HP_GUESS_ZERO, HP_GUESS_PREV, HP_GUESS_LEARNED = 0, 1, 2
 HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
@@ -28,7 +28,7 @@ SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_profile_totals", "hp_last_error",
            "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
-KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual")
+KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual", "guess")
 
 
 class hp_c128(C.Structure):
@@ -198,6 +198,14 @@ class Plan:
 
     def set_guess(self, mode):
         return self._check(self.L.hp_set_guess(self.handle, int(mode)), "hp_set_guess")
+
+    def set_guess_net(self, net, chunk=8):
+        """Attach a trained UNet for HP_GUESS_LEARNED (None detaches); the plan keeps a reference."""
+        from . import unet as un
+        L = un.lib()
+        self._net = net
+        rc = L.hp_set_guess_net(self.handle, net.handle if net is not None else None, int(chunk))
+        return self._check(rc, "hp_set_guess_net")
 
     def set_form(self, form, substeps=1):
         """HP_FORM_EXP or HP_FORM_SQRT (pseudo-differential form, `substeps` RK4 substeps per

@@ -3,11 +3,13 @@ and training, all driven through the library (hp.h, hp_unet.h).
 
 The network's job and the fallback are described in include/hp_unet.h: for
 pole k it predicts the correction u_k - w = -P x_k, the guess is
-x0_k = M_k^{-1}(w + sigma_k net_k), and hp_step_guess keeps the zero start for
-any pole whose guess has a larger FP64 residual than the zero start.  Every
-arithmetic step (preconditioner solves, feature planes, forward and reverse
-passes, Adam, the GMRES solves that make the training pairs) runs in the
-library's HIP kernels; this module only orders the calls and holds tensors.
+x0_k = M_k^{-1}(w + sigma_k net_k), and the step keeps the zero start for any
+pole whose guess has a larger FP64 residual than the zero start.  The guess
+step itself is the plan's HP_GUESS_LEARNED mode (the library orders its own
+calls); every arithmetic step of data generation and training (preconditioner
+solves, feature planes, forward and reverse passes, Adam, the GMRES solves
+that make the training pairs) runs in the library's HIP kernels; this module
+only orders those calls and holds tensors.
 """
 from __future__ import annotations
 
@@ -26,39 +28,19 @@ def pole_features(poles) -> np.ndarray:
 
 
 class LearnedGuess:
-    """Guesses for all poles of a plan from a trained net; poles go through the net in
-    chunks of `chunk` samples (activation memory grows with chunk * nx * ny)."""
+    """The plan's learned-guess mode: the net is attached with hp_set_guess_net and the mode set
+    to HP_GUESS_LEARNED, so the library itself computes every pole's starting point at the start
+    of each step (preconditioner solves, feature planes, forward passes on `chunk` poles at a
+    time); this class only makes those two calls and steps."""
 
-    def __init__(self, plan: hp.Plan, net: UNet, poles, n0: float, edge_width: int, chunk: int = 8):
+    def __init__(self, plan: hp.Plan, net: UNet, chunk: int = 8):
         self.plan, self.net = plan, net
-        self.feats = pole_features(poles)
-        self.n0, self.W, self.chunk = n0, edge_width, chunk
-        self._y = self._x0 = None
+        plan.set_guess_net(net, chunk)
+        plan.set_guess(hp.HP_GUESS_LEARNED)
 
-    def guesses(self, w, n2):
-        """x0 (K, ncomp, ny, nx) complex128 for the step's field w and medium n2 (device)."""
-        import torch
-        K = self.plan.npoles
-        if self._y is None or self._y.shape[1:] != w.shape:
-            self._y = torch.empty((K,) + tuple(w.shape), dtype=torch.complex128, device=w.device)
-            self._x0 = torch.empty_like(self._y)
-        Y, X0 = self._y, self._x0
-        for k in range(K):
-            self.plan.apply_preconditioner(k, w, Y[k])
-        for k0 in range(0, K, self.chunk):
-            k1 = min(K, k0 + self.chunk)
-            scal = self.net.guess_stats(w, Y[k0:k1], n2, self.n0, self.W)
-            xin = self.net.guess_pack(w, Y[k0:k1], n2, scal, self.feats[k0:k1], self.n0, self.W)
-            out = self.net.forward(xin)
-            T = self.net.guess_unpack(w, out, scal)
-            for j, k in enumerate(range(k0, k1)):
-                self.plan.apply_preconditioner(k, T[j], X0[k])
-        return X0
-
-    def step(self, w, n2, E_out=None):
+    def step(self, w, n2=None, E_out=None):
         """One step from learned guesses: (E_out, accepted flags)."""
-        X0 = self.guesses(w, n2)
-        return self.plan.step_guess(w, [X0[k] for k in range(self.plan.npoles)], n2=n2, E_out=E_out)
+        return self.plan.step_guess(w, None, n2=n2, E_out=E_out)
 
 
 def plan_for(N, ncomp, poles, residues, r_inf, d2, d1, W, tol, precision=hp.HP_FP64, eta=0.25, dz=1.0):

@@ -15,7 +15,7 @@ from . import hp
 
 SYMBOLS = ("hp_unet_create", "hp_unet_num_params", "hp_unet_set_precision", "hp_unet_get_params", "hp_unet_set_params",
            "hp_unet_forward", "hp_unet_grad", "hp_unet_adam", "hp_guess_stats", "hp_guess_pack",
-           "hp_guess_unpack", "hp_guess_target", "hp_unet_last_error", "hp_unet_destroy")
+           "hp_guess_unpack", "hp_guess_target", "hp_set_guess_net", "hp_unet_last_error", "hp_unet_destroy")
 
 _ready = False
 HP_UNET_F32, HP_UNET_BF16 = 0, 1
@@ -40,6 +40,7 @@ def lib():
                                     C.c_int, vp]
         L.hp_guess_unpack.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, C.c_int, vp]
         L.hp_guess_target.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int, vp]
+        L.hp_set_guess_net.argtypes = [vp, vp, C.c_int]
         L.hp_unet_last_error.argtypes = [vp]
         L.hp_unet_last_error.restype = C.c_char_p
         L.hp_unet_destroy.argtypes = [vp]

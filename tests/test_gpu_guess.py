@@ -133,3 +133,73 @@ def test_previous_step_guess_propagation(precision):
     (a, n0), (b, n1) = res[hp.HP_GUESS_ZERO], res[hp.HP_GUESS_PREV]
     assert rel_l2(b, a) < 1e-7
     assert n1 < n0, (n0, n1)
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_learned_mode_orders_the_same_calls_as_the_caller_would(ncomp):
+    """HP_GUESS_LEARNED: the library computes each pole's guess itself (y_k = M_k^-1 w, feature
+    planes, the net on `chunk` poles at a time, t_k = w + sigma_k net_k, x0_k = M_k^-1 t_k).  The
+    same guesses made call by call through the C ABI and passed to hp_step_guess give the same
+    step, bit for bit, and the same accepted flags; the step meets tol on every pole.  An
+    untrained net (random weights) is enough: the check is of the orchestration, not the net."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp, learn
+    from paper_2410_17446_amd.unet import UNet
+    N, W = 64, 8
+    wl = workload(N=N, ncomp=ncomp, W=W, npoles=8, tol=1e-10)
+    net = UNet(3, 8, 4 * ncomp + 3, 2 * ncomp, seed=3)
+    w, n2 = to_gpu(wl["w"]), to_gpu(wl["n2"])
+    # by hand, 3 poles per forward pass
+    plan = gpu_plan(wl)
+    plan.set_medium(n2)
+    K, chunk = plan.npoles, 3
+    feats = learn.pole_features(wl["fit"]["poles"])
+    x0 = []
+    for k0 in range(0, K, chunk):
+        ks = list(range(k0, min(K, k0 + chunk)))
+        Y = torch.empty((len(ks),) + tuple(w.shape), dtype=torch.complex128, device="cuda")
+        for j, k in enumerate(ks):
+            plan.apply_preconditioner(k, w, Y[j])
+        scal = net.guess_stats(w, Y, n2, 1.0, W)
+        out = net.forward(net.guess_pack(w, Y, n2, scal, feats[ks], 1.0, W))
+        T = net.guess_unpack(w, out, scal)
+        for j, k in enumerate(ks):
+            x = torch.empty_like(w)
+            plan.apply_preconditioner(k, T[j], x)
+            x0.append(x)
+    ref, acc_ref = plan.step_guess(w, x0)
+    it_ref, _ = plan.stats()
+    plan.close()
+    # by the library
+    plan = gpu_plan(wl)
+    with pytest.raises(hp.HPError, match="needs a net"):
+        plan.set_guess(hp.HP_GUESS_LEARNED)
+    lg = learn.LearnedGuess(plan, net, chunk=chunk)
+    out, acc = lg.step(w, n2)
+    it, rr = plan.stats()
+    assert acc == acc_ref and it == it_ref
+    assert torch.equal(out, ref)
+    assert max(rr) <= 1e-10
+    # hp_step in the same mode uses the same guesses
+    out2 = plan.step(w, n2)
+    assert torch.equal(out2, ref)
+    # detaching the net returns the plan to zero starts
+    plan.set_guess_net(None)
+    zero = gpu_plan(wl)
+    assert torch.equal(plan.step(w, n2), zero.step(w, n2))
+    plan.close()
+    zero.close()
+
+
+def test_learned_mode_rejects_a_mismatched_net():
+    torch = _cuda()
+    from paper_2410_17446_amd import hp
+    from paper_2410_17446_amd.unet import UNet
+    wl = workload(N=64, W=8)
+    plan = gpu_plan(wl)
+    with pytest.raises(hp.HPError, match="cin"):
+        plan.set_guess_net(UNet(3, 8, 11, 4, seed=1))      # a vector net on a scalar plan
+    other = torch.cuda.Stream()                            # default priority
+    with pytest.raises(hp.HPError, match="stream"):
+        plan.set_guess_net(UNet(3, 8, 7, 2, seed=1, stream=other.cuda_stream))
+    plan.close()
