@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--workers", type=int, default=8, help="batch workers (batch64 workload)")
     ap.add_argument("--unet-base", type=int, default=32, help="U-Net base channels (learned workload)")
     ap.add_argument("--train-n", type=int, default=256, help="training grid (learned workload)")
+    ap.add_argument("--learned-workload", default="scalar1024", choices=["scalar1024", "vector2048"],
+                    help="workload the learned guesses are timed on")
+    ap.add_argument("--learned-chunk", type=int, default=8, help="poles per U-Net forward pass (learned)")
     ap.add_argument("--train-draws", type=int, default=48, help="(medium, beam) draws for training")
     ap.add_argument("--train-seconds", type=float, default=90.0, help="training time budget")
     ap.add_argument("--event-period", type=int, default=EVENT_PERIOD,
@@ -194,25 +197,30 @@ def unet_forward_flops(levels, base, cin, cout, H, W):
 
 
 def run_learned(args):
-    """Learned initial guesses on the scalar1024 workload against the plain method and the
-    previous-step start: train a U-Net on FP64 solve pairs the propagator makes at 256^2
-    (random media and beams, the same 16-pole table), then time steps of all three from the
-    same field (the plain method's field after the warmup steps)."""
+    """Learned initial guesses (the plan's HP_GUESS_LEARNED mode: U-Net guesses for every pole,
+    computed in batched forward passes, with the lockstep solves of all poles) against the plain
+    method and the previous-step start, on the scalar1024 workload (the headline's second arm) or,
+    with --learned-workload vector2048, on the 2048^2 vector workload (E_x, E_y, 24 poles): train
+    a U-Net on FP64 solve pairs the propagator makes at --train-n (random media and beams, the same
+    pole table), then time steps of all three modes from the same field (the plain method's field
+    after the warmup steps)."""
     import numpy as np
     import torch
 
     from paper_2410_17446_amd import hp, inputs, learn, tables
     from paper_2410_17446_amd.unet import HP_UNET_BF16, HP_UNET_F32, UNet
-    cfg = dict(inputs.CONFIGS["scalar1024"])
+    cfg = dict(inputs.CONFIGS[args.learned_workload])
+    nc = cfg["ncomp"]
+    cin, cout = 4 * nc + 3, 2 * nc
     poles, residues, r_inf, d2, d1 = tables.plan_tables(inputs.K0 * cfg["dz"], cfg["npoles"])
     fit = dict(poles=poles, residues=residues, r_inf=r_inf)
     levels, base = 4, args.unet_base
     prec = HP_UNET_BF16 if args.unet_precision == "bf16" else HP_UNET_F32
-    net = UNet(levels, base, 7, 2, seed=0, precision=prec)
+    net = UNet(levels, base, cin, cout, seed=0, precision=prec)
     t0 = time.perf_counter()
-    X, T = learn.generate(net, fit, d2, d1, args.train_n, 1, count=args.train_draws, seed=1, tol=1e-10,
+    X, T = learn.generate(net, fit, d2, d1, args.train_n, nc, count=args.train_draws, seed=1, tol=1e-10,
                           poles_per_field=8)
-    Xv, Tv = learn.generate(net, fit, d2, d1, args.train_n, 1, count=8, seed=2, tol=1e-10, poles_per_field=8)
+    Xv, Tv = learn.generate(net, fit, d2, d1, args.train_n, nc, count=8, seed=2, tol=1e-10, poles_per_field=8)
     t_gen = time.perf_counter() - t0
     print(f"# training pairs: {X.shape[0]} at {args.train_n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
     learn.train(net, X, T, steps=3, batch=8, lr=1e-3)   # first calls allocate; not timed
@@ -222,7 +230,7 @@ def run_learned(args):
     torch.cuda.synchronize()
     per = (time.perf_counter() - t0) / 20
     nsteps = max(10, int(args.train_seconds / per))
-    net = UNet(levels, base, 7, 2, seed=0, precision=prec)
+    net = UNet(levels, base, cin, cout, seed=0, precision=prec)
     t0 = time.perf_counter()
     losses = learn.train(net, X, T, steps=nsteps, batch=8, lr=1e-3, lr_final=1e-4, log_every=max(1, nsteps // 5))
     torch.cuda.synchronize()
@@ -232,7 +240,7 @@ def run_learned(args):
           file=sys.stderr, flush=True)
     del X, T
     N = cfg["N"]
-    mk = lambda: hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=inputs.K0, n0=1.0, dz=cfg["dz"], ncomp=1,
+    mk = lambda: hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=inputs.K0, n0=1.0, dz=cfg["dz"], ncomp=nc,
                          poles=poles, residues=residues, r_inf=r_inf, d2=d2, d1=d1, edge_width=cfg["W"],
                          edge_eta=cfg["eta_max"], tol=cfg["tol"], restart=cfg["restart"], max_cycles=20)
     w0 = torch.from_numpy(inputs.beam(cfg)).cuda()
@@ -249,7 +257,7 @@ def run_learned(args):
             plan.step(start)           # the first step has no previous solutions; untimed
         # the learned mode: the library computes every pole's guess from the net at the start of
         # each step (hp_set_guess_net + HP_GUESS_LEARNED); its time is the "guess" kernel class
-        lg = learn.LearnedGuess(plan, net, chunk=8) if mode == "learned" else None
+        lg = learn.LearnedGuess(plan, net, chunk=args.learned_chunk) if mode == "learned" else None
         if lg is not None:
             lg.step(start)             # allocate activations; untimed
             plan.profile(True, classes=["guess"])
@@ -280,8 +288,8 @@ def run_learned(args):
     for mode in res:
         f = res[mode].pop("field").cpu().numpy()
         res[mode]["err_vs_plain"] = float(np.linalg.norm(f - ref) / np.linalg.norm(ref))
-    # U-Net forward throughput at the inference shape (8 poles per launch)
-    x = torch.randn(8, 7, N, N, device="cuda")
+    # U-Net forward throughput at the inference shape (learned_chunk poles per launch)
+    x = torch.randn(args.learned_chunk, cin, N, N, device="cuda")
     net.forward(x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -289,15 +297,16 @@ def run_learned(args):
         net.forward(x)
     torch.cuda.synchronize()
     fwd = (time.perf_counter() - t0) / 3
-    tflops = unet_forward_flops(levels, base, 7, 2, N, N) * 8 / fwd / 1e12
-    line = {"metric": "propagation steps/s (1024^2, 16 poles, tol 1e-8) with learned initial guesses",
+    tflops = unet_forward_flops(levels, base, cin, cout, N, N) * args.learned_chunk / fwd / 1e12
+    what = f"{N}^2{' vector' if nc == 2 else ''}, {cfg['npoles']} poles, tol {cfg['tol']:g}"
+    line = {"metric": f"propagation steps/s ({what}) with learned initial guesses, all poles batched",
             "value": res["learned"]["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 / res["learned"]["steps_per_s"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "c128+f32", "data": "synthetic",
-            "config": {"workload": "scalar1024", "grid": N, "poles": cfg["npoles"], "tol": cfg["tol"],
+            "config": {"workload": args.learned_workload, "grid": N, "poles": cfg["npoles"], "tol": cfg["tol"],
                        "unet": {"levels": levels, "base": base, "params": net.nparam,
-                                "convolutions": args.unet_precision},
-                       "training": {"grid": args.train_n, "pairs": args.train_draws * 8,
+                                "convolutions": args.unet_precision, "poles_per_forward": args.learned_chunk},
+                       "training": {"grid": args.train_n, "components": nc, "pairs": args.train_draws * 8,
                                     "adam_steps": nsteps, "batch": 8, "seconds": t_train,
                                     "datagen_seconds": t_gen, "final_loss": float(np.mean(losses[-20:])),
                                     "heldout_mse": mse, "heldout_mse_free_space": mse0}},

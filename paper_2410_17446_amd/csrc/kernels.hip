@@ -920,15 +920,27 @@ __global__ __launch_bounds__(64) void k_arnoldi(PoleState* __restrict__ st, cons
     // least squares R y = g, then y~ = Rc^{-1} y (the coefficients of the stored Z~);
     // both triangles go through LDS, packed (one parallel load each)
     __shared__ c128 tri[HP_MAXM * (HP_MAXM + 1) / 2];
-    const int n = m + 1;
-    for (int c = 0; c < n; ++c)
-      for (int r = tid; r <= c; r += 64)
-        tri[pk(r, c)] = (c == m) ? c2[r] : (c == m - 1 ? c1[r] : S.H[r + c * LD]);
+    const int n = m + 1, npk = n * (n + 1) / 2;
+    // packed index e = c (c + 1)/2 + r: every thread loads entries of its own, all at once
+    auto unpack = [](int e, int& r, int& c) {
+      c = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      if ((c + 1) * (c + 2) / 2 <= e) ++c;
+      if (c * (c + 1) / 2 > e) --c;
+      r = e - c * (c + 1) / 2;
+    };
+    for (int e = tid; e < npk; e += 64) {
+      int r, c;
+      unpack(e, r, c);
+      tri[e] = (c == m) ? c2[r] : (c == m - 1 ? c1[r] : S.H[r + c * LD]);
+    }
     for (int i = tid; i < n; i += 64) rhs[i] = S.g[i];
     __syncthreads();
     upper_solve(tri, rhs, y, n);
-    for (int c = 0; c < n; ++c)
-      for (int r = tid; r <= c; r += 64) tri[pk(r, c)] = S.Rc[r + c * LD];
+    for (int e = tid; e < npk; e += 64) {
+      int r, c;
+      unpack(e, r, c);
+      tri[e] = S.Rc[r + c * LD];
+    }
     for (int i = tid; i < n; i += 64) rhs[i] = y[i];  // the least-squares solution
     __syncthreads();
     upper_solve(tri, rhs, y, n);

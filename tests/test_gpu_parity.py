@@ -492,3 +492,41 @@ def test_full_step_scalar1024_matches_oracle():
     err = rel_l2(out, ref)
     print(f"1024^2 step vs oracle: relative L2 {err:.3e}, iterations {stats.iters}")
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("table,dz", [("pf_lookup_n1_16.json", 0.5), ("pf_lookup_n1.0003_16.json", 2.0)])
+def test_plan_from_the_lookup_table_matches_oracle(table, dz):
+    """A plan whose partial fractions come from a shipped lookup table over k0 dz (Sec. 3.1: the
+    coefficients depend on K = k0 n0 dz only, so one table at fixed n0 serves every step length
+    in it): a 128^2 step against the oracle's step with the same table entry, the oracle's
+    iteration counts replayed, 1e-10 relative L2; the table entry equals a fresh fit's accuracy
+    on the fit's interval."""
+    torch = _cuda()
+    import os
+    from oracle import fit as ofit
+    from paper_2410_17446_amd import hp, tables
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_17446_amd", "data",
+                        table)
+    lut = tables.PFLookup.load(path)
+    k0 = 2 * np.pi
+    poles, residues, r_inf = lut.get(k0, dz, lut.n0)
+    z = np.linspace(-4, 2, 4001)
+    r = r_inf + (1.0 / np.subtract.outer(z, poles)) @ residues
+    assert np.abs(r - ofit.target(z, k0 * lut.n0 * dz)).max() < 2e-5
+    N = 128
+    c, d = tables.stencil_d2(), tables.stencil_d1()
+    xs = inputs.coords(N, 0.25)
+    n2 = (lut.n0 * (1 + 0.02 * np.sin(2 * np.pi * xs)[None, :] * np.sin(2 * np.pi * xs)[:, None])) ** 2
+    w = inputs.gaussian_beam(N, 0.25, 4.0)
+    g = op.Grid(N=N, dx=0.25, dy=0.25, k0=k0, n0=lut.n0, c=c, d=d, W=16, eta_max=0.25)
+    co = op.coefficients(g, n2, False)
+    ref, stats = st.step(g, co, w, st.PFTable(poles, residues, r_inf), dz, 1e-10)
+    assert all(len(cy) == 1 for cy in stats.cycle_iters)
+    plan = hp.Plan(nx=N, ny=N, dx=0.25, dy=0.25, k0=k0, n0=lut.n0, dz=dz, ncomp=1, poles=poles, residues=residues,
+                   r_inf=r_inf, d2=c, d1=d, edge_width=16, edge_eta=0.25, tol=1e-10)
+    plan.set_fixed_iters([cy[0] for cy in stats.cycle_iters])
+    out = plan.step(to_gpu(w), to_gpu(n2)).cpu().numpy()
+    plan.close()
+    err = rel_l2(out, ref)
+    print(f"{table} at dz = {dz}: relative L2 vs oracle {err:.3e}, iterations {stats.iters}")
+    assert err < 1e-10
