@@ -235,6 +235,41 @@ int hp_set_launch(hp_plan plan, int col_variant);
 enum { HP_FORM_EXP = 0, HP_FORM_SQRT = 1 };
 int hp_set_form(hp_plan plan, int form, int substeps);
 
+/* Absorbing layers (Sec. 4.1): the periphery of W = edge_width cells along
+ * each axis becomes a perfectly matched layer by complex-coordinate
+ * stretching of the transverse derivatives, d/dx -> (1/g) d/dx with
+ *   g(x) = 1 + i sigma,  sigma = sigma_max ((W + 1 - d)/W)^2 for 1 <= d <= W,
+ *   0 beyond (d: distance in cells to the axis's nearer Dirichlet node),
+ * so that along each axis
+ *   d^2/dx~^2 = (1/g^2) d^2/dx^2 - (g'/g^3) d/dx,
+ * discretised node by node with the plan's 13-point D2 and D1 (odd
+ * reflection about the Dirichlet nodes) and the exact derivative g'.  Zbar
+ * keeps its medium term V = (n^2 - n0^2)/n0^2, zero inside the layers; the
+ * free-space problem of pole b_k is the Sylvester equation of Sec. 4.2 eq.
+ * fs_sylvester with the stretched matrices, solved by eigen-decomposition of
+ * the one-axis operator s D~ = Q diag(lam) Q^-1 (s = 1/(k0 n0)^2; both axes
+ * share it):  W = Q [(Q^-1 Y Q^-T) / (lam_p + lam_q - b_k)] Q^T.  The step of
+ * eq. approx_prop then has no separate edge loss (edge_eta is ignored): the
+ * layers absorb.  GMRES ends every solve on its FP64 true residual.
+ *
+ * Q, Qinv: host complex128 [N-1][N-1] row-major, lam: host complex128 [N-1],
+ * N = nx = ny, for the unknowns 1..N-1 of one axis (computed by the caller,
+ * e.g. by a dense eigensolver); the library copies them (2 N^2 complex128 on
+ * the device) and checks on the host that Q diag(lam) Qinv reproduces its own
+ * s D~ on two pseudo-random vectors to 1e-6 (HP_EINVAL otherwise) and that no
+ * pole meets lam_p + lam_q.  The first call allocates the tables, one field
+ * per pole and the inner-product partials (hipMalloc), freed with the plan.
+ * Requires ncomp = 1, nx = ny, dx = dy, HP_FP64 (HP_EINVAL otherwise), the
+ * exponential form and HP_GUESS_ZERO (HP_ESTATE otherwise); while the layers
+ * are set hp_set_form, hp_set_guess and hp_step_guess with guesses return
+ * HP_ESTATE, hp_apply_operator and hp_apply_preconditioner apply the stretched
+ * operators, and hp_apply_preconditioner_noalloc returns HP_ESTATE.
+ * sigma_max = 0 with Q, Qinv, lam all NULL removes the layers.  In the
+ * kernel timing the class HP_K_PML holds the four dense stages of every
+ * round, and its byte figure counts floating-point operations instead
+ * (32 (N-1)^3 per pole and round). */
+int hp_set_pml(hp_plan plan, double sigma_max, const void* Q, const void* Qinv, const void* lam);
+
 /* x_k of the last step, guess step or solve for pole k (Sec. 2 eq. W_k_def):
  * device [ncomp][ny][nx] complex128.  Synchronous. */
 int hp_get_solution(hp_plan plan, int pole, void* x);
@@ -289,7 +324,7 @@ int hp_apply_preconditioner_noalloc(hp_plan plan, int pole, const void* x, void*
  * milliseconds and summed algorithmic bytes since the last hp_profile call;
  * arrays have HP_K_COUNT entries (NULL to skip). */
 enum { HP_K_ROW_FWD = 0, HP_K_COL = 1, HP_K_ROW_APPLY = 2, HP_K_UPDATE = 3, HP_K_SMALL = 4,
-       HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_GUESS = 7, HP_K_COUNT = 8 };
+       HP_K_FINAL = 5, HP_K_RESIDUAL = 6, HP_K_GUESS = 7, HP_K_PML = 8, HP_K_COUNT = 9 };
 int hp_profile(hp_plan plan, int enable);
 int hp_profile_read(hp_plan plan, long* launches, double* ms, double* bytes);
 /* Time only every period-th launch of each timed class (period >= 1, counted

@@ -16,6 +16,7 @@
 #include "../../include/hp.h"
 #include "../../include/hp_unet.h"
 #include "kernels.hpp"
+#include "pml.hpp"
 
 // the learned guess needs the net's stream and channel counts (unet.hip)
 hipStream_t unet_stream(hp_unet n);
@@ -125,6 +126,15 @@ struct hp_plan_s {
   std::vector<double> lg_feat;  // per pole: asinh(Re b_k), asinh(Im b_k)
   double* n2copy = nullptr;    // the medium of the last hp_set_medium (the net's V plane reads it)
   void* scratch = nullptr;     // this device's address of the library's static scratch (no-alloc calls)
+  // absorbing layers (hp_set_pml): padded eigenvector matrices Q, Q^-1 [N][N], eigenvalues [N],
+  // the stretched stencil's node factors a2, a1 [N], one field per pole for the dense stages,
+  // and the partial inner products of the medium pass
+  bool pml = false;
+  double pml_sigma = 0.0;
+  char* pml_mem = nullptr;
+  c128 *pml_q = nullptr, *pml_qi = nullptr, *pml_lam = nullptr, *pml_a2 = nullptr, *pml_a1 = nullptr;
+  c128* pml_s = nullptr;
+  double2* pml_part = nullptr;
   std::string scratch_err;
   std::string err;
 };
@@ -397,6 +407,27 @@ void fold(hp_plan p, int k) {
   launch_mark_folded(p->st, k, 1, p->stream);
 }
 
+// Absorbing layers: z = sigma_m M_k^-1 u_m for the poles list[0..n) by the
+// eigen route of the Sylvester equation, Q [(Q^-1 u Q^-T) / (lam_p + lam_q - b_k)] Q^T,
+// in four dense stages through the pole's P field and its own scratch field.
+void pml_prec(hp_plan p, const PoleState* st, const int* list, int n, int* active_out, PmlRef in, PmlRef out,
+              c128* bufA, c128* bufB) {
+  const int N = p->d.nx;
+  const size_t fn = p->fieldn;
+  const PmlRef a{nullptr, bufA, fn, 0}, b{nullptr, bufB, fn, 0};
+  launch_pml_gemm(true, 0, p->pml_qi, in, a, st, list, n, active_out, p->pml_lam, N, p->stream);
+  launch_pml_gemm(false, 1, p->pml_qi, a, b, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  launch_pml_gemm(true, 0, p->pml_q, b, a, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  launch_pml_gemm(false, 2, p->pml_q, a, out, st, list, n, nullptr, p->pml_lam, N, p->stream);
+}
+
+// Floating-point operations of one pole's four dense stages: 8 n^3 per complex
+// product of n x n matrices, n = N - 1 unknowns per axis.
+double pml_flops(hp_plan p) {
+  const double n = p->d.nx - 1.0;
+  return 4.0 * 8.0 * n * n * n;
+}
+
 // Guess residuals for several poles at once: one buffer and one set of
 // partial sums per pole (allocated on first use, freed with the plan).
 int ensure_guess_buffers(hp_plan p, bool prev) {
@@ -422,8 +453,12 @@ int restart_from_residuals(hp_plan p, const std::vector<int>& rs, const std::vec
   const size_t ustride = (size_t)(p->d.restart + 1) * fn;
   {
     Prof pr(p, HP_K_ROW_FWD, nr * (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
-    launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
-                               p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
+    if (p->pml)
+      launch_pml_copy(p->guess_r, fn, rj.data(), reinterpret_cast<c128*>(p->U), ustride, rs.data(), nr,
+                      p->guess_rpart, rblk, (int)rblk, p->d.nx, p->stream);
+    else
+      launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
+                                 p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
   }
   bool changed = false;
   for (int k : rs) {
@@ -469,10 +504,19 @@ int check_poles(hp_plan p, const std::vector<int>& chk, const c128* w, int beta_
     launch_accum_batch<T>(p->X, fn, fld<T>(p->Z, 0, fn), (size_t)p->d.restart * fn, fn, p->st, chk.data(), n,
                           p->geo, p->stream);
     launch_mark_list(p->st, chk.data(), n, p->stream);  // X_k now holds the whole solution
-    launch_row_inv_batch<double>(p->X, fn, chk.data(), n, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
-                                 p->stream);
-    launch_apply_op_batch(p->guess_x, fn, w, p->guess_r, fn, p->coef, shifts.data(), n, p->sc, p->geo,
-                          p->guess_part, p->nopblk, p->stream);
+    if (p->pml) {
+      // X_k is physical already: gather the listed poles' accumulators
+      for (int a = 0; a < n; ++a)
+        HPCHK(hipMemcpyAsync(p->guess_x + (size_t)a * fn, p->X + (size_t)chk[a] * fn, fn * sizeof(c128),
+                             hipMemcpyDeviceToDevice, p->stream));
+      launch_pml_residual(p->guess_x, fn, w, p->guess_r, fn, p->coef, p->pml_a2, p->pml_a1, p->sc, shifts.data(), n,
+                          p->guess_part, p->nopblk, p->nopblk, p->d.nx, p->stream);
+    } else {
+      launch_row_inv_batch<double>(p->X, fn, chk.data(), n, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
+                                   p->stream);
+      launch_apply_op_batch(p->guess_x, fn, w, p->guess_r, fn, p->coef, shifts.data(), n, p->sc, p->geo,
+                            p->guess_part, p->nopblk, p->stream);
+    }
   }
   HPCHK(hipMemcpyAsync(p->guess_part_h, p->guess_part, (size_t)n * p->nopblk * sizeof(double),
                        hipMemcpyDeviceToHost, p->stream));
@@ -573,7 +617,13 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
   // shared first Krylov vector: S_x w (every pole's right-hand side is w)
   {
     Prof pr(p, HP_K_ROW_FWD, U1 * (16.0 + es));
-    launch_row_fwd<T, C>(w, bR, p->part_misc, twx, p->geo, p->stream);
+    if (p->pml) {
+      const int zero = 0;
+      launch_pml_copy(w, 0, &zero, reinterpret_cast<c128*>(bR), 0, &zero, 1, p->part_misc, 0, p->nrowblk * d.ncomp,
+                      d.nx, p->stream);
+    } else {
+      launch_row_fwd<T, C>(w, bR, p->part_misc, twx, p->geo, p->stream);
+    }
   }
   bool changed = false;
   for (int k : subset) {
@@ -636,7 +686,8 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       }
     }
     const double dup = shared > 0 ? shared - 1.0 : 0.0, dup0 = shared_m0 > 0 ? shared_m0 - 1.0 : 0.0;
-    prof_settle(p, HP_K_COL, f.pslot[0], U1 * es * (col - dup0));
+    // absorbing layers: the dense stages count floating-point operations
+    prof_settle(p, p->pml ? HP_K_PML : HP_K_COL, f.pslot[0], p->pml ? nw * pml_flops(p) : U1 * es * (col - dup0));
     prof_settle(p, HP_K_ROW_APPLY, f.pslot[1], nw ? U1 * es * (row - dup) + (U1 / d.ncomp) * 8.0 * planes : 0.0);
     prof_settle(p, HP_K_UPDATE, f.pslot[2], U1 * es * (upd - dup));
   };
@@ -683,22 +734,43 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       fl.ms[a] = mk_;
       fl.sh[a] = p->uptr_h[(size_t)poles[a] * (HP_MAXM + 1)] == (void*)bR;
     }
-    {
-      // the column pass takes the list in its arguments and stores it to ad
-      // for the kernels after it (no host-to-device copy per round)
-      Prof pr(p, HP_K_COL, -1.0, &fl.pslot[0]);
-      launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, poles.data(), na, ad, p->mu_x, p->mu_y, twy, p->geo,
-                       p->sc, p->stream);
-    }
-    {
-      Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
-      launch_row_apply<T, C>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<C>(p), p->st, ad, na, p->part_dots, twx,
-                             p->geo,
-                          p->sc, p->stream);
-    }
-    {
-      Prof pr(p, HP_K_SMALL, 0.0);
-      launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->reduce_done, p->stream);
+    if (p->pml) {
+      // absorbing layers: the dense stages (the first stores the list to ad),
+      // then p = A_k z - ~v_m with the inner products, on physical fields
+      c128* Zc = reinterpret_cast<c128*>(p->Z);
+      c128* Pc = reinterpret_cast<c128*>(p->P);
+      c128* const* uc = reinterpret_cast<c128* const*>(p->uptr);
+      {
+        Prof pr(p, HP_K_PML, -1.0, &fl.pslot[0]);
+        pml_prec(p, p->st, poles.data(), na, ad, PmlRef{uc, nullptr, 0, 0}, PmlRef{nullptr, Zc, zsp, zsi}, Pc,
+                 p->pml_s);
+      }
+      {
+        Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
+        launch_pml_apply(Zc, zsp, zsi, Pc, psp, uc, p->coef, p->pml_a2, p->pml_a1, p->sc, p->st, ad, na, p->pml_part,
+                         d.nx, p->stream);
+      }
+      {
+        Prof pr(p, HP_K_SMALL, 0.0);
+        launch_reduce_dots(p->pml_part, pml_apply_parts(d.nx), p->st, ad, na, maxm, p->reduce_done, p->stream);
+      }
+    } else {
+      {
+        // the column pass takes the list in its arguments and stores it to ad
+        // for the kernels after it (no host-to-device copy per round)
+        Prof pr(p, HP_K_COL, -1.0, &fl.pslot[0]);
+        launch_col<T, C>(up, Zb, zsp, zsi, DZb, dzsp, p->st, poles.data(), na, ad, p->mu_x, p->mu_y, twy, p->geo,
+                         p->sc, p->stream);
+      }
+      {
+        Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
+        launch_row_apply<T, C>(Zb, zsp, zsi, DZb, dzsp, Pb, psp, up, coef_as<C>(p), p->st, ad, na, p->part_dots,
+                               twx, p->geo, p->sc, p->stream);
+      }
+      {
+        Prof pr(p, HP_K_SMALL, 0.0);
+        launch_reduce_dots(p->part_dots, p->napplyblk, p->st, ad, na, maxm, p->reduce_done, p->stream);
+      }
     }
     {
       Prof pr(p, HP_K_UPDATE, -1.0, &fl.pslot[2]);
@@ -775,7 +847,9 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
         continue;
       }
       const bool fixed = !p->fixed.empty() && p->fixed[k] > 0;
-      if (fixed || (flag == 1 && !p->mixed)) {  // converged on the FP64 estimate
+      // converged on the FP64 estimate; with absorbing layers the eigen-route
+      // preconditioner's rounding (up to eps cond(Q)^2) lets the true residual decide
+      if (fixed || (flag == 1 && !p->mixed && !p->pml)) {
         p->relres[k] = -1.0;
         continue;
       }
@@ -838,9 +912,13 @@ int solve_and_sum(hp_plan p, const c128* w, c128* out, c128 phase, c128 rinf_pha
     double terms = 0.0;
     for (int k = 0; k < K; ++k) terms += p->m_h[k];
     Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
-    launch_final<T>(w, out, reinterpret_cast<cx<T>*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
-                    p->fieldn, p->st, K, phase, rinf_phase, loss_coef, d.edge_eta, d.edge_width, p->tw64_x, p->geo,
-                    p->stream);
+    if (p->pml)  // the layers absorb: no separate loss
+      launch_pml_final(w, out, reinterpret_cast<c128*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
+                       p->fieldn, p->st, K, phase, rinf_phase, d.nx, p->stream);
+    else
+      launch_final<T>(w, out, reinterpret_cast<cx<T>*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
+                      p->fieldn, p->st, K, phase, rinf_phase, loss_coef, d.edge_eta, d.edge_width, p->tw64_x,
+                      p->geo, p->stream);
   }
   if (p->guess_mode == HP_GUESS_PREV) {  // keep the solutions as the next step's guesses
     launch_accum_batch<T>(p->X, p->fieldn, fld<T>(p->Z, 0, p->fieldn), (size_t)d.restart * p->fieldn, p->fieldn,
@@ -986,7 +1064,11 @@ int run_solve(hp_plan p, int k, const c128* rhs, c128* x) {
   int rc = run_poles<T, C>(p, rhs, std::vector<int>{k}, &noconv);
   if (rc) return rc;
   fold<T>(p, k);
-  launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+  if (p->pml)
+    HPCHK(hipMemcpyAsync(x, p->X + (size_t)k * p->fieldn, p->fieldn * sizeof(c128), hipMemcpyDeviceToDevice,
+                         p->stream));
+  else
+    launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
   HPCHK(hipGetLastError());
   HPCHK(hipStreamSynchronize(p->stream));
   return noconv ? HP_WARN_NOCONV : HP_OK;
@@ -996,7 +1078,11 @@ int run_solve(hp_plan p, int k, const c128* rhs, c128* x) {
 template <typename T>
 int get_solution(hp_plan p, int k, c128* x) {
   fold<T>(p, k);
-  launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
+  if (p->pml)
+    HPCHK(hipMemcpyAsync(x, p->X + (size_t)k * p->fieldn, p->fieldn * sizeof(c128), hipMemcpyDeviceToDevice,
+                         p->stream));
+  else
+    launch_row_inv<double>(p->X + (size_t)k * p->fieldn, x, p->tw64_x, p->geo, tile_width<T>(), p->stream);
   HPCHK(hipGetLastError());
   HPCHK(hipStreamSynchronize(p->stream));
   return HP_OK;
@@ -1011,8 +1097,16 @@ int apply_prec(hp_plan p, int pole, const c128* x, c128* y) {
   void* tbl[HP_MAXM + 1] = {nullptr};
   tbl[0] = p->tmpR;
   const int zero = 0;
+  if (p->pml) tbl[0] = const_cast<c128*>(x);
   HPCHK(hipMemcpyAsync(p->st_scratch, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
   HPCHK(hipMemcpyAsync(p->uptr_scratch, tbl, sizeof(tbl), hipMemcpyHostToDevice, p->stream));
+  if (p->pml) {
+    pml_prec(p, p->st_scratch, &zero, 1, nullptr, PmlRef{reinterpret_cast<c128* const*>(p->uptr_scratch), nullptr, 0, 0},
+             PmlRef{nullptr, y, 0, 0}, reinterpret_cast<c128*>(p->P), p->pml_s);
+    HPCHK(hipGetLastError());
+    HPCHK(hipStreamSynchronize(p->stream));
+    return HP_OK;
+  }
   launch_row_fwd<T, C>(x, reinterpret_cast<cx<T>*>(p->tmpR), p->part_misc, reinterpret_cast<const cx<C>*>(p->tw_x),
                     p->geo, p->stream);
   // the first basis slot of pole 0 in Z serves as output; the DZ slot as scratch
@@ -1196,6 +1290,7 @@ int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* con
   }
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium: pass n2 or call hp_set_medium first");
   if (p->form != HP_FORM_EXP) return fail(p, HP_ESTATE, "initial guesses apply to the exponential form only");
+  if (p->pml && x0) return fail(p, HP_ESTATE, "guesses are not available with absorbing layers");
   const c128* w = reinterpret_cast<const c128*>(E_in);
   c128* out = reinterpret_cast<c128*>(E_out);
   std::vector<const c128*> g(p->d.npoles, nullptr);
@@ -1263,6 +1358,7 @@ int hp_set_guess(hp_plan p, int mode) {
     return fail(p, HP_EINVAL, "unknown guess mode");
   if (mode == HP_GUESS_LEARNED && !p->net)
     return fail(p, HP_ESTATE, "HP_GUESS_LEARNED needs a net: call hp_set_guess_net first");
+  if (mode != HP_GUESS_ZERO && p->pml) return fail(p, HP_ESTATE, "guesses are not available with absorbing layers");
   p->guess_mode = mode;
   p->prev_valid = false;
   return HP_OK;
@@ -1319,6 +1415,7 @@ int hp_set_guess_net(hp_plan p, hp_unet net, int chunk) {
 int hp_set_form(hp_plan p, int form, int substeps) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
   if (form != HP_FORM_EXP && form != HP_FORM_SQRT) return fail(p, HP_EINVAL, "unknown form");
+  if (form != HP_FORM_EXP && p->pml) return fail(p, HP_ESTATE, "absorbing layers apply to the exponential form only");
   if (form == HP_FORM_EXP) {
     p->form = form;
     p->substeps = 1;
@@ -1349,6 +1446,155 @@ int hp_set_form(hp_plan p, int form, int substeps) {
     gmax = std::max(gmax, std::abs(1.0 + z * (1.0 + z * (0.5 + z * (1.0 / 6.0 + z / 24.0)))));
   }
   return gmax > 1.0 + 1e-6 ? HP_WARN_UNSTABLE : HP_OK;
+}
+
+static void free_pml(hp_plan p) {
+  if (p->pml_mem) (void)hipFree(p->pml_mem);
+  p->pml_mem = nullptr;
+  p->pml_q = p->pml_qi = p->pml_lam = p->pml_a2 = p->pml_a1 = p->pml_s = nullptr;
+  p->pml_part = nullptr;
+  p->pml = false;
+  p->pml_sigma = 0.0;
+}
+
+int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, const void* lam) {
+  if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
+  HPCHK(hipStreamSynchronize(p->stream));
+  if (sigma_max == 0.0 && !Q && !Qinv && !lam) {
+    free_pml(p);
+    return HP_OK;
+  }
+  const hp_plan_desc& d = p->d;
+  if (d.ncomp != 1 || d.nx != d.ny || d.dx != d.dy)
+    return fail(p, HP_EINVAL, "absorbing layers need a scalar plan (ncomp = 1) on a square grid (nx = ny, dx = dy)");
+  if (d.precision != HP_FP64) return fail(p, HP_EINVAL, "absorbing layers need precision HP_FP64");
+  if (!(sigma_max > 0.0) || !std::isfinite(sigma_max)) return fail(p, HP_EINVAL, "sigma_max must be finite and > 0");
+  if (!Q || !Qinv || !lam) return fail(p, HP_EINVAL, "Q, Qinv, lam must all be given");
+  if (p->form != HP_FORM_EXP) return fail(p, HP_ESTATE, "absorbing layers apply to the exponential form only");
+  if (p->guess_mode != HP_GUESS_ZERO) return fail(p, HP_ESTATE, "absorbing layers need the guess mode HP_GUESS_ZERO");
+  using cd = std::complex<double>;
+  const int N = d.nx, n = N - 1, W = d.edge_width;
+  const cd* q = reinterpret_cast<const cd*>(Q);
+  const cd* qi = reinterpret_cast<const cd*>(Qinv);
+  const cd* l = reinterpret_cast<const cd*>(lam);
+  for (size_t i = 0; i < (size_t)n * n; ++i)
+    if (!std::isfinite(q[i].real()) || !std::isfinite(q[i].imag()) || !std::isfinite(qi[i].real()) ||
+        !std::isfinite(qi[i].imag()))
+      return fail(p, HP_EINVAL, "Q or Qinv holds a NaN or Inf");
+  // the stretch g = 1 + i sigma, sigma = sigma_max ((W + 1 - d)/W)^2 at distance d in [1, W] cells from
+  // the nearer Dirichlet node, and its derivative along the axis
+  const double h = d.dx, sc = 1.0 / ((d.k0 * d.n0) * (d.k0 * d.n0));
+  std::vector<c128> a2(N), a1(N);
+  std::vector<cd> a2c(N), a1c(N);
+  for (int j = 0; j < N; ++j) {
+    const int dist = std::min(j, N - j);
+    const double t = (dist >= 1 && dist <= W) ? (W + 1.0 - dist) / W : 0.0;
+    const double dsdd = -2.0 * sigma_max * t / W;  // d sigma / d(distance), per cell
+    const double dsdx = (j <= N - j ? dsdd : -dsdd) / h;
+    const cd g(1.0, sigma_max * t * t), gp(0.0, dsdx);
+    a2c[j] = 1.0 / (g * g);
+    a1c[j] = sc * gp / (g * g * g);
+    a2[j] = mk(a2c[j].real(), a2c[j].imag());
+    a1[j] = mk(a1c[j].real(), a1c[j].imag());
+  }
+  // the tables must decompose this library's stretched operator: compare
+  // Q (lam .* (Q^-1 x)) with s D~ x for two pseudo-random x
+  {
+    uint64_t rs = 0x9E3779B97F4A7C15ull;
+    auto rnd = [&]() {
+      rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+      return (double)(rs >> 11) / 9007199254740992.0 - 0.5;
+    };
+    for (int probe = 0; probe < 2; ++probe) {
+      std::vector<cd> x(n), t(n), ye(n, 0.0), yd(n);
+      for (int j = 0; j < n; ++j) x[j] = cd(rnd(), rnd());
+      for (int r = 0; r < n; ++r) {
+        cd acc = 0.0;
+        for (int c = 0; c < n; ++c) acc += qi[(size_t)r * n + c] * x[c];
+        t[r] = l[r] * acc;
+      }
+      for (int r = 0; r < n; ++r) {
+        cd acc = 0.0;
+        for (int c = 0; c < n; ++c) acc += q[(size_t)r * n + c] * t[c];
+        ye[r] = acc;
+      }
+      auto at = [&](int k) -> cd {
+        double sg = 1.0;
+        if (k < 0) {
+          k = -k;
+          sg = -1.0;
+        } else if (k > N) {
+          k = 2 * N - k;
+          sg = -1.0;
+        }
+        if (k == 0 || k == N) return 0.0;
+        return sg * x[k - 1];
+      };
+      double num = 0.0, den = 0.0;
+      for (int j = 1; j < N; ++j) {
+        cd s2 = p->sc.c2x[0] * x[j - 1], s1 = 0.0;
+        for (int mm = 1; mm <= 6; ++mm) {
+          s2 += p->sc.c2x[mm] * (at(j + mm) + at(j - mm));
+          s1 += p->sc.d1x[mm - 1] * (at(j + mm) - at(j - mm));
+        }
+        yd[j - 1] = a2c[j] * s2 - a1c[j] * s1;
+        num += std::norm(yd[j - 1] - ye[j - 1]);
+        den += std::norm(yd[j - 1]);
+      }
+      if (!(num <= 1e-12 * den))
+        return fail(p, HP_EINVAL,
+                    "Q diag(lam) Q^-1 does not reproduce the stretched operator s D~ of this plan (relative error " +
+                        std::to_string(std::sqrt(num / den)) + ")");
+    }
+  }
+  for (int k = 0; k < d.npoles; ++k) {
+    const cd b(p->poles[k].re, p->poles[k].im);
+    double mn = 1e300;
+    for (int a = 0; a < n; ++a)
+      for (int c = 0; c < n; ++c) mn = std::min(mn, std::abs(l[a] + l[c] - b));
+    if (!(mn > 1e-12 * (1.0 + std::abs(b))))
+      return fail(p, HP_EINVAL, "pole " + std::to_string(k) + " lies on the stretched free-space spectrum");
+  }
+  const size_t NN = (size_t)N * N, fn = p->fieldn, K = (size_t)d.npoles;
+  const size_t nparts = (size_t)pml_apply_parts(N);
+  if (!p->pml_mem) {
+    const size_t bytes = (2 * NN + 3 * (size_t)N + K * fn) * sizeof(c128) + K * (HP_MAXM + 1) * 2 * nparts * sizeof(double2);
+    hipError_t e = hipMalloc(&p->pml_mem, bytes);
+    if (e != hipSuccess) {
+      p->pml_mem = nullptr;
+      return fail(p, HP_ENOMEM, std::string("absorbing-layer tables: ") + hipGetErrorString(e));
+    }
+    c128* c = reinterpret_cast<c128*>(p->pml_mem);
+    p->pml_q = c;
+    p->pml_qi = c + NN;
+    p->pml_lam = c + 2 * NN;
+    p->pml_a2 = p->pml_lam + N;
+    p->pml_a1 = p->pml_a2 + N;
+    p->pml_s = p->pml_a1 + N;
+    p->pml_part = reinterpret_cast<double2*>(p->pml_s + K * fn);
+  }
+  // padded to N x N: row and column 0 zero
+  std::vector<c128> pad(NN, mk(0.0, 0.0));
+  for (int src = 0; src < 2; ++src) {
+    const cd* m = src ? qi : q;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        const cd v = m[(size_t)r * n + c];
+        pad[(size_t)(r + 1) * N + c + 1] = mk(v.real(), v.imag());
+      }
+    HPCHK(hipMemcpy(src ? p->pml_qi : p->pml_q, pad.data(), NN * sizeof(c128), hipMemcpyHostToDevice));
+  }
+  std::vector<c128> lp(N, mk(0.0, 0.0));
+  for (int r = 0; r < n; ++r) lp[r + 1] = mk(l[r].real(), l[r].imag());
+  HPCHK(hipMemcpy(p->pml_lam, lp.data(), N * sizeof(c128), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->pml_a2, a2.data(), N * sizeof(c128), hipMemcpyHostToDevice));
+  HPCHK(hipMemcpy(p->pml_a1, a1.data(), N * sizeof(c128), hipMemcpyHostToDevice));
+  // the medium-pass slots and the dense stages' scratch start from zero (rows 0 and columns 0 stay so)
+  HPCHK(hipMemset(p->pml_s, 0, K * fn * sizeof(c128)));
+  p->pml = true;
+  p->pml_sigma = sigma_max;
+  p->prev_valid = false;
+  return HP_OK;
 }
 
 int hp_get_solution(hp_plan p, int pole, void* x) {
@@ -1434,8 +1680,12 @@ int hp_apply_operator(hp_plan p, int pole, const void* x, void* y) {
   if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
   const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
-  launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, b, p->sc, p->geo,
-                  nullptr, p->stream);
+  if (p->pml)
+    launch_pml_residual(reinterpret_cast<const c128*>(x), 0, nullptr, reinterpret_cast<c128*>(y), 0, p->coef,
+                        p->pml_a2, p->pml_a1, p->sc, &b, 1, nullptr, 0, p->nopblk, p->d.nx, p->stream);
+  else
+    launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, b, p->sc, p->geo,
+                    nullptr, p->stream);
   HPCHK(hipGetLastError());
   return HP_OK;
 }
@@ -1523,6 +1773,7 @@ void hp_plan_destroy(hp_plan p) {
   if (p->guess_part_h) (void)hipHostFree(p->guess_part_h);
   if (p->rk) (void)hipFree(p->rk);
   free_guess_net(p);
+  free_pml(p);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -1783,6 +2034,7 @@ int hp_apply_preconditioner_noalloc(hp_plan p, int pole, const void* x, void* y)
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
   if (!x || !y || x == y) return fail(p, HP_EINVAL, "x, y must be distinct device buffers");
   if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
+  if (p->pml) return fail(p, HP_ESTATE, "no allocation-free form of the absorbing-layer preconditioner");
   const size_t es = p->mixed ? sizeof(c64) : sizeof(c128);
   const size_t need = (p->d.ncomp == 2 ? 3 : 2) * align256(p->fieldn * es);
   const size_t part = (size_t)p->nrowblk * p->d.ncomp * sizeof(double);

@@ -1,0 +1,370 @@
+// Kernels of the absorbing-layer form of the step (Sec. 4.1, Sec. 4.2):
+// the dense stages of the eigen-route Sylvester solve, the stretched explicit
+// operator (for the Arnoldi step with its inner products, and for true
+// residuals), copies and the residue-weighted sum.  FP64 throughout.
+#include "pml.hpp"
+
+namespace {
+
+__device__ __forceinline__ double pml_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over a 256-thread workgroup in a fixed order; valid in thread 0.
+__device__ __forceinline__ double pml_block_sum(double v, double* red) {
+  v = pml_wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return threadIdx.x == 0 ? (red[0] + red[1]) + (red[2] + red[3]) : 0.0;
+}
+
+__device__ __forceinline__ const c128* pml_field(const PmlRef& r, int k, int m) {
+  return r.tbl ? r.tbl[(size_t)k * (HP_MAXM + 1) + m] : r.base + (size_t)k * r.sp + (size_t)m * r.si;
+}
+
+// ------------------------------------------------------------------ dense stages
+
+// Complex FP64 products on the vector ALU: on this chip the FP64 rate of the
+// vector units equals that of the matrix cores, and the complex product needs
+// no operand splitting there.  64 x 64 output tile per 256-thread workgroup,
+// 4 x 4 outputs per thread (rows ty + 16 i, columns tx + 16 j), K in steps of
+// 16 staged through LDS with the next step's global loads in flight during
+// the current step's products.
+constexpr int GT = 64, GK = 16, GWG = 256;
+
+template <bool LEFT, int EPI>
+__global__ __launch_bounds__(GWG) void k_pml_gemm(const c128* __restrict__ mat, PmlRef in, PmlRef out,
+                                                  const PoleState* __restrict__ st, PoleList list,
+                                                  int* __restrict__ active_out, const c128* __restrict__ lam, int N) {
+  const int k = list.k[blockIdx.z];
+  if (active_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[blockIdx.z] = k;
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  const c128* __restrict__ X = pml_field(in, k, m);
+  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m));
+  const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  // A[r][j] = Mat[r][j] (left) or X[r][j] (right); B[j][c] = X[j][c] (left) or Mat[c][j] (right)
+  const c128* __restrict__ Ag = LEFT ? mat : X;
+  const c128* __restrict__ Bg = LEFT ? X : mat;
+  __shared__ c128 As[GK][GT + 1];
+  __shared__ c128 Bs[GK][GT + 1];
+  c128 ra[4], rb[4];
+  auto fetch = [&](int j0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + GWG * q;
+      ra[q] = Ag[(size_t)(r0 + (e >> 4)) * N + j0 + (e & 15)];
+      if (LEFT)
+        rb[q] = Bg[(size_t)(j0 + (e >> 6)) * N + c0 + (e & 63)];
+      else
+        rb[q] = Bg[(size_t)(c0 + (e >> 4)) * N + j0 + (e & 15)];
+    }
+  };
+  c128 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
+  fetch(0);
+  for (int j0 = 0; j0 < N; j0 += GK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + GWG * q;
+      As[e & 15][e >> 4] = ra[q];
+      if (LEFT)
+        Bs[e >> 6][e & 63] = rb[q];
+      else
+        Bs[e & 15][e >> 4] = rb[q];
+    }
+    __syncthreads();
+    if (j0 + GK < N) fetch(j0 + GK);
+#pragma unroll 4
+    for (int kk = 0; kk < GK; ++kk) {
+      c128 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j].re = fma(a[i].re, b[j].re, fma(-a[i].im, b[j].im, acc[i][j].re));
+          acc[i][j].im = fma(a[i].re, b[j].im, fma(a[i].im, b[j].re, acc[i][j].im));
+        }
+    }
+    __syncthreads();
+  }
+  const c128 bk = st[k].bk;
+  const double sg = st[k].sigma[m];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + ty + 16 * i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tx + 16 * j;
+      c128 v = acc[i][j];
+      if (EPI == 1) v = (r == 0 || c == 0) ? mk(0.0, 0.0) : cdiv(v, lam[r] + lam[c] - bk);
+      if (EPI == 2) v = sg * v;
+      Y[(size_t)r * N + c] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ stretched explicit operator
+
+// x at node (i, j) with odd reflection about the Dirichlet nodes 0 and N
+__device__ __forceinline__ c128 pml_ld(const c128* __restrict__ x, int i, int j, int N) {
+  double sg = 1.0;
+  if (i < 0) {
+    i = -i;
+    sg = -sg;
+  } else if (i > N) {
+    i = 2 * N - i;
+    sg = -sg;
+  }
+  if (j < 0) {
+    j = -j;
+    sg = -sg;
+  } else if (j > N) {
+    j = 2 * N - j;
+    sg = -sg;
+  }
+  if (i == 0 || j == 0 || i == N || j == N) return mk(0.0, 0.0);
+  return sg * x[(size_t)i * N + j];
+}
+
+// (Zbar~ - b I) x at interior node (i, j): the stretched stencils along both
+// axes plus (V - b) x
+__device__ __forceinline__ c128 pml_op(const c128* __restrict__ x, int i, int j, int N, const double* __restrict__ V,
+                                       const c128* __restrict__ a2, const c128* __restrict__ a1, const StencilCoef& sc,
+                                       c128 b) {
+  const size_t idx = (size_t)i * N + j;
+  const c128 ctr = x[idx];
+  c128 sxx = sc.c2x[0] * ctr, syy = sc.c2x[0] * ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
+#pragma unroll
+  for (int mm = 1; mm <= 6; ++mm) {
+    const c128 xp = pml_ld(x, i, j + mm, N), xm = pml_ld(x, i, j - mm, N);
+    const c128 yp = pml_ld(x, i + mm, j, N), ym = pml_ld(x, i - mm, j, N);
+    sxx = sxx + sc.c2x[mm] * (xp + xm);
+    sx1 = sx1 + sc.d1x[mm - 1] * (xp - xm);
+    syy = syy + sc.c2x[mm] * (yp + ym);
+    sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
+  }
+  return (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1) + (V[idx] * ctr - b * ctr);
+}
+
+__global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x, size_t xbs,
+                                                      const c128* __restrict__ rhs, c128* __restrict__ y, size_t ybs,
+                                                      const double* __restrict__ V, const c128* __restrict__ a2,
+                                                      const c128* __restrict__ a1, StencilCoef sc, ShiftList sh,
+                                                      double* __restrict__ part, size_t pbs, int N) {
+  __shared__ double red[4];
+  const int z = blockIdx.z;
+  x += (size_t)z * xbs;
+  y += (size_t)z * ybs;
+  const c128 b = sh.b[z];
+  const size_t fsz = (size_t)N * N;
+  double nrm = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    c128 v = mk(0.0, 0.0);
+    if (i > 0 && j > 0) {
+      const c128 ax = pml_op(x, i, j, N, V, a2, a1, sc, b);
+      v = rhs ? rhs[idx] - ax : ax;
+    }
+    y[idx] = v;
+    nrm += abs2(v);
+  }
+  const double s = pml_block_sum(nrm, red);
+  if (threadIdx.x == 0 && part) part[(size_t)z * pbs + blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------------ operator pass and inner products
+
+// p = A_k z_m - sigma_m u_m with A_k applied by the explicit stretched stencil:
+// then A_k z_m = ~v_m + p holds for the z_m actually stored, whatever the
+// rounding of the dense stages (the eigenvector matrices of the stretched
+// operator are far from unitary), so the Arnoldi relation of the stored Z is
+// exact up to the rounding of p itself.
+
+constexpr int AP_E = 4;  // elements per thread
+
+__global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbase, size_t zsp, size_t zsi,
+                                                   c128* __restrict__ pbase, size_t psp, c128* const* __restrict__ uptr,
+                                                   const double* __restrict__ V, const c128* __restrict__ a2,
+                                                   const c128* __restrict__ a1, StencilCoef sc,
+                                                   const PoleState* __restrict__ st, const int* __restrict__ active,
+                                                   double2* __restrict__ part, int nparts, int N) {
+  const int k = active[blockIdx.y];
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  const size_t fsz = (size_t)N * N;
+  const c128 bk = st[k].bk;
+  const double sg = st[k].sigma[m];
+  const c128* z = zbase + (size_t)k * zsp + (size_t)m * zsi;
+  c128* p = pbase + (size_t)k * psp;
+  const c128* const* up = uptr + (size_t)k * (HP_MAXM + 1);
+  const size_t base = (size_t)blockIdx.x * 256 * AP_E + threadIdx.x;
+  c128 pv[AP_E], um[AP_E];
+  {
+    const c128* u = up[m];
+#pragma unroll
+    for (int e = 0; e < AP_E; ++e) {
+      const size_t idx = base + (size_t)e * 256;
+      pv[e] = mk(0.0, 0.0);
+      um[e] = mk(0.0, 0.0);
+      if (idx < fsz) {
+        const int i = (int)(idx / N), j = (int)(idx % N);
+        um[e] = u[idx];
+        if (i > 0 && j > 0) pv[e] = pml_op(z, i, j, N, V, a2, a1, sc, bk) - sg * um[e];
+        p[idx] = pv[e];
+      }
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = blockIdx.x * 4 + wave;
+  for (int i = 0; i <= m; ++i) {
+    const c128* u = up[i];
+    double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll
+    for (int e = 0; e < AP_E; ++e) {
+      const size_t idx = base + (size_t)e * 256;
+      const c128 a = (i == m) ? um[e] : (idx < fsz ? u[idx] : mk(0.0, 0.0));
+      pr += a.re * pv[e].re + a.im * pv[e].im;
+      pi += a.re * pv[e].im - a.im * pv[e].re;
+      qr += a.re * um[e].re + a.im * um[e].im;
+      qi += a.re * um[e].im - a.im * um[e].re;
+    }
+    pr = pml_wave_sum(pr);
+    pi = pml_wave_sum(pi);
+    qr = pml_wave_sum(qr);
+    qi = pml_wave_sum(qi);
+    if (lane == 0) {
+      const size_t b = (((size_t)k * (HP_MAXM + 1) + i) * 2) * nparts + slot;
+      part[b] = make_double2(pr, pi);
+      part[b + nparts] = make_double2(qr, qi);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ copies and the sum
+
+__global__ __launch_bounds__(256) void k_pml_copy(const c128* __restrict__ src, size_t sbs, PoleList isel,
+                                                  c128* __restrict__ dst, size_t dbs, PoleList osel,
+                                                  double* __restrict__ part, size_t part_bs, int N) {
+  __shared__ double red[4];
+  const int z = blockIdx.z;
+  src += (size_t)isel.k[z] * sbs;
+  dst += (size_t)osel.k[z] * dbs;
+  const size_t fsz = (size_t)N * N;
+  double nrm = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    const c128 v = (i > 0 && j > 0) ? src[idx] : mk(0.0, 0.0);
+    dst[idx] = v;
+    nrm += abs2(v);
+  }
+  const double s = pml_block_sum(nrm, red);
+  if (threadIdx.x == 0) part[(size_t)z * part_bs + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_pml_final(const c128* __restrict__ w, c128* __restrict__ out,
+                                                   const c128* __restrict__ zbase, size_t zsp, size_t zsi,
+                                                   const c128* __restrict__ xacc, size_t xsp,
+                                                   const PoleState* __restrict__ st, int npoles, c128 phase,
+                                                   c128 rinf_phase, int N) {
+  const size_t fsz = (size_t)N * N;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    c128 v = mk(0.0, 0.0);
+    if (i > 0 && j > 0) {
+      c128 acc = mk(0.0, 0.0);
+      for (int k = 0; k < npoles; ++k) {
+        const c128 ak = st[k].ak;
+        if (st[k].has_x) acc = acc + ak * xacc[(size_t)k * xsp + idx];
+        const int mk_ = st[k].m;
+        const c128* zk = zbase + (size_t)k * zsp + idx;
+        for (int q = 0; q < mk_; ++q) acc = acc + (ak * st[k].y[q]) * zk[(size_t)q * zsi];
+      }
+      v = phase * acc + rinf_phase * w[idx];
+    }
+    out[idx] = v;
+  }
+}
+
+PoleList make_list(const int* sel, int n) {
+  PoleList l;
+  l.n = n;
+  for (int a = 0; a < HP_MAXPOLES; ++a) l.k[a] = a < n ? sel[a] : 0;
+  return l;
+}
+
+int flat_blocks(size_t n) {
+  size_t b = (n + 1023) / 1024;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace
+
+void launch_pml_gemm(bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out, const PoleState* st,
+                     const int* list, int n, int* active_out, const c128* lam, int N, hipStream_t s) {
+  const PoleList l = make_list(list, n);
+  const dim3 grid(N / GT, N / GT, n);
+#define G_(L, E) \
+  hipLaunchKernelGGL((k_pml_gemm<L, E>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, N)
+  if (left) {
+    if (epilogue == 1)
+      G_(true, 1);
+    else if (epilogue == 2)
+      G_(true, 2);
+    else
+      G_(true, 0);
+  } else {
+    if (epilogue == 1)
+      G_(false, 1);
+    else if (epilogue == 2)
+      G_(false, 2);
+    else
+      G_(false, 0);
+  }
+#undef G_
+}
+
+int pml_apply_parts(int N) {
+  const size_t fsz = (size_t)N * N;
+  return (int)((fsz + 256 * AP_E - 1) / (256 * AP_E)) * 4;
+}
+
+void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, size_t psp, c128* const* uptr,
+                      const double* V, const c128* a2, const c128* a1, const StencilCoef& sc, const PoleState* st,
+                      const int* active, int nactive, double2* part, int N, hipStream_t s) {
+  const int nparts = pml_apply_parts(N);
+  hipLaunchKernelGGL(k_pml_apply, dim3(nparts / 4, nactive), dim3(256), 0, s, zbase, zsp, zsi, pbase, psp, uptr, V,
+                     a2, a1, sc, st, active, part, nparts, N);
+}
+
+void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* V,
+                         const c128* a2, const c128* a1, const StencilCoef& sc, const c128* shifts, int n,
+                         double* part, size_t pbs, int nblk, int N, hipStream_t s) {
+  ShiftList sh;
+  for (int a = 0; a < HP_MAXPOLES; ++a) sh.b[a] = a < n ? shifts[a] : mk(0.0, 0.0);
+  hipLaunchKernelGGL(k_pml_residual, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, V, a2, a1, sc, sh,
+                     part, pbs, N);
+}
+
+void launch_pml_copy(const c128* src, size_t sbs, const int* isel, c128* dst, size_t dbs, const int* osel, int n,
+                     double* part, size_t part_bs, int nblk, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_pml_copy, dim3(nblk, 1, n), dim3(256), 0, s, src, sbs, make_list(isel, n), dst, dbs,
+                     make_list(osel, n), part, part_bs, N);
+}
+
+void launch_pml_final(const c128* w, c128* out, const c128* zbase, size_t zsp, size_t zsi, const c128* xacc,
+                      size_t xsp, const PoleState* st, int npoles, c128 phase, c128 rinf_phase, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_pml_final, dim3(flat_blocks((size_t)N * N)), dim3(256), 0, s, w, out, zbase, zsp, zsi, xacc,
+                     xsp, st, npoles, phase, rinf_phase, N);
+}

@@ -22,13 +22,13 @@ HP_GUESS_ZERO, HP_GUESS_PREV, HP_GUESS_LEARNED = 0, 1, 2
 HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_set_pml", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_apply_preconditioner_noalloc",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_profile_totals", "hp_last_error",
            "hp_plan_destroy",
            "hp_batch_create", "hp_batch_propagate", "hp_batch_stats", "hp_batch_destroy")
-KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual", "guess")
+KERNEL_CLASSES = ("row_fwd", "col", "row_apply", "update", "small", "final", "residual", "guess", "pml_gemm")
 
 
 class hp_c128(C.Structure):
@@ -68,6 +68,7 @@ def lib():
         L.hp_autotune.argtypes = [vp, vp, vp, C.c_int, vp, ip]
         L.hp_set_launch.argtypes = [vp, C.c_int]
         L.hp_batch_set_launch.argtypes = [vp, ip]
+        L.hp_set_pml.argtypes = [vp, C.c_double, vp, vp, vp]
         L.hp_get_solution.argtypes = [vp, C.c_int, vp]
         L.hp_apply_medium.argtypes = [vp, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
@@ -211,6 +212,16 @@ class Plan:
         """HP_FORM_EXP or HP_FORM_SQRT (pseudo-differential form, `substeps` RK4 substeps per
         step); returns HP_OK or HP_WARN_UNSTABLE."""
         return self._check(self.L.hp_set_form(self.handle, int(form), int(substeps)), "hp_set_form")
+
+    def set_pml(self, sigma_max, Q=None, Qinv=None, lam=None):
+        """Absorbing layers on the plan's edge_width cells (hp_set_pml): Q, Qinv (N-1, N-1) and lam
+        (N-1,) the eigen-decomposition of the one-axis stretched operator (tables.pml_eigen); all
+        None with sigma_max = 0 removes them."""
+        if Q is None:
+            return self._check(self.L.hp_set_pml(self.handle, float(sigma_max), None, None, None), "hp_set_pml")
+        arrs = [np.ascontiguousarray(a, dtype=np.complex128) for a in (Q, Qinv, lam)]
+        return self._check(self.L.hp_set_pml(self.handle, float(sigma_max), *(a.ctypes.data for a in arrs)),
+                           "hp_set_pml")
 
     def solution(self, pole, x=None):
         import torch

@@ -181,6 +181,44 @@ def plan_tables(K: float, npoles: int):
     return f.poles, f.residues, f.r_inf, stencil_d2(), stencil_d1()
 
 
+def pml_stretched_d2(N: int, h: float, k0: float, n0: float, W: int, sigma_max: float, d2=None, d1=None):
+    """s D~: the one-axis stretched second derivative of the absorbing layers (Sec. 4.1) on the
+    unknowns 1..N-1, as a dense (N-1, N-1) complex matrix, s = 1/(k0 n0)^2.
+
+    The stretch is g = 1 + i sigma with sigma = sigma_max ((W + 1 - d)/W)^2 at distance d in
+    [1, W] cells from the nearer Dirichlet node (0 beyond), and d^2/dx~^2 = (1/g^2) D2 - (g'/g^3) D1
+    with the 13-point stencils (odd reflection about the Dirichlet nodes 0 and N)."""
+    c = np.asarray(stencil_d2() if d2 is None else d2, float)
+    dd = np.asarray(stencil_d1() if d1 is None else d1, float)
+    n = N - 1
+    nodes = np.arange(1, N)
+    C2 = np.zeros((n, n))
+    C1 = np.zeros((n, n))
+    for m in range(-6, 7):
+        tgt = nodes + m
+        sign = np.where((tgt < 0) | (tgt > N), -1.0, 1.0)
+        tgt = np.where(tgt < 0, -tgt, np.where(tgt > N, 2 * N - tgt, tgt))
+        keep = (tgt >= 1) & (tgt <= N - 1)
+        rows, cols = nodes[keep] - 1, tgt[keep] - 1
+        np.add.at(C2, (rows, cols), sign[keep] * c[abs(m)])
+        if m:
+            np.add.at(C1, (rows, cols), sign[keep] * np.sign(m) * dd[abs(m) - 1])
+    dist = np.minimum(nodes, N - nodes)
+    t = np.where(dist <= W, (W + 1.0 - dist) / W, 0.0)
+    g = 1.0 + 1j * sigma_max * t ** 2
+    dsig = -2.0 * sigma_max * t / W / h            # d sigma/d(distance) per unit length
+    gp = 1j * np.where(nodes <= N - nodes, dsig, -dsig)
+    s = 1.0 / (k0 * n0) ** 2
+    return s * ((1.0 / g ** 2)[:, None] * (C2 / h ** 2) - (gp / g ** 3)[:, None] * (C1 / h))
+
+
+def pml_eigen(N: int, h: float, k0: float, n0: float, W: int, sigma_max: float, d2=None, d1=None):
+    """(Q, Qinv, lam) with s D~ = Q diag(lam) Qinv (pml_stretched_d2), the tables hp_set_pml takes."""
+    A = pml_stretched_d2(N, h, k0, n0, W, sigma_max, d2, d1)
+    lam, Q = np.linalg.eig(A)
+    return Q, np.linalg.inv(Q), lam
+
+
 def cauchy_sqrt_table(N: int, alpha: float = 1.0):
     """(poles, residues, r_inf) of sqrt(1+z) ~ r_inf + sum_j a_j/(z - b_j) from the Cauchy
     integral over the cut w in [-1, 1] of the Moebius variable w = (z+1+i alpha)/(z+1-i alpha),

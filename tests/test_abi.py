@@ -104,6 +104,7 @@ def test_null_arguments():
     assert L.hp_profile_sample(None, 1) == -1
     assert L.hp_profile_read(None, None, None, None) == -1
     assert L.hp_profile_totals(None, None, None) == -1
+    assert L.hp_set_pml(None, 1.0, None, None, None) == -1
     assert b"NULL" in L.hp_last_error(None)
     L.hp_plan_destroy(None)
 

@@ -1,0 +1,178 @@
+"""Parity of the absorbing-layer form (hp_set_pml) against the oracle's PML (oracle/pml.py).
+
+Both sides stretch the transverse derivatives by g = 1 + i sigma (Sec. 4.1) and precondition
+each pole by the Sylvester equation of eq. fs_sylvester with the stretched matrices; the oracle
+solves it by Bartels-Stewart, the library by the eigen-decomposition of the one-axis operator
+(tables.pml_eigen).  Tolerances:
+  operator: 1e-13 relative (the same stencil arithmetic in another order);
+  preconditioner: 20 eps n cond(Q)^2 (the eigenvector matrices are far from unitary: each of the
+      four dense products can amplify rounding by cond(Q));
+  a step with the oracle's iteration counts replayed: 1e-9 (the two preconditioners agree to the
+      bound above, and the Arnoldi step applies the explicit operator to the stored z, so both
+      sides run the same GMRES up to that difference);
+  a step on the library's own stopping test: every solve's FP64 true residual <= tol and the
+      field within 1e-8 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+from oracle import pml
+from paper_2410_17446_amd import tables
+
+from helpers import K0, rel_l2, to_gpu, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(N=64, W=12, sm=1.0, npoles=8, medium=("sine", 0.05, 2.0), tol=1e-10):
+    wl = workload(N=N, W=W, npoles=npoles, medium=medium, tol=tol)
+    g = pml.PMLGrid(N=N, h=0.25, k0=K0, n0=1.0, c=wl["c"], d=wl["d"], W=W, sigma_max=sm)
+    return wl, g
+
+
+def _plan(wl, g, tol=None):
+    from paper_2410_17446_amd import hp
+    cfg, f = wl["cfg"], wl["fit"]
+    plan = hp.Plan(nx=cfg["N"], ny=cfg["N"], dx=0.25, dy=0.25, k0=K0, n0=1.0, dz=cfg["dz"], ncomp=1,
+                   poles=f["poles"], residues=f["residues"], r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"],
+                   edge_width=g.W, edge_eta=0.25, tol=tol or cfg["tol"], restart=30, max_cycles=20, precision=0)
+    Q, Qi, lam = tables.pml_eigen(g.N, g.h, g.k0, g.n0, g.W, g.sigma_max, wl["c"], wl["d"])
+    plan.set_pml(g.sigma_max, Q, Qi, lam)
+    return plan, Q
+
+
+def _tilted_beam(N, h=0.25, waist=2.0, sin_t=0.5):
+    xs = (np.arange(N) - N / 2) * h
+    X, Y = np.meshgrid(xs, xs)
+    w = np.exp(-(X ** 2 + Y ** 2) / waist ** 2) * np.exp(1j * K0 * sin_t * X)
+    w[0, :] = 0
+    w[:, 0] = 0
+    return w
+
+
+@pytest.mark.parametrize("pole", [-1, 0, 5])
+def test_pml_operator_matches_oracle(pole):
+    torch = _cuda()
+    wl, g = _setup()
+    plan, _ = _plan(wl, g)
+    plan.set_medium(to_gpu(wl["n2"]))
+    V = pml.medium(g, wl["n2"])
+    x = np.random.default_rng(3).standard_normal((64, 64)) + 1j * np.random.default_rng(4).standard_normal((64, 64))
+    x[0, :] = 0
+    x[:, 0] = 0
+    b = 0.0 if pole < 0 else wl["fit"]["poles"][pole]
+    ref = pml.apply_shifted(g, V, x, b)
+    y = torch.zeros((1, 64, 64), dtype=torch.complex128, device="cuda")
+    plan.apply_operator(pole, to_gpu(x[None]), y)
+    assert rel_l2(y.cpu().numpy()[0], ref) < 1e-13
+
+
+@pytest.mark.parametrize("N,sm", [(64, 1.0), (128, 1.0), (128, 4.0), (256, 10.0)])
+def test_pml_preconditioner_matches_oracle(N, sm):
+    torch = _cuda()
+    wl, g = _setup(N=N, W=max(12, N // 8), sm=sm)
+    plan, Q = _plan(wl, g)
+    bound = 20 * 2.2e-16 * (N - 1) * np.linalg.cond(Q) ** 2
+    x = np.random.default_rng(5).standard_normal((N, N)) + 1j * np.random.default_rng(6).standard_normal((N, N))
+    x[0, :] = 0
+    x[:, 0] = 0
+    for pole in (0, 3, 7):
+        b = wl["fit"]["poles"][pole]
+        ref = pml.apply_minv(g, x, b)
+        y = torch.zeros((1, N, N), dtype=torch.complex128, device="cuda")
+        plan.apply_preconditioner(pole, to_gpu(x[None]), y)
+        err = rel_l2(y.cpu().numpy()[0], ref)
+        assert err < max(bound, 1e-12), (pole, err, bound)
+
+
+def test_pml_step_replayed_iterations():
+    """One step of a beam tilted toward the layer through a weak sine medium, with the oracle's
+    per-pole iteration counts replayed (one cycle each)."""
+    torch = _cuda()
+    wl, g = _setup()
+    w = _tilted_beam(64)
+    V = pml.medium(g, wl["n2"])
+    f = wl["fit"]
+    ref, res = pml.step(g, V, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+    counts = [r.iters for r in res]
+    assert all(r.cycles == 1 for r in res)
+    plan, _ = _plan(wl, g)
+    plan.set_fixed_iters(counts)
+    out = plan.step(to_gpu(w[None]), to_gpu(wl["n2"]))
+    assert rel_l2(out.cpu().numpy()[0], ref) < 1e-9
+    it, _ = plan.stats()
+    assert it == counts
+
+
+def test_pml_step_own_tolerance_and_solve():
+    """Without replay every pole stops on its FP64 true residual (<= tol), iteration counts stay
+    within a few of the oracle's, the field agrees to ~tol, and hp_solve's solution has the
+    oracle operator's residual <= tol."""
+    torch = _cuda()
+    wl, g = _setup()
+    w = _tilted_beam(64)
+    V = pml.medium(g, wl["n2"])
+    f = wl["fit"]
+    ref, res = pml.step(g, V, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+    plan, _ = _plan(wl, g)
+    out = plan.step(to_gpu(w[None]), to_gpu(wl["n2"]))
+    it, rr = plan.stats()
+    assert max(rr) <= 1e-10
+    assert all(abs(a - r.iters) <= 3 for a, r in zip(it, res)), (it, [r.iters for r in res])
+    assert rel_l2(out.cpu().numpy()[0], ref) < 1e-8
+    x = plan.solve(2, to_gpu(w[None])).cpu().numpy()[0]
+    r = pml.apply_shifted(g, V, x, f["poles"][2]) - w
+    r[0, :] = 0
+    r[:, 0] = 0
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(w)
+
+
+def test_pml_absorbs_like_the_oracle():
+    """The oracle's absorption scenario (beam of waist 2 lambda at 30 degrees, N = 64, W = 12,
+    sigma_max = 1, 8 poles, free space) on the library: after 14 steps of lambda the field matches
+    the oracle's PML propagation to 1e-8 of the peak, and after 24 steps under 1 % of the power is
+    left (the oracle's own pin compares the 14-step field with a twice larger domain)."""
+    torch = _cuda()
+    wl, g = _setup(medium=("uniform",))
+    n2 = np.ones((64, 64))
+    V = pml.medium(g, n2)
+    f = wl["fit"]
+    w = _tilted_beam(64)
+    p0 = np.sum(np.abs(w) ** 2)
+    plan, _ = _plan(wl, g)
+    plan.set_medium(to_gpu(n2))
+    wo, wg = w.copy(), to_gpu(w[None])
+    for s in range(24):
+        if s < 14:
+            wo, _ = pml.step(g, V, wo, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+        wg = plan.step(wg)
+        if s == 13:
+            assert np.abs(wg.cpu().numpy()[0] - wo).max() < 1e-8 * np.abs(w).max()
+    assert np.sum(np.abs(wg.cpu().numpy()) ** 2) / p0 < 1e-2
+
+
+def test_pml_mode_switches():
+    """The layers need a scalar FP64 plan; guesses and the square-root form are refused while
+    they are set; removing them restores the plain edge-layer step."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp
+    wl, g = _setup()
+    plan, _ = _plan(wl, g)
+    with pytest.raises(hp.HPError):
+        plan.set_guess(hp.HP_GUESS_PREV)
+    with pytest.raises(hp.HPError):
+        plan.set_form(hp.HP_FORM_SQRT, 4)
+    Q, Qi, lam = tables.pml_eigen(64, 0.25, K0, 1.0, 12, 2.0, wl["c"], wl["d"])
+    with pytest.raises(hp.HPError):
+        plan.set_pml(1.0, Q, Qi, lam)       # tables of another sigma_max: the probe check fails
+    plan.set_pml(0.0)
+    plan.set_guess(hp.HP_GUESS_PREV)
+    out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    assert np.isfinite(out.cpu().numpy()).all()

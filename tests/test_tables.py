@@ -127,3 +127,21 @@ def test_lookup_round_trip_and_misses(tmp_path):
         u.get(k0, 0.75, 1.0)          # k0 dz not tabulated
     with pytest.raises(KeyError):
         u.get(k0, 1.0, 1.0003)        # other reference index
+
+
+# ---------------------------------------------------------------- absorbing-layer tables (Sec. 4.1)
+
+
+@pytest.mark.parametrize("N,W,sm", [(32, 6, 1.0), (64, 12, 3.0)])
+def test_pml_stretched_matrix_matches_oracle(N, W, sm):
+    """The library's stretched one-axis operator and the oracle's (written separately from the
+    same definition) agree entry by entry, and pml_eigen decomposes it."""
+    from oracle import pml
+    c, d = tables.stencil_d2(), tables.stencil_d1()
+    g = pml.PMLGrid(N=N, h=0.25, k0=2 * np.pi, n0=1.0, c=c, d=d, W=W, sigma_max=sm)
+    ref = g.s * pml.d2_stretched_matrix(g)
+    A = tables.pml_stretched_d2(N, 0.25, 2 * np.pi, 1.0, W, sm, c, d)
+    assert np.abs(A - ref).max() <= 1e-14 * np.abs(ref).max()
+    Q, Qi, lam = tables.pml_eigen(N, 0.25, 2 * np.pi, 1.0, W, sm, c, d)
+    assert np.abs(Q @ (lam[:, None] * Qi) - ref).max() < 1e-10 * np.abs(ref).max()
+    assert lam.imag.min() > 0      # the layers move the spectrum above the real axis
