@@ -24,7 +24,9 @@ sizes run concurrently), learned (a U-Net trained on the GPU from the
 propagator's own solves supplies GMRES starting points; timed against the plain
 method and the previous-step start on scalar1024), unet (training steps of that
 U-Net at its training shape), copy (the HBM reference for the counters) and
-sqrt1024 (the scalar1024 workload through the pseudo-differential form: 25
+pml512 (absorbing layers: 512^2 with PML layers of 64 cells, the eigen-route
+Sylvester preconditioner's dense products), sqrt1024 (the scalar1024 workload
+through the pseudo-differential form: 25
 Cauchy-integral terms of sqrt(1+z), alpha = 1, eight RK4 substeps of lambda/8
 per lambda step, FP64; the field is compared with the exponential form's after
 the same number of steps) and sineprod768 (z-dependent rotated sine-product
@@ -384,7 +386,7 @@ EVENT_PERIOD = 4  # the timed steps bracket every 4th launch of the dominant ker
 
 
 def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None, event_period=EVENT_PERIOD,
-             autotune=0):
+             autotune=0, pml=None):
     poles, residues, r_inf, d2, d1 = tables
     N = cfg["N"]
     plan = hp.Plan(nx=N, ny=N, dx=cfg["dx"], dy=cfg["dx"], k0=hp_k0(), n0=1.0, dz=cfg["dz"], ncomp=cfg["ncomp"],
@@ -393,6 +395,8 @@ def run_mode(hp, torch, cfg, tables, precision, w0, n2, warmup, steps, form=None
                    precision=precision)
     if form is not None:
         plan.set_form(*form)
+    if pml is not None:
+        plan.set_pml(*pml)
     plan.set_medium(n2)
     create_status = plan.create_status
     a = w0.clone()
@@ -568,6 +572,90 @@ def run_sineprod(args):
     return 0
 
 
+FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector (and FP64 matrix) peak
+PML_SIGMA = 10.0
+
+
+def run_pml(args):
+    """Absorbing layers (Sec. 4.1): the scalar workload of the sine-product runs of Sec. 5 on 512^2
+    cells of lambda/4 (128 lambda) with PML layers of 64 cells (16 lambda) on every side, sigma_max
+    = 10, a Gaussian beam (1/e radius 8 lambda) tilted 20 degrees off axis and 16 lambda off centre
+    toward the layer, sine-product medium n = 1 + 0.02 sin(2 pi x) sin(2 pi y), 16 poles, dz =
+    lambda, tol 1e-8, FP64.  The preconditioner is the eigen route of the stretched Sylvester
+    equation: four dense complex products per pole and Arnoldi step."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, tables
+    N, W = 512, 64
+    cfg = dict(N=N, dx=0.25, ncomp=1, W=W, eta_max=0.25, dz=1.0, npoles=16, tol=1e-8, restart=30,
+               medium=("sine", 0.02, 1.0), w0=8.0)
+    tab = tables.plan_tables(inputs.K0 * cfg["dz"], cfg["npoles"])
+    Q, Qi, lam = tables.pml_eigen(N, cfg["dx"], inputs.K0, 1.0, W, PML_SIGMA, tab[3], tab[4])
+    cond = float(np.linalg.cond(Q))
+    w = inputs.tilted_beam(N, cfg["dx"], cfg["w0"], np.sin(np.radians(20.0)), x0=16.0)
+    w0 = torch.from_numpy(w).cuda()
+    n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
+    r = run_mode(hp, torch, cfg, tab, hp.HP_FP64, w0, n2, args.warmup, args.steps, event_period=args.event_period,
+                 pml=(PML_SIGMA, Q, Qi, lam))
+    value = args.steps / r["seconds"]
+    prof, brk, dom = r["prof"], r["breakdown"], r["dom"]
+    n_l, ms, amount = prof[dom]
+    if dom == "pml_gemm":
+        achieved = amount / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        roof = {"bound": "alu", "kernel": "pml_gemm (the four dense stages of a round)", "achieved": achieved,
+                "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFS,
+                "traffic": None, "algorithmic_flops_per_launch": amount / max(n_l, 1),
+                "flops_convention": "8 (N-1)^3 per complex product, four products per pole that did the round",
+                "peak_is": "FP64 vector ALU (256 CUs x 2.4 GHz x 128 FP64 flops/clock; the FP64 matrix "
+                           "cores have the same rate)"}
+    else:
+        achieved = amount / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
+                 "timed": f"every {args.event_period}th launch in the timed steps"})
+    f_in, f_out = w0.cpu().numpy(), r["field"].cpu().numpy()
+    gemm_ms = brk["pml_gemm"][1]
+    line = {
+        "metric": f"propagation steps/s ({N}^2, {cfg['npoles']} poles, PML layers of {W} cells)",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["seconds"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "pml512", "grid": N, "pml_cells": W, "sigma_max": PML_SIGMA, "poles": cfg["npoles"],
+                   "tol": cfg["tol"], "mode": "fp64", "beam": "1/e radius 8 lambda, 20 degrees, 16 lambda off axis"},
+        "last_step_iters": r["iters"], "last_step_true_relres_max": max(r["relres"]),
+        "eigenvector_condition": cond,
+        "power_ratio": float(np.sum(np.abs(f_out) ** 2) / np.sum(np.abs(f_in) ** 2)),
+        "roofline": roof,
+        "warmup_kernel_ms": {k: brk[k][1] for k in brk},
+        "warmup_pml_gemm_TFLOPs": (brk["pml_gemm"][2] / (gemm_ms * 1e-3) / 1e12) if gemm_ms > 0 else None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_pml(cfg, tab, w, inputs.medium_n2(cfg))
+    print(json.dumps(line))
+    return 0
+
+
+def cpu_baseline_pml(cfg, tab, w, n2):
+    """The oracle's PML solve (Bartels-Stewart preconditioner) of one pole of step 1, scaled to steps/s."""
+    from oracle import pml
+    from paper_2410_17446_amd import inputs
+    poles = tab[0]
+    g = pml.PMLGrid(N=cfg["N"], h=cfg["dx"], k0=inputs.K0, n0=1.0, c=tab[3], d=tab[4], W=cfg["W"],
+                    sigma_max=PML_SIGMA)
+    V = pml.medium(g, n2)
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
+    j = len(poles) // 2
+    t0 = time.perf_counter()
+    r = pml.solve_pole(g, V, w[0], poles[j], cfg["tol"], cfg["restart"])
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / (dt * cfg["npoles"]), unit="steps/s", cores=threads, kind="oracle",
+                sample=f"GMRES solve of pole {j} (of {cfg['npoles']}) in step 1 of the {cfg['N']}^2 PML workload "
+                       f"({dt:.1f} s, {r.iters} iterations); per-step time = sample time x {cfg['npoles']}; "
+                       f"numpy/scipy BLAS and LAPACK threads as the box sets them")
+
+
 def run_sqrt(args):
     """scalar1024 through the pseudo-differential form (FP64), compared with the exponential form."""
     import numpy as np
@@ -636,6 +724,8 @@ def main():
         return run_sqrt(args)
     if args.config == "sineprod768":
         return run_sineprod(args)
+    if args.config == "pml512":
+        return run_pml(args)
     import numpy as np
     import torch
 

@@ -1541,7 +1541,9 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
         num += std::norm(yd[j - 1] - ye[j - 1]);
         den += std::norm(yd[j - 1]);
       }
-      if (!(num <= 1e-12 * den))
+      // the dense stages only precondition (the Arnoldi step applies the explicit
+      // operator to the stored z), so 1e-3 leaves GMRES its convergence
+      if (!(num <= 1e-6 * den))
         return fail(p, HP_EINVAL,
                     "Q diag(lam) Q^-1 does not reproduce the stretched operator s D~ of this plan (relative error " +
                         std::to_string(std::sqrt(num / den)) + ")");

@@ -33,6 +33,17 @@ def gaussian_beam(N: int, dx: float, w0: float, ncomp: int = 1, x0: float = 0.0,
     return out
 
 
+def tilted_beam(N: int, dx: float, w0: float, sin_t: float, x0: float = 0.0) -> np.ndarray:
+    """Gaussian beam (1/e radius w0) centred at x = x0 with the phase exp(i k0 sin_t x): travelling
+    at angle asin(sin_t) to the axis in the x-z plane; (1, N, N)."""
+    x = coords(N, dx)
+    X, Y = np.meshgrid(x, x)
+    u = np.exp(-((X - x0) ** 2 + Y ** 2) / w0 ** 2) * np.exp(1j * K0 * sin_t * X)
+    u[0, :] = 0.0
+    u[:, 0] = 0.0
+    return u[None].astype(np.complex128)
+
+
 def sine_product_n2(N: int, dx: float, amp: float, period: float) -> np.ndarray:
     """n^2 for n = 1 + amp sin(2 pi x/period) sin(2 pi y/period)."""
     x = coords(N, dx)
