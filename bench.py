@@ -597,7 +597,7 @@ def run_pml(args):
     w0 = torch.from_numpy(w).cuda()
     n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
     r = run_mode(hp, torch, cfg, tab, hp.HP_FP64, w0, n2, args.warmup, args.steps, event_period=args.event_period,
-                 pml=(PML_SIGMA, Q, Qi, lam))
+                 pml=(PML_SIGMA, Q, Qi, lam), autotune=args.autotune)
     value = args.steps / r["seconds"]
     prof, brk, dom = r["prof"], r["breakdown"], r["dom"]
     n_l, ms, amount = prof[dom]
@@ -623,7 +623,8 @@ def run_pml(args):
         "ms_per_step": 1e3 * r["seconds"] / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c128", "data": "synthetic",
         "config": {"workload": "pml512", "grid": N, "pml_cells": W, "sigma_max": PML_SIGMA, "poles": cfg["npoles"],
-                   "tol": cfg["tol"], "mode": "fp64", "beam": "1/e radius 8 lambda, 20 degrees, 16 lambda off axis"},
+                   "tol": cfg["tol"], "mode": "fp64", "beam": "1/e radius 8 lambda, 20 degrees, 16 lambda off axis",
+                   "dense_stage_variant": r["variant"]},
         "last_step_iters": r["iters"], "last_step_true_relres_max": max(r["relres"]),
         "eigenvector_condition": cond,
         "power_ratio": float(np.sum(np.abs(f_out) ** 2) / np.sum(np.abs(f_in) ** 2)),

@@ -196,7 +196,12 @@ int hp_autotune(hp_plan plan, const void* E_in, const double* n2, int reps, void
 
 /* Set the column-pass variant (0, 1 or 2, as hp_autotune reports it) directly,
  * e.g. to reuse a choice measured once for plans of the same shape.  HP_EINVAL
- * for another value. */
+ * for another value.  With absorbing layers (hp_set_pml) the variant picks the
+ * form of the preconditioner's dense complex products instead (0..3), and
+ * hp_autotune chooses among those: 0 vector-ALU products on 64 x 64 tiles;
+ * matrix-core (FP64 MFMA) products on 1 64 x 64 tiles while the round's poles
+ * give every CU two workgroups, else 32 x 32 tiles, 2 always 32 x 32, 3 always
+ * 64 x 64.  Removing the layers turns variant 3 back into 1. */
 int hp_set_launch(hp_plan plan, int col_variant);
 
 /* What a step does with the pole table.

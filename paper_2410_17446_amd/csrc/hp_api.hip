@@ -415,10 +415,11 @@ void pml_prec(hp_plan p, const PoleState* st, const int* list, int n, int* activ
   const int N = p->d.nx;
   const size_t fn = p->fieldn;
   const PmlRef a{nullptr, bufA, fn, 0}, b{nullptr, bufB, fn, 0};
-  launch_pml_gemm(true, 0, p->pml_qi, in, a, st, list, n, active_out, p->pml_lam, N, p->stream);
-  launch_pml_gemm(false, 1, p->pml_qi, a, b, st, list, n, nullptr, p->pml_lam, N, p->stream);
-  launch_pml_gemm(true, 0, p->pml_q, b, a, st, list, n, nullptr, p->pml_lam, N, p->stream);
-  launch_pml_gemm(false, 2, p->pml_q, a, out, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  const int v = p->geo.col_variant;  // the launch variant picks the dense stages' form
+  launch_pml_gemm(v, true, 0, p->pml_qi, in, a, st, list, n, active_out, p->pml_lam, N, p->stream);
+  launch_pml_gemm(v, false, 1, p->pml_qi, a, b, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  launch_pml_gemm(v, true, 0, p->pml_q, b, a, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  launch_pml_gemm(v, false, 2, p->pml_q, a, out, st, list, n, nullptr, p->pml_lam, N, p->stream);
 }
 
 // Floating-point operations of one pole's four dense stages: 8 n^3 per complex
@@ -1305,7 +1306,9 @@ int hp_step_guess(hp_plan p, const void* E_in, const double* n2, const void* con
 
 int hp_set_launch(hp_plan p, int col_variant) {
   if (!p) return fail(nullptr, HP_EINVAL, "plan is NULL");
-  if (col_variant < 0 || col_variant > 2) return fail(p, HP_EINVAL, "col_variant must be 0, 1 or 2");
+  const int top = p->pml ? 3 : 2;  // with absorbing layers: the dense stages' forms 0..3
+  if (col_variant < 0 || col_variant > top)
+    return fail(p, HP_EINVAL, p->pml ? "variant must be 0, 1, 2 or 3" : "col_variant must be 0, 1 or 2");
   p->geo.col_variant = col_variant;
   return HP_OK;
 }
@@ -1323,7 +1326,7 @@ int hp_autotune(hp_plan p, const void* E_in, const double* n2, int reps, void* E
   const int keep = p->geo.col_variant;
   double best = 0.0;
   int bestv = keep;
-  for (int v = 0; v < 3; ++v) {
+  for (int v = 0; v < (p->pml ? 4 : 3); ++v) {
     p->geo.col_variant = v;
     int rc = hp_step(p, E_in, nullptr, E_out);  // untimed: first use of this variant's kernels
     if (rc < 0) {
@@ -1455,6 +1458,7 @@ static void free_pml(hp_plan p) {
   p->pml_part = nullptr;
   p->pml = false;
   p->pml_sigma = 0.0;
+  if (p->geo.col_variant > 2) p->geo.col_variant = 1;  // a dense-stage form with no column-pass meaning
 }
 
 int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, const void* lam) {

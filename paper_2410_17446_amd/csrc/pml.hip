@@ -115,6 +115,119 @@ __global__ __launch_bounds__(GWG) void k_pml_gemm(const c128* __restrict__ mat, 
   }
 }
 
+// The same products on the matrix cores: v_mfma_f64_16x16x4f64 multiplies a
+// 16 x 4 by a 4 x 16 FP64 block per wave (operand element (i, k) of A and
+// (k, j) of B in lane i + 16 k and j + 16 k; result (i, j) in element i / 4 of
+// lane j + 16 (i % 4), i.e. element r of lane l holds (4 r + l / 16, l % 16)).  A complex block takes four real products into two
+// accumulators (re += Ar Br - Ai Bi, im += Ar Bi + Ai Br); each lane reads its
+// complex operand from LDS with one 16-byte load, so LDS carries a quarter of
+// the bytes per multiply-add that the vector-ALU form needs.  BT x BT block
+// tile, four waves of BT/2 x BT/2, K staged through LDS in steps of 16 as there;
+// at most 128 registers per lane (accumulators included), four waves per SIMD.
+typedef double pml_d4 __attribute__((ext_vector_type(4)));
+
+template <bool LEFT, int EPI, int BT>
+__global__ __launch_bounds__(GWG, 4) void k_pml_gemm_mfma(const c128* __restrict__ mat, PmlRef in, PmlRef out,
+                                                       const PoleState* __restrict__ st, PoleList list,
+                                                       int* __restrict__ active_out, const c128* __restrict__ lam,
+                                                       int N) {
+  constexpr int WT = BT / 2, MB = WT / 16, LPT = BT * GK / GWG;
+  const int k = list.k[blockIdx.z];
+  if (active_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[blockIdx.z] = k;
+  if (st[k].flag) return;
+  const int m = st[k].m;
+  const c128* __restrict__ X = pml_field(in, k, m);
+  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m));
+  const int r0 = blockIdx.y * BT, c0 = blockIdx.x * BT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * WT, wc = (wave & 1) * WT;
+  const c128* __restrict__ Ag = LEFT ? mat : X;
+  const c128* __restrict__ Bg = LEFT ? X : mat;
+  __shared__ c128 As[GK][BT + 1];
+  __shared__ c128 Bs[GK][BT + 1];
+  c128 ra[LPT], rb[LPT];
+  auto fetch = [&](int j0) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + GWG * q;
+      ra[q] = Ag[(size_t)(r0 + e / GK) * N + j0 + e % GK];
+      if (LEFT)
+        rb[q] = Bg[(size_t)(j0 + e / BT) * N + c0 + e % BT];
+      else
+        rb[q] = Bg[(size_t)(c0 + e / GK) * N + j0 + e % GK];
+    }
+  };
+  pml_d4 cr[MB][MB], ci[MB][MB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      cr[a][b] = pml_d4{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = pml_d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int li = lane & 15, lk = lane >> 4;
+  fetch(0);
+  for (int j0 = 0; j0 < N; j0 += GK) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + GWG * q;
+      As[e % GK][e / GK] = ra[q];
+      if (LEFT)
+        Bs[e / BT][e % BT] = rb[q];
+      else
+        Bs[e % GK][e / GK] = rb[q];
+    }
+    __syncthreads();
+    if (j0 + GK < N) fetch(j0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      double ar[MB], ai[MB], nai[MB], br[MB], bi[MB];
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        const c128 v = As[ks + lk][wr + a * 16 + li];
+        ar[a] = v.re;
+        ai[a] = v.im;
+        nai[a] = -v.im;
+      }
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        const c128 v = Bs[ks + lk][wc + b * 16 + li];
+        br[b] = v.re;
+        bi[b] = v.im;
+      }
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], bi[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const c128 bk = st[k].bk;
+  const double sg = st[k].sigma[m];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wr + a * 16 + 4 * r + lk, col = c0 + wc + b * 16 + li;
+        c128 v = mk(cr[a][b][r], ci[a][b][r]);
+        if (EPI == 1) v = (row == 0 || col == 0) ? mk(0.0, 0.0) : cdiv(v, lam[row] + lam[col] - bk);
+        if (EPI == 2) v = sg * v;
+        Y[(size_t)row * N + col] = v;
+      }
+}
+
 // ------------------------------------------------------------------ stretched explicit operator
 
 // x at node (i, j) with odd reflection about the Dirichlet nodes 0 and N
@@ -311,12 +424,25 @@ int flat_blocks(size_t n) {
 
 }  // namespace
 
-void launch_pml_gemm(bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out, const PoleState* st,
-                     const int* list, int n, int* active_out, const c128* lam, int N, hipStream_t s) {
+void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out,
+                     const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N,
+                     hipStream_t s) {
   const PoleList l = make_list(list, n);
-  const dim3 grid(N / GT, N / GT, n);
-#define G_(L, E) \
-  hipLaunchKernelGGL((k_pml_gemm<L, E>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, N)
+  // variant 1 takes 64 x 64 tiles while they give every CU two workgroups, else 32 x 32
+  const int big = n * (N / 64) * (N / 64) >= 512;
+  const int bt = (variant == 2 || (variant == 1 && !big)) ? 32 : 64;
+  const dim3 grid(N / bt, N / bt, n);
+#define G_(L, E)                                                                                                   \
+  do {                                                                                                             \
+    if (variant == 0)                                                                                              \
+      hipLaunchKernelGGL((k_pml_gemm<L, E>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, N);     \
+    else if (bt == 32)                                                                                             \
+      hipLaunchKernelGGL((k_pml_gemm_mfma<L, E, 32>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, \
+                         N);                                                                                       \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_pml_gemm_mfma<L, E, 64>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, \
+                         N);                                                                                       \
+  } while (0)
   if (left) {
     if (epilogue == 1)
       G_(true, 1);

@@ -35,8 +35,12 @@ struct PmlRef {
 // skip themselves): left Out = Mat In, or right Out = In Mat^T; epilogue 0
 // none, 1 divide entry (p, q) by lam_p + lam_q - b_k, 2 scale by the pole's
 // sigma_m.  active_out (may be NULL) receives the list for later kernels.
-void launch_pml_gemm(bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out, const PoleState* st,
-                     const int* list, int n, int* active_out, const c128* lam, int N, hipStream_t s);
+// variant: 0 vector-ALU products on 64 x 64 tiles; matrix-core products on
+// 1 64 x 64 tiles while n (N/64)^2 >= 512 (two workgroups per CU), else
+// 32 x 32, 2 always 32 x 32 (four times the workgroups), 3 always 64 x 64.
+void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out,
+                     const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N,
+                     hipStream_t s);
 
 // p = (Zbar~ - b_k I) z_m - sigma_m u_m into P[k] (so that A_k z_m = ~v_m + p
 // for the z_m as stored) and the partial inner products <u_i, p>, <u_i, u_m>,

@@ -72,6 +72,47 @@ def test_aperture_centerline_intensity_against_closed_form():
     assert err_far < 3e-3
 
 
+def test_aperture_with_pml_against_closed_form():
+    """The same aperture problem with the paper's boundary: PML layers of 40 cells (10 lambda, the
+    paper's depth at lambda/4) by complex-coordinate stretching (Sec. 4.1, sigma_max = 10) around a
+    304 x 304 physical grid, the eigen-route Sylvester preconditioner, steps of lambda/20 to 120
+    lambda.  The centerline intensity must again be no worse than the paper's propagator."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp, tables
+    N, dx, W, a, dz, L, sm = 384, 0.25, 40, 10.0, 0.05, 120.0, 10.0
+    nsteps = int(round(L / dz))
+    c, d = stencil.stencils()
+    f = fit.fit_exp_sqrt(K0 * dz, 16)
+    plan = hp.Plan(nx=N, ny=N, dx=dx, dy=dx, k0=K0, n0=1.0, dz=dz, ncomp=1, poles=f["poles"],
+                   residues=f["residues"], r_inf=f["r_inf"], d2=c, d1=d, edge_width=W, edge_eta=0.25,
+                   tol=1e-10, restart=30, max_cycles=20)
+    plan.set_pml(sm, *tables.pml_eigen(N, dx, K0, 1.0, W, sm, c, d))
+    x = inputs.coords(N, dx)
+    X, Y = np.meshgrid(x, x)
+    w = (X ** 2 + Y ** 2 <= a * a).astype(complex)[None]
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    plan.set_medium(to_gpu(np.ones((N, N))))
+    A, B = to_gpu(w), torch.empty_like(to_gpu(w))
+    centre = torch.empty(nsteps, dtype=torch.complex128, device="cuda")
+    for s in range(nsteps):
+        plan.step(A, E_out=B)
+        centre[s] = B[0, N // 2, N // 2]
+        A, B = B, A
+    it, rr = plan.stats()
+    assert max(rr) <= 1e-10
+    I = np.abs(centre.cpu().numpy()) ** 2
+    z = dz * np.arange(1, nsteps + 1)
+    ref = aperture_intensity(z, a, K0)
+    err = np.linalg.norm(I - ref) / np.linalg.norm(ref)
+    far = z >= 20.0
+    err_far = np.linalg.norm(I[far] - ref[far]) / np.linalg.norm(ref[far])
+    print(f"aperture with PML: centerline intensity relative L2 {err:.3e} (paper's propagator "
+          f"{PAPER['aperture_centerline_l2_propagator']:.2e}); beyond 20 lambda {err_far:.3e}")
+    assert err < PAPER["aperture_centerline_l2_propagator"]
+    assert err_far < 3e-3
+
+
 @pytest.mark.parametrize("beam,N", [("narrow", 128), ("wide", 192)])
 def test_gaussian_beam_peaks_against_closed_form(beam, N):
     """Sec. 5.2: Gaussian beams of 1/e spectral width k0 n0 (narrow, w = lambda/(pi n0)) and

@@ -74,11 +74,15 @@ def test_pml_operator_matches_oracle(pole):
     assert rel_l2(y.cpu().numpy()[0], ref) < 1e-13
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("N,sm", [(64, 1.0), (128, 1.0), (128, 4.0), (256, 10.0)])
-def test_pml_preconditioner_matches_oracle(N, sm):
+def test_pml_preconditioner_matches_oracle(N, sm, variant):
+    """Every form of the dense stages (vector ALU; matrix cores with the tile chosen by the round's
+    workgroup count, on 32 x 32 and on 64 x 64 tiles)."""
     torch = _cuda()
     wl, g = _setup(N=N, W=max(12, N // 8), sm=sm)
     plan, Q = _plan(wl, g)
+    plan.set_launch(variant)
     bound = 20 * 2.2e-16 * (N - 1) * np.linalg.cond(Q) ** 2
     x = np.random.default_rng(5).standard_normal((N, N)) + 1j * np.random.default_rng(6).standard_normal((N, N))
     x[0, :] = 0
@@ -92,7 +96,8 @@ def test_pml_preconditioner_matches_oracle(N, sm):
         assert err < max(bound, 1e-12), (pole, err, bound)
 
 
-def test_pml_step_replayed_iterations():
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_pml_step_replayed_iterations(variant):
     """One step of a beam tilted toward the layer through a weak sine medium, with the oracle's
     per-pole iteration counts replayed (one cycle each)."""
     torch = _cuda()
@@ -104,6 +109,7 @@ def test_pml_step_replayed_iterations():
     counts = [r.iters for r in res]
     assert all(r.cycles == 1 for r in res)
     plan, _ = _plan(wl, g)
+    plan.set_launch(variant)
     plan.set_fixed_iters(counts)
     out = plan.step(to_gpu(w[None]), to_gpu(wl["n2"]))
     assert rel_l2(out.cpu().numpy()[0], ref) < 1e-9
