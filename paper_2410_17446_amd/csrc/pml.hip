@@ -138,7 +138,9 @@ __global__ __launch_bounds__(GWG, 4) void k_pml_gemm_mfma(const c128* __restrict
   const int m = st[k].m;
   const c128* __restrict__ X = pml_field(in, k, m);
   c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m));
-  const int r0 = blockIdx.y * BT, c0 = blockIdx.x * BT;
+  // right products: consecutive workgroups (spread over the XCDs) take consecutive row
+  // tiles, so each XCD keeps its row slabs of the field operand
+  const int r0 = (LEFT ? blockIdx.y : blockIdx.x) * BT, c0 = (LEFT ? blockIdx.x : blockIdx.y) * BT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * WT, wc = (wave & 1) * WT;
   const c128* __restrict__ Ag = LEFT ? mat : X;
