@@ -240,6 +240,23 @@ int hp_set_launch(hp_plan plan, int col_variant);
 enum { HP_FORM_EXP = 0, HP_FORM_SQRT = 1 };
 int hp_set_form(hp_plan plan, int form, int substeps);
 
+/* The rational approximation of Sec. 3.1 computed on the device, for a
+ * step size without a table entry: AAA (greedy support points, weights from
+ * the smallest singular vector of the Loewner matrix) followed by
+ * lawson_steps (0..1000; 40 is what the host fit uses) Lawson reweightings of
+ * the linearised least-squares problem, on 4001 uniform samples of
+ * z in [-4, 2] of exp(iK sqrt(1+z)) (principal branch), keeping the iterate
+ * whose partial fractions have the smallest largest sample error (AAA's own
+ * included).  K = k0 n0 dz > 0, degree = number of poles (1..31).  One
+ * workgroup runs the whole fit in one launch on `stream` (NULL: the null
+ * stream; hipMalloc of about 5 MB of scratch, freed before returning);
+ * synchronous.  Outputs (host arrays): poles [degree], residues [degree],
+ * *r_inf, and *max_err (may be NULL) the largest |r - f| on the samples.
+ * HP_EINVAL for bad arguments or when the kept denominator does not have
+ * degree finite roots; the message is in hp_last_error(NULL). */
+int hp_fit_exp_sqrt(double K, int degree, int lawson_steps, void* stream, hp_c128* poles, hp_c128* residues,
+                    hp_c128* r_inf, double* max_err);
+
 /* Absorbing layers (Sec. 4.1): the periphery of W = edge_width cells along
  * each axis becomes a perfectly matched layer by complex-coordinate
  * stretching of the transverse derivatives, d/dx -> (1/g) d/dx with

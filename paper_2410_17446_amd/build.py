@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhp.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "hp_api.hip", "unet.hip", "pml.hip"]
+SOURCES = ["kernels.hip", "hp_api.hip", "unet.hip", "pml.hip", "fit.hip"]
 ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 
 

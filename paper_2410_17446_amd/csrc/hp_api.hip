@@ -18,6 +18,9 @@
 #include "kernels.hpp"
 #include "pml.hpp"
 
+// the rational fit on the device (fit.hip)
+int fit_exp_sqrt_device(double K, int degree, int lawson_steps, hipStream_t s, std::vector<c128>& h,
+                        std::string* why);
 // the learned guess needs the net's stream and channel counts (unet.hip)
 hipStream_t unet_stream(hp_unet n);
 void unet_shape(hp_unet n, int* levels, int* cin, int* cout);
@@ -1600,6 +1603,29 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
   p->pml = true;
   p->pml_sigma = sigma_max;
   p->prev_valid = false;
+  return HP_OK;
+}
+
+int hp_fit_exp_sqrt(double K, int degree, int lawson_steps, void* stream, hp_c128* poles, hp_c128* residues,
+                    hp_c128* r_inf, double* max_err) {
+  if (!(K > 0.0) || !std::isfinite(K)) return fail(nullptr, HP_EINVAL, "K must be finite and > 0");
+  if (degree < 1 || degree > 31) return fail(nullptr, HP_EINVAL, "degree must be in [1, 31]");
+  if (lawson_steps < 0 || lawson_steps > 1000) return fail(nullptr, HP_EINVAL, "lawson_steps must be in [0, 1000]");
+  if (!poles || !residues || !r_inf) return fail(nullptr, HP_EINVAL, "poles/residues/r_inf is NULL");
+  std::vector<c128> h;
+  std::string why;
+  if (fit_exp_sqrt_device(K, degree, lawson_steps, reinterpret_cast<hipStream_t>(stream), h, &why))
+    return fail(nullptr, HP_EHIP, why);
+  const int np = (int)h[2 * (size_t)degree + 1].im;
+  if (max_err) *max_err = h[2 * (size_t)degree + 1].re;
+  if (np != degree)
+    return fail(nullptr, HP_EINVAL,
+                "the fit's denominator has " + std::to_string(np) + " finite roots, not " + std::to_string(degree));
+  for (int k = 0; k < degree; ++k) {
+    poles[k] = hp_c128{h[k].re, h[k].im};
+    residues[k] = hp_c128{h[degree + k].re, h[degree + k].im};
+  }
+  *r_inf = hp_c128{h[2 * (size_t)degree].re, h[2 * (size_t)degree].im};
   return HP_OK;
 }
 

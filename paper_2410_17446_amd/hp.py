@@ -22,7 +22,7 @@ HP_GUESS_ZERO, HP_GUESS_PREV, HP_GUESS_LEARNED = 0, 1, 2
 HP_FORM_EXP, HP_FORM_SQRT = 0, 1
 
 SYMBOLS = ("hp_workspace_bytes", "hp_plan_create", "hp_set_medium", "hp_step", "hp_solve", "hp_propagate",
-           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_set_pml", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
+           "hp_step_guess", "hp_set_guess", "hp_autotune", "hp_set_launch", "hp_batch_set_launch", "hp_set_form", "hp_set_pml", "hp_fit_exp_sqrt", "hp_get_solution", "hp_apply_medium", "hp_get_stats",
            "hp_set_fixed_iters", "hp_apply_operator", "hp_apply_preconditioner",
            "hp_apply_preconditioner_noalloc",
            "hp_profile", "hp_profile_read", "hp_profile_sample", "hp_profile_totals", "hp_last_error",
@@ -69,6 +69,8 @@ def lib():
         L.hp_set_launch.argtypes = [vp, C.c_int]
         L.hp_batch_set_launch.argtypes = [vp, ip]
         L.hp_set_pml.argtypes = [vp, C.c_double, vp, vp, vp]
+        L.hp_fit_exp_sqrt.argtypes = [C.c_double, C.c_int, C.c_int, vp, C.POINTER(hp_c128), C.POINTER(hp_c128),
+                                      C.POINTER(hp_c128), dp]
         L.hp_get_solution.argtypes = [vp, C.c_int, vp]
         L.hp_apply_medium.argtypes = [vp, vp, vp]
         L.hp_get_stats.argtypes = [vp, ip, dp]
@@ -103,6 +105,21 @@ def _ptr(t) -> int | None:
     if not t.is_contiguous():
         raise HPError("tensor must be contiguous")
     return t.data_ptr()
+
+
+def fit_exp_sqrt(K, degree, lawson_steps=40, stream=None):
+    """The rational fit of exp(iK sqrt(1+z)) computed on the GPU (hp_fit_exp_sqrt): (poles,
+    residues, r_inf, max_err) as numpy complex arrays, a complex and a float."""
+    L = lib()
+    P = (hp_c128 * degree)()
+    R = (hp_c128 * degree)()
+    r = hp_c128()
+    e = C.c_double()
+    rc = L.hp_fit_exp_sqrt(float(K), int(degree), int(lawson_steps), stream, P, R, C.byref(r), C.byref(e))
+    if rc < 0:
+        raise HPError(f"hp_fit_exp_sqrt: {rc}: {L.hp_last_error(None).decode()}")
+    return (np.array([complex(x.re, x.im) for x in P]), np.array([complex(x.re, x.im) for x in R]),
+            complex(r.re, r.im), float(e.value))
 
 
 class Plan:

@@ -133,3 +133,16 @@ def test_pole_on_the_free_space_spectrum_is_rejected_on_the_host():
     out = C.c_void_p()
     assert L.hp_plan_create(C.byref(d), None, None, C.byref(out)) == -1 and not out.value
     assert b"spectrum" in L.hp_last_error(None)
+
+
+def test_device_fit_validates_on_the_host():
+    """hp_fit_exp_sqrt rejects bad arguments before touching a GPU, with a message."""
+    L = hp.lib()
+    P = (hp.hp_c128 * 8)()
+    R = (hp.hp_c128 * 8)()
+    r = hp.hp_c128()
+    assert L.hp_fit_exp_sqrt(0.0, 8, 40, None, P, R, C.byref(r), None) == -1
+    assert b"K must be" in L.hp_last_error(None)
+    assert L.hp_fit_exp_sqrt(6.28, 32, 40, None, P, R, C.byref(r), None) == -1
+    assert b"degree" in L.hp_last_error(None)
+    assert L.hp_fit_exp_sqrt(6.28, 8, 40, None, None, R, C.byref(r), None) == -1
