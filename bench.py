@@ -25,7 +25,8 @@ propagator's own solves supplies GMRES starting points; timed against the plain
 method and the previous-step start on scalar1024), unet (training steps of that
 U-Net at its training shape), copy (the HBM reference for the counters) and
 pml512 (absorbing layers: 512^2 with PML layers of 64 cells, the eigen-route
-Sylvester preconditioner's dense products), sqrt1024 (the scalar1024 workload
+Sylvester preconditioner's dense products), fit (the rational fit on the device
+against the host's), sqrt1024 (the scalar1024 workload
 through the pseudo-differential form: 25
 Cauchy-integral terms of sqrt(1+z), alpha = 1, eight RK4 substeps of lambda/8
 per lambda step, FP64; the field is compared with the exponential form's after
@@ -657,6 +658,44 @@ def cpu_baseline_pml(cfg, tab, w, n2):
                        f"numpy/scipy BLAS and LAPACK threads as the box sets them")
 
 
+def run_fit(args):
+    """The rational fit of Sec. 3.1 on the device (hp_fit_exp_sqrt) against the host's (tables.RationalFit):
+    time per fit and the largest sample error of each, for the step sizes of the workloads (dz = lambda,
+    16 poles), the beam runs (dz = lambda/20, n0 = 1.0003, 25 poles) and a quarter-wave step."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17446_amd import hp, inputs, tables
+    torch.cuda.synchronize()
+    hp.fit_exp_sqrt(inputs.K0, 8)           # module load and first launch, outside the timings
+    cases = [("dz=lambda", inputs.K0, 16), ("dz=lambda/4", inputs.K0 / 4, 12),
+             ("beam dz=lambda/20", inputs.K0 * 1.0003 * 0.05, 25)]
+    out = {}
+    for name, K, deg in cases:
+        t0 = time.perf_counter()
+        p, r, ri, e_dev = hp.fit_exp_sqrt(K, deg)
+        t_dev = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        f = tables.RationalFit(K, deg)
+        t_host = time.perf_counter() - t0
+        z = np.linspace(-4, 2, 4001)
+        e_host = float(np.abs(f(z) - tables.exp_sqrt(z, K)).max())
+        out[name] = {"K": K, "poles": deg, "device_s": t_dev, "host_s": t_host, "device_max_err": e_dev,
+                     "host_max_err": e_host}
+        print(f"# {name}: device {t_dev * 1e3:.0f} ms ({e_dev:.2e}), host {t_host * 1e3:.0f} ms ({e_host:.2e})",
+              file=sys.stderr, flush=True)
+    tot_dev = sum(v["device_s"] for v in out.values())
+    line = {"metric": "rational fits/s (AAA-Lawson of exp(iK sqrt(1+z)), 4001 samples, 40 Lawson steps)",
+            "value": len(out) / tot_dev, "unit": "fits/s", "n_gpus": 1, "steps": len(out), "warmup": 1,
+            "ms_per_step": 1e3 * tot_dev / len(out), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "fit", "cases": [c[0] for c in cases]},
+            "fits": out,
+            "host_fits_per_s": len(out) / sum(v["host_s"] for v in out.values())}
+    print(json.dumps(line))
+    return 0
+
+
 def run_sqrt(args):
     """scalar1024 through the pseudo-differential form (FP64), compared with the exponential form."""
     import numpy as np
@@ -727,6 +766,8 @@ def main():
         return run_sineprod(args)
     if args.config == "pml512":
         return run_pml(args)
+    if args.config == "fit":
+        return run_fit(args)
     import numpy as np
     import torch
 

@@ -223,51 +223,51 @@ __device__ void f_min_right_sv(const FitArgs& A, int c, FitShared& sh, c128* R, 
   }
   __syncthreads();
   const int cp = c + (c & 1);  // players of the round-robin; player c is a bye when c is odd
+  // a wave per column pair (lane i holds row i), pairs of a round spread over the waves;
+  // a pair is rotated while its columns' inner product exceeds 1e-14 of their norms
+  const int wave = tid >> 6, lane = tid & 63;
+  auto wsum = [](double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return __shfl(v, 0, 64);  // every lane takes lane 0's sum
+  };
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) sh.flag = 0;
     __syncthreads();
     for (int round = 0; round < cp - 1; ++round) {
-      if (tid < cp / 2) {
+      for (int slot = wave; slot < cp / 2; slot += FWAVES) {
         int p, q;
-        if (tid == 0) {
+        if (slot == 0) {
           p = round;
           q = cp - 1;
         } else {
-          p = (round + tid) % (cp - 1);
-          q = (round - tid + (cp - 1)) % (cp - 1);
+          p = (round + slot) % (cp - 1);
+          q = (round - slot + (cp - 1)) % (cp - 1);
         }
-        if (p < c && q < c) {
-          c128* rp = R + (size_t)p * FMAXC;
-          c128* rq = R + (size_t)q * FMAXC;
-          double al = 0.0, be = 0.0;
-          c128 ga = mk(0.0, 0.0);
-          for (int i = 0; i < c; ++i) {
-            al += abs2(rp[i]);
-            be += abs2(rq[i]);
-            ga = ga + cmulc(rp[i], rq[i]);
-          }
-          const double g = sqrt(abs2(ga));
-          if (g > 1e-15 * sqrt(al * be) && g > 0.0) {
-            const double zeta = (be - al) / (2.0 * g);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-            const c128 ph = mk(ga.re / g, ga.im / g);  // e^{i phi}
-            const c128 phc = f_conj(ph);
-            for (int i = 0; i < c; ++i) {
-              const c128 x = rp[i], y = rq[i];
-              rp[i] = cs * x - sn * (phc * y);
-              rq[i] = sn * (ph * x) + cs * y;
-            }
-            c128* vp = V + (size_t)p * FMAXC;
-            c128* vq = V + (size_t)q * FMAXC;
-            for (int i = 0; i < c; ++i) {
-              const c128 x = vp[i], y = vq[i];
-              vp[i] = cs * x - sn * (phc * y);
-              vq[i] = sn * (ph * x) + cs * y;
-            }
-            sh.flag = 1;
-          }
+        if (p >= c || q >= c) continue;
+        c128* rp = R + (size_t)p * FMAXC;
+        c128* rq = R + (size_t)q * FMAXC;
+        const c128 x = lane < c ? rp[lane] : mk(0.0, 0.0), y = lane < c ? rq[lane] : mk(0.0, 0.0);
+        const double al = wsum(abs2(x)), be = wsum(abs2(y));
+        const c128 xy = cmulc(x, y);
+        const c128 ga = mk(wsum(xy.re), wsum(xy.im));
+        const double g = sqrt(abs2(ga));
+        if (!(g > 1e-14 * sqrt(al * be) && g > 0.0)) continue;
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        const c128 ph = mk(ga.re / g, ga.im / g);  // e^{i phi}
+        const c128 phc = f_conj(ph);
+        if (lane < c) {
+          rp[lane] = cs * x - sn * (phc * y);
+          rq[lane] = sn * (ph * x) + cs * y;
+          c128* vp = V + (size_t)p * FMAXC;
+          c128* vq = V + (size_t)q * FMAXC;
+          const c128 u = vp[lane], w = vq[lane];
+          vp[lane] = cs * u - sn * (phc * w);
+          vq[lane] = sn * (ph * u) + cs * w;
         }
+        if (lane == 0) sh.flag = 1;
       }
       __syncthreads();
     }
@@ -321,7 +321,7 @@ __device__ int f_partial_fractions(int n, const c128* a, const c128* b, FitShare
     sh.flag = 0;
   }
   __syncthreads();
-  for (int it = 0; it < 500; ++it) {
+  for (int it = 0; it < 200; ++it) {
     double step = 0.0;
     if (tid < np) {
       const c128 zi = sh.z[tid];
@@ -347,7 +347,7 @@ __device__ int f_partial_fractions(int n, const c128* a, const c128* b, FitShare
     const double mx = f_block_max(tid < np ? step : 0.0, sh.red);
     if (tid < np) sh.z[tid] = sh.zn[tid];
     __syncthreads();
-    if (mx < 1e-15) break;
+    if (mx < 1e-14) break;
   }
   // residues and the value at infinity
   if (tid == 0) {
