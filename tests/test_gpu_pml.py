@@ -75,7 +75,7 @@ def test_pml_operator_matches_oracle(pole):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
-@pytest.mark.parametrize("N,sm", [(64, 1.0), (128, 1.0), (128, 4.0), (256, 10.0)])
+@pytest.mark.parametrize("N,sm", [(64, 1.0), (128, 1.0), (128, 4.0), (192, 10.0), (256, 10.0)])
 def test_pml_preconditioner_matches_oracle(N, sm, variant):
     """Every form of the dense stages (vector ALU; matrix cores with the tile chosen by the round's
     workgroup count, on 32 x 32 and on 64 x 64 tiles)."""
@@ -115,6 +115,27 @@ def test_pml_step_replayed_iterations(variant):
     assert rel_l2(out.cpu().numpy()[0], ref) < 1e-9
     it, _ = plan.stats()
     assert it == counts
+
+
+def test_pml_step_on_a_three_tile_grid():
+    """N = 192 (3 x 64: an odd number of 64-wide tiles, six 32-wide ones), 24-cell layers: one
+    step with the oracle's counts replayed, by every dense-stage form."""
+    torch = _cuda()
+    wl, g = _setup(N=192, W=24, sm=10.0, medium=("sine", 0.02, 2.0))
+    w = _tilted_beam(192, waist=4.0)
+    V = pml.medium(g, wl["n2"])
+    f = wl["fit"]
+    ref, res = pml.step(g, V, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+    counts = [r.iters for r in res]
+    assert all(r.cycles == 1 for r in res)
+    plan, _ = _plan(wl, g)
+    plan.set_fixed_iters(counts)
+    plan.set_medium(to_gpu(wl["n2"]))
+    for variant in (0, 1, 2, 3):
+        plan.set_launch(variant)
+        out = plan.step(to_gpu(w[None]))
+        assert rel_l2(out.cpu().numpy()[0], ref) < 1e-9, variant
+        assert plan.stats()[0] == counts
 
 
 def test_pml_step_own_tolerance_and_solve():
