@@ -133,3 +133,57 @@ def step(g: PMLGrid, V, w, poles, residues, r_inf, dz, tol, restart=30, schedule
         acc = acc + a * r.x
         res.append(r)
     return np.exp(-1j * K) * op.unpack(acc, 1, g.N)[0], res
+
+
+# ---------------------------------------------------------------- vector fields (E_x, E_y)
+
+def vector_grid(g: PMLGrid) -> op.Grid:
+    """The plain operator's grid with its edge region set to the PML width (and no loss): the
+    coefficient planes V and psi of eq. Z_bar_eq are then zero inside the layers."""
+    return op.Grid(N=g.N, dx=g.h, dy=g.h, k0=g.k0, n0=g.n0, c=g.c, d=g.d, W=g.W, eta_max=0.0)
+
+
+def apply_shifted_vector(g: PMLGrid, co, w: np.ndarray, b: complex, D=None, D0=None) -> np.ndarray:
+    """(Zbar~ - b I) w for a vector field w (2, N, N): eq. Z_bar_eq with the stretched transverse
+    second derivatives.  co: op.coefficients(vector_grid(g), n2, True).  The psi terms and V vanish
+    in the layers, the only rows whose first derivatives the stretching changes; elsewhere g = 1, so
+    the plain operator's psi terms are the stretched operator's, and only its Laplacian rows change:
+    the plain s (D2x + D2y) is replaced by s (D2x~ + D2y~) in each component."""
+    D = d2_stretched_matrix(g) if D is None else D
+    if D0 is None:
+        D0 = d2_stretched_matrix(PMLGrid(g.N, g.h, g.k0, g.n0, g.c, g.d, g.W, 0.0))
+    out = op.apply_shifted(vector_grid(g), co, w, b)
+    for c in range(2):
+        u = w[c, 1:, 1:]
+        out[c, 1:, 1:] += g.s * ((u @ D.T + D @ u) - (u @ D0.T + D0 @ u))
+    return out
+
+
+def solve_pole_vector(g: PMLGrid, co, w, b_k, tol, restart=30, schedule=None, D=None, D0=None):
+    """The shifted vector solve; the preconditioner is the Sylvester solve per component (the
+    free-space operator does not couple E_x and E_y)."""
+    D = d2_stretched_matrix(g) if D is None else D
+    if D0 is None:
+        D0 = d2_stretched_matrix(PMLGrid(g.N, g.h, g.k0, g.n0, g.c, g.d, g.W, 0.0))
+    N = g.N
+    A = lambda x: op.pack(apply_shifted_vector(g, co, op.unpack(x, 2, N), b_k, D, D0))
+
+    def Minv(v):
+        y = op.unpack(v, 2, N)
+        return op.pack(np.stack([apply_minv(g, y[c], b_k, D) for c in range(2)]))
+
+    return gmres(A, Minv, op.pack(w), tol, restart=restart, schedule=schedule)
+
+
+def step_vector(g: PMLGrid, co, w, poles, residues, r_inf, dz, tol, restart=30, schedules=None):
+    """One step of eq. approx_prop for a vector field with the PML operator."""
+    D = d2_stretched_matrix(g)
+    D0 = d2_stretched_matrix(PMLGrid(g.N, g.h, g.k0, g.n0, g.c, g.d, g.W, 0.0))
+    K = g.k0 * g.n0 * dz
+    acc = r_inf * op.pack(w)
+    res = []
+    for k, (b, a) in enumerate(zip(poles, residues)):
+        r = solve_pole_vector(g, co, w, b, tol, restart, None if schedules is None else schedules[k], D, D0)
+        acc = acc + a * r.x
+        res.append(r)
+    return np.exp(-1j * K) * op.unpack(acc, 2, g.N), res

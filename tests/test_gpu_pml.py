@@ -203,3 +203,56 @@ def test_pml_mode_switches():
     plan.set_guess(hp.HP_GUESS_PREV)
     out = plan.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
     assert np.isfinite(out.cpu().numpy()).all()
+
+
+def test_pml_failure_modes():
+    """A NaN in n^2 stops every pole (HP_EINVAL with a message) and the plan then steps a valid
+    medium as before; GMRES(2) with one cycle returns HP_WARN_NOCONV with each pole's one-cycle
+    iterate, which equals the oracle's with the same schedule."""
+    torch = _cuda()
+    from paper_2410_17446_amd import hp
+    wl, g = _setup()
+    w = _tilted_beam(64)
+    V = pml.medium(g, wl["n2"])
+    f = wl["fit"]
+    plan, _ = _plan(wl, g)
+    bad = wl["n2"].copy()
+    bad[32, 30] = np.nan
+    with pytest.raises(hp.HPError, match="NaN or Inf"):
+        plan.step(to_gpu(w[None]), to_gpu(bad))
+    ref, res = pml.step(g, V, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+    out = plan.step(to_gpu(w[None]), to_gpu(wl["n2"]))
+    assert rel_l2(out.cpu().numpy()[0], ref) < 1e-8
+    plan.close()
+    K = len(f["poles"])
+    assert min(r.iters for r in res) > 2            # no pole converges within two steps
+    ref2, res2 = pml.step(g, V, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10, restart=2,
+                          schedules=[[2]] * K)
+    plan = hp.Plan(nx=64, ny=64, dx=0.25, dy=0.25, k0=K0, n0=1.0, dz=1.0, ncomp=1, poles=f["poles"],
+                   residues=f["residues"], r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"], edge_width=12,
+                   edge_eta=0.25, tol=1e-10, restart=2, max_cycles=1)
+    plan.set_pml(g.sigma_max, *tables.pml_eigen(64, 0.25, K0, 1.0, 12, g.sigma_max, wl["c"], wl["d"]))
+    out = plan.step(to_gpu(w[None]), to_gpu(wl["n2"]))
+    assert plan.last_status == hp.HP_WARN_NOCONV
+    it, rr = plan.stats()
+    assert it == [2] * K and max(rr) > 1e-10
+    assert rel_l2(out.cpu().numpy()[0], ref2) < 1e-8
+
+
+def test_pml_refuses_other_plans():
+    """The layers are built for scalar FP64 plans on square grids: a vector plan, a mixed-precision
+    plan and a 64 x 128 plan refuse them, and stay usable."""
+    _cuda()
+    from paper_2410_17446_amd import hp
+    wl, g = _setup()
+    f = wl["fit"]
+    Q, Qi, lam = tables.pml_eigen(64, 0.25, K0, 1.0, 12, 1.0, wl["c"], wl["d"])
+    common = dict(dx=0.25, dy=0.25, k0=K0, n0=1.0, dz=1.0, poles=f["poles"], residues=f["residues"],
+                  r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"], edge_width=12, edge_eta=0.25, tol=1e-10,
+                  restart=30, max_cycles=20)
+    for kw in (dict(nx=64, ny=64, ncomp=2, precision=0), dict(nx=64, ny=64, ncomp=1, precision=hp.HP_MIXED),
+               dict(nx=64, ny=128, ncomp=1, precision=0)):
+        plan = hp.Plan(**common, **kw)
+        with pytest.raises(hp.HPError):
+            plan.set_pml(1.0, Q, Qi, lam)
+        plan.close()

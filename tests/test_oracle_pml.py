@@ -111,3 +111,68 @@ def test_pml_absorbs_a_beam_leaving_the_domain():
     assert p < 1e-2
     _, p0 = run(64, 12, 0.0, 24)
     assert p0 > 0.5
+
+
+def test_vector_pml_operator_reduces_to_the_scalar_one_in_a_homogeneous_medium():
+    """With n = n0 (psi = 0, V = 0) the vector operator decouples: each component is the scalar
+    PML operator.  This pins the replacement of the plain Laplacian rows by the stretched ones (a
+    plain Laplacian left in, or a wrong sign, fails)."""
+    g = _grid(40, 8, 1.5)
+    co = op.coefficients(pml.vector_grid(g), np.ones((40, 40)), True)
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal((2, 40, 40)) + 1j * rng.standard_normal((2, 40, 40))
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    b = -0.4 - 0.02j
+    out = pml.apply_shifted_vector(g, co, w, b)
+    V = pml.medium(g, np.ones((40, 40)))
+    for c in range(2):
+        ref = pml.apply_shifted(g, V, w[c], b)
+        assert np.abs(out[c] - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_vector_pml_operator_keeps_the_coupling_in_the_interior():
+    """Away from the layers (every stencil point outside them) the vector PML operator is the plain
+    vector operator of eq. Z_bar_eq, psi coupling included; inside the layers it is the scalar PML
+    operator per component (psi and V are zero there)."""
+    N, W = 48, 8
+    g = _grid(N, W, 2.0)
+    x = (np.arange(N) - N / 2) * g.h
+    X, Y = np.meshgrid(x, x)
+    n2 = (1 + 0.05 * np.sin(2 * np.pi * X / 2.0) * np.sin(2 * np.pi * Y / 2.0)) ** 2
+    og = pml.vector_grid(g)
+    co = op.coefficients(og, n2, True)
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    b = -1.1 - 0.07j
+    out = pml.apply_shifted_vector(g, co, w, b)
+    plain = op.apply_shifted(og, co, w, b)
+    inner = slice(W + 7, N - W - 6)
+    assert np.abs(out[:, inner, inner] - plain[:, inner, inner]).max() < 1e-12 * np.abs(plain).max()
+    assert np.abs(co.psi_x[inner, inner]).max() > 1e-3         # the coupling is really there
+    V = pml.medium(g, n2)
+    edge = (slice(1, W + 1), slice(1, N))
+    for c in range(2):
+        ref = pml.apply_shifted(g, V, w[c], b)
+        assert np.abs(out[c][edge] - ref[edge]).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_vector_pml_step_of_a_decoupled_field_is_the_scalar_step():
+    """In a homogeneous medium an x-polarised beam stays x-polarised and its step is the scalar
+    PML step (the solves and the weighted sum per component)."""
+    N, W = 32, 6
+    g = _grid(N, W, 1.0)
+    f = fit.fit_exp_sqrt(K2PI, 6)
+    x = (np.arange(N) - N / 2) * g.h
+    X, Y = np.meshgrid(x, x)
+    u = np.exp(-(X ** 2 + Y ** 2) / 1.5 ** 2) * np.exp(1j * K2PI * 0.4 * X)
+    u[0, :] = 0
+    u[:, 0] = 0
+    w = np.stack([u, np.zeros_like(u)])
+    co = op.coefficients(pml.vector_grid(g), np.ones((N, N)), True)
+    out, _ = pml.step_vector(g, co, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-11)
+    ref, _ = pml.step(g, pml.medium(g, np.ones((N, N))), u, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-11)
+    assert np.abs(out[1]).max() < 1e-12
+    assert np.abs(out[0] - ref).max() < 1e-9 * np.abs(ref).max()
