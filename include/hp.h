@@ -266,7 +266,9 @@ int hp_fit_exp_sqrt(double K, int degree, int lawson_steps, void* stream, hp_c12
  *   d^2/dx~^2 = (1/g^2) d^2/dx^2 - (g'/g^3) d/dx,
  * discretised node by node with the plan's 13-point D2 and D1 (odd
  * reflection about the Dirichlet nodes) and the exact derivative g'.  Zbar
- * keeps its medium term V = (n^2 - n0^2)/n0^2, zero inside the layers; the
+ * keeps its medium term V = (n^2 - n0^2)/n0^2 and, for vector fields, its psi
+ * coupling, both zero inside the layers (so only the Laplacian rows of the
+ * layers change, in each component); the
  * free-space problem of pole b_k is the Sylvester equation of Sec. 4.2 eq.
  * fs_sylvester with the stretched matrices, solved by eigen-decomposition of
  * the one-axis operator s D~ = Q diag(lam) Q^-1 (s = 1/(k0 n0)^2; both axes
@@ -284,7 +286,7 @@ int hp_fit_exp_sqrt(double K, int degree, int lawson_steps, void* stream, hp_c12
  * make Q so ill-conditioned, cond(Q) above 1e13, that its rounding breaks that
  * bound) and that no pole meets lam_p + lam_q.  The first call allocates the tables, one field
  * per pole and the inner-product partials (hipMalloc), freed with the plan.
- * Requires ncomp = 1, nx = ny, dx = dy, HP_FP64 (HP_EINVAL otherwise), the
+ * Requires nx = ny, dx = dy, HP_FP64 (HP_EINVAL otherwise; ncomp 1 or 2), the
  * exponential form and HP_GUESS_ZERO (HP_ESTATE otherwise); while the layers
  * are set hp_set_form, hp_set_guess and hp_step_guess with guesses return
  * HP_ESTATE, hp_apply_operator and hp_apply_preconditioner apply the stretched

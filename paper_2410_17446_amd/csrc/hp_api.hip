@@ -419,17 +419,18 @@ void pml_prec(hp_plan p, const PoleState* st, const int* list, int n, int* activ
   const size_t fn = p->fieldn;
   const PmlRef a{nullptr, bufA, fn, 0}, b{nullptr, bufB, fn, 0};
   const int v = p->geo.col_variant;  // the launch variant picks the dense stages' form
-  launch_pml_gemm(v, true, 0, p->pml_qi, in, a, st, list, n, active_out, p->pml_lam, N, p->stream);
-  launch_pml_gemm(v, false, 1, p->pml_qi, a, b, st, list, n, nullptr, p->pml_lam, N, p->stream);
-  launch_pml_gemm(v, true, 0, p->pml_q, b, a, st, list, n, nullptr, p->pml_lam, N, p->stream);
-  launch_pml_gemm(v, false, 2, p->pml_q, a, out, st, list, n, nullptr, p->pml_lam, N, p->stream);
+  const int nc = p->d.ncomp;
+  launch_pml_gemm(v, true, 0, p->pml_qi, in, a, st, list, n, active_out, p->pml_lam, N, nc, p->stream);
+  launch_pml_gemm(v, false, 1, p->pml_qi, a, b, st, list, n, nullptr, p->pml_lam, N, nc, p->stream);
+  launch_pml_gemm(v, true, 0, p->pml_q, b, a, st, list, n, nullptr, p->pml_lam, N, nc, p->stream);
+  launch_pml_gemm(v, false, 2, p->pml_q, a, out, st, list, n, nullptr, p->pml_lam, N, nc, p->stream);
 }
 
 // Floating-point operations of one pole's four dense stages: 8 n^3 per complex
-// product of n x n matrices, n = N - 1 unknowns per axis.
+// product of n x n matrices, n = N - 1 unknowns per axis, for each component.
 double pml_flops(hp_plan p) {
   const double n = p->d.nx - 1.0;
-  return 4.0 * 8.0 * n * n * n;
+  return 4.0 * 8.0 * n * n * n * p->d.ncomp;
 }
 
 // Guess residuals for several poles at once: one buffer and one set of
@@ -459,7 +460,7 @@ int restart_from_residuals(hp_plan p, const std::vector<int>& rs, const std::vec
     Prof pr(p, HP_K_ROW_FWD, nr * (double)(p->d.nx - 1) * (p->d.ny - 1) * p->d.ncomp * (16.0 + sizeof(cx<T>)));
     if (p->pml)
       launch_pml_copy(p->guess_r, fn, rj.data(), reinterpret_cast<c128*>(p->U), ustride, rs.data(), nr,
-                      p->guess_rpart, rblk, (int)rblk, p->d.nx, p->stream);
+                      p->guess_rpart, rblk, (int)rblk, p->d.nx, p->d.ncomp, p->stream);
     else
       launch_row_fwd_batch<T, C>(p->guess_r, fn, rj.data(), fld<T>(p->U, 0, fn), ustride, rs.data(), nr,
                                  p->guess_rpart, rblk, reinterpret_cast<const cx<C>*>(p->tw_x), p->geo, p->stream);
@@ -514,7 +515,7 @@ int check_poles(hp_plan p, const std::vector<int>& chk, const c128* w, int beta_
         HPCHK(hipMemcpyAsync(p->guess_x + (size_t)a * fn, p->X + (size_t)chk[a] * fn, fn * sizeof(c128),
                              hipMemcpyDeviceToDevice, p->stream));
       launch_pml_residual(p->guess_x, fn, w, p->guess_r, fn, p->coef, p->pml_a2, p->pml_a1, p->sc, shifts.data(), n,
-                          p->guess_part, p->nopblk, p->nopblk, p->d.nx, p->stream);
+                          p->guess_part, p->nopblk, p->nopblk, p->d.nx, p->d.ncomp, p->stream);
     } else {
       launch_row_inv_batch<double>(p->X, fn, chk.data(), n, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
                                    p->stream);
@@ -624,7 +625,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     if (p->pml) {
       const int zero = 0;
       launch_pml_copy(w, 0, &zero, reinterpret_cast<c128*>(bR), 0, &zero, 1, p->part_misc, 0, p->nrowblk * d.ncomp,
-                      d.nx, p->stream);
+                      d.nx, d.ncomp, p->stream);
     } else {
       launch_row_fwd<T, C>(w, bR, p->part_misc, twx, p->geo, p->stream);
     }
@@ -682,7 +683,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       const int mm = f.ms[a];
       ++nw;
       col += 1.0 + outs;                                         // u_m read, z (+ D1y z) written
-      row += (d.ncomp == 2 ? 3.0 : 2.0) + (mm + 1.0);           // z (+ D1y z), p, u_0..u_m
+      row += (d.ncomp == 2 && !p->pml ? 3.0 : 2.0) + (mm + 1.0);  // z (+ D1y z), p, u_0..u_m
       upd += 1.0 + (mm + 1.0) + 1.0 + (mm > 0 ? 1.0 : 0.0);     // p, u_0..u_m, u_{m+1}, rewritten u_m
       if (f.sh[a]) {
         ++shared;
@@ -752,7 +753,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       {
         Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
         launch_pml_apply(Zc, zsp, zsi, Pc, psp, uc, p->coef, p->pml_a2, p->pml_a1, p->sc, p->st, ad, na, p->pml_part,
-                         d.nx, p->stream);
+                         d.nx, d.ncomp, p->stream);
       }
       {
         Prof pr(p, HP_K_SMALL, 0.0);
@@ -918,7 +919,7 @@ int solve_and_sum(hp_plan p, const c128* w, c128* out, c128 phase, c128 rinf_pha
     Prof pr(p, HP_K_FINAL, U1 * (es * terms + 32.0));
     if (p->pml)  // the layers absorb: no separate loss
       launch_pml_final(w, out, reinterpret_cast<c128*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
-                       p->fieldn, p->st, K, phase, rinf_phase, d.nx, p->stream);
+                       p->fieldn, p->st, K, phase, rinf_phase, d.nx, d.ncomp, p->stream);
     else
       launch_final<T>(w, out, reinterpret_cast<cx<T>*>(p->Z), (size_t)d.restart * p->fieldn, p->fieldn, p->X,
                       p->fieldn, p->st, K, phase, rinf_phase, loss_coef, d.edge_eta, d.edge_width, p->tw64_x,
@@ -1472,8 +1473,7 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
     return HP_OK;
   }
   const hp_plan_desc& d = p->d;
-  if (d.ncomp != 1 || d.nx != d.ny || d.dx != d.dy)
-    return fail(p, HP_EINVAL, "absorbing layers need a scalar plan (ncomp = 1) on a square grid (nx = ny, dx = dy)");
+  if (d.nx != d.ny || d.dx != d.dy) return fail(p, HP_EINVAL, "absorbing layers need a square grid (nx = ny, dx = dy)");
   if (d.precision != HP_FP64) return fail(p, HP_EINVAL, "absorbing layers need precision HP_FP64");
   if (!(sigma_max > 0.0) || !std::isfinite(sigma_max)) return fail(p, HP_EINVAL, "sigma_max must be finite and > 0");
   if (!Q || !Qinv || !lam) return fail(p, HP_EINVAL, "Q, Qinv, lam must all be given");
@@ -1714,7 +1714,7 @@ int hp_apply_operator(hp_plan p, int pole, const void* x, void* y) {
   const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
   if (p->pml)
     launch_pml_residual(reinterpret_cast<const c128*>(x), 0, nullptr, reinterpret_cast<c128*>(y), 0, p->coef,
-                        p->pml_a2, p->pml_a1, p->sc, &b, 1, nullptr, 0, p->nopblk, p->d.nx, p->stream);
+                        p->pml_a2, p->pml_a1, p->sc, &b, 1, nullptr, 0, p->nopblk, p->d.nx, p->d.ncomp, p->stream);
   else
     launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, b, p->sc, p->geo,
                     nullptr, p->stream);

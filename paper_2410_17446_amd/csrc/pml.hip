@@ -38,13 +38,17 @@ constexpr int GT = 64, GK = 16, GWG = 256;
 template <bool LEFT, int EPI>
 __global__ __launch_bounds__(GWG) void k_pml_gemm(const c128* __restrict__ mat, PmlRef in, PmlRef out,
                                                   const PoleState* __restrict__ st, PoleList list,
-                                                  int* __restrict__ active_out, const c128* __restrict__ lam, int N) {
-  const int k = list.k[blockIdx.z];
-  if (active_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[blockIdx.z] = k;
+                                                  int* __restrict__ active_out, const c128* __restrict__ lam, int N,
+                                                  int ncomp) {
+  // blockIdx.z: pole list entry a, field component comp (components are N x N planes)
+  const int a_ = blockIdx.z / ncomp, comp = blockIdx.z % ncomp;
+  const int k = list.k[a_];
+  if (active_out && comp == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[a_] = k;
   if (st[k].flag) return;
   const int m = st[k].m;
-  const c128* __restrict__ X = pml_field(in, k, m);
-  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m));
+  const size_t co = (size_t)comp * N * N;
+  const c128* __restrict__ X = pml_field(in, k, m) + co;
+  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m)) + co;
   const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   // A[r][j] = Mat[r][j] (left) or X[r][j] (right); B[j][c] = X[j][c] (left) or Mat[c][j] (right)
@@ -130,14 +134,16 @@ template <bool LEFT, int EPI, int BT>
 __global__ __launch_bounds__(GWG, 4) void k_pml_gemm_mfma(const c128* __restrict__ mat, PmlRef in, PmlRef out,
                                                        const PoleState* __restrict__ st, PoleList list,
                                                        int* __restrict__ active_out, const c128* __restrict__ lam,
-                                                       int N) {
+                                                       int N, int ncomp) {
   constexpr int WT = BT / 2, MB = WT / 16, LPT = BT * GK / GWG;
-  const int k = list.k[blockIdx.z];
-  if (active_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[blockIdx.z] = k;
+  const int a_ = blockIdx.z / ncomp, comp = blockIdx.z % ncomp;
+  const int k = list.k[a_];
+  if (active_out && comp == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) active_out[a_] = k;
   if (st[k].flag) return;
   const int m = st[k].m;
-  const c128* __restrict__ X = pml_field(in, k, m);
-  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m));
+  const size_t co = (size_t)comp * N * N;
+  const c128* __restrict__ X = pml_field(in, k, m) + co;
+  c128* __restrict__ Y = const_cast<c128*>(pml_field(out, k, m)) + co;
   // right products: consecutive workgroups (spread over the XCDs) take consecutive row
   // tiles, so each XCD keeps its row slabs of the field operand
   const int r0 = (LEFT ? blockIdx.y : blockIdx.x) * BT, c0 = (LEFT ? blockIdx.x : blockIdx.y) * BT;
@@ -253,14 +259,18 @@ __device__ __forceinline__ c128 pml_ld(const c128* __restrict__ x, int i, int j,
   return sg * x[(size_t)i * N + j];
 }
 
-// (Zbar~ - b I) x at interior node (i, j): the stretched stencils along both
-// axes plus (V - b) x
-__device__ __forceinline__ c128 pml_op(const c128* __restrict__ x, int i, int j, int N, const double* __restrict__ V,
-                                       const c128* __restrict__ a2, const c128* __restrict__ a1, const StencilCoef& sc,
-                                       c128 b) {
-  const size_t idx = (size_t)i * N + j;
-  const c128 ctr = x[idx];
-  c128 sxx = sc.c2x[0] * ctr, syy = sc.c2x[0] * ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
+// Stencil sums of one component at interior node (i, j): the stretched
+// Laplacian s (D2x~ + D2y~) x, the plain first derivatives D1x x and D1y x
+// (the psi coupling's; it is zero where the stretching acts) and x itself.
+struct PmlPoint {
+  c128 lap, dx, dy, ctr;
+};
+__device__ __forceinline__ PmlPoint pml_point(const c128* __restrict__ x, int i, int j, int N,
+                                              const c128* __restrict__ a2, const c128* __restrict__ a1,
+                                              const StencilCoef& sc) {
+  PmlPoint r;
+  r.ctr = x[(size_t)i * N + j];
+  c128 sxx = sc.c2x[0] * r.ctr, syy = sc.c2x[0] * r.ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
 #pragma unroll
   for (int mm = 1; mm <= 6; ++mm) {
     const c128 xp = pml_ld(x, i, j + mm, N), xm = pml_ld(x, i, j - mm, N);
@@ -270,12 +280,39 @@ __device__ __forceinline__ c128 pml_op(const c128* __restrict__ x, int i, int j,
     syy = syy + sc.c2x[mm] * (yp + ym);
     sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
   }
-  return (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1) + (V[idx] * ctr - b * ctr);
+  r.lap = (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1);
+  r.dx = sx1;
+  r.dy = sy1;
+  return r;
 }
 
+// (Zbar~ - b I) x at interior node (i, j) for the NC components of x (planes fsz
+// apart): the stretched Laplacian plus (V - b) x, and for vector fields the psi
+// coupling of eq. Z_bar_eq (coefficient planes 1..5: s psi_x, s psi_y, s psi_xx,
+// s psi_yy, s psi_xy, zero in the layers).
+template <int NC>
+__device__ __forceinline__ void pml_op(const c128* __restrict__ x, int i, int j, int N,
+                                       const double* __restrict__ coef, const c128* __restrict__ a2,
+                                       const c128* __restrict__ a1, const StencilCoef& sc, c128 b, c128* out) {
+  const size_t fsz = (size_t)N * N, idx = (size_t)i * N + j;
+  const double V = coef[idx];
+  PmlPoint pt[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) pt[c] = pml_point(x + c * fsz, i, j, N, a2, a1, sc);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = pt[c].lap + (V * pt[c].ctr - b * pt[c].ctr);
+  if constexpr (NC == 2) {
+    const double px = coef[fsz + idx], py = coef[2 * fsz + idx], pxx = coef[3 * fsz + idx],
+                 pyy = coef[4 * fsz + idx], pxy = coef[5 * fsz + idx];
+    out[0] = out[0] + pxx * pt[0].ctr + px * pt[0].dx + pxy * pt[1].ctr + py * pt[1].dx;
+    out[1] = out[1] + pxy * pt[0].ctr + px * pt[0].dy + pyy * pt[1].ctr + py * pt[1].dy;
+  }
+}
+
+template <int NC>
 __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x, size_t xbs,
                                                       const c128* __restrict__ rhs, c128* __restrict__ y, size_t ybs,
-                                                      const double* __restrict__ V, const c128* __restrict__ a2,
+                                                      const double* __restrict__ coef, const c128* __restrict__ a2,
                                                       const c128* __restrict__ a1, StencilCoef sc, ShiftList sh,
                                                       double* __restrict__ part, size_t pbs, int N) {
   __shared__ double red[4];
@@ -287,13 +324,15 @@ __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x
   double nrm = 0.0;
   for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
     const int i = (int)(idx / N), j = (int)(idx % N);
-    c128 v = mk(0.0, 0.0);
-    if (i > 0 && j > 0) {
-      const c128 ax = pml_op(x, i, j, N, V, a2, a1, sc, b);
-      v = rhs ? rhs[idx] - ax : ax;
+    c128 ax[NC];
+    if (i > 0 && j > 0) pml_op<NC>(x, i, j, N, coef, a2, a1, sc, b, ax);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      c128 v = mk(0.0, 0.0);
+      if (i > 0 && j > 0) v = rhs ? rhs[c * fsz + idx] - ax[c] : ax[c];
+      y[c * fsz + idx] = v;
+      nrm += abs2(v);
     }
-    y[idx] = v;
-    nrm += abs2(v);
   }
   const double s = pml_block_sum(nrm, red);
   if (threadIdx.x == 0 && part) part[(size_t)z * pbs + blockIdx.x] = s;
@@ -309,9 +348,10 @@ __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x
 
 constexpr int AP_E = 4;  // elements per thread
 
+template <int NC>
 __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbase, size_t zsp, size_t zsi,
                                                    c128* __restrict__ pbase, size_t psp, c128* const* __restrict__ uptr,
-                                                   const double* __restrict__ V, const c128* __restrict__ a2,
+                                                   const double* __restrict__ coef, const c128* __restrict__ a2,
                                                    const c128* __restrict__ a1, StencilCoef sc,
                                                    const PoleState* __restrict__ st, const int* __restrict__ active,
                                                    double2* __restrict__ part, int nparts, int N) {
@@ -325,19 +365,29 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
   c128* p = pbase + (size_t)k * psp;
   const c128* const* up = uptr + (size_t)k * (HP_MAXM + 1);
   const size_t base = (size_t)blockIdx.x * 256 * AP_E + threadIdx.x;
-  c128 pv[AP_E], um[AP_E];
+  c128 pv[AP_E][NC], um[AP_E][NC];
   {
     const c128* u = up[m];
 #pragma unroll
     for (int e = 0; e < AP_E; ++e) {
       const size_t idx = base + (size_t)e * 256;
-      pv[e] = mk(0.0, 0.0);
-      um[e] = mk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        pv[e][c] = mk(0.0, 0.0);
+        um[e][c] = mk(0.0, 0.0);
+      }
       if (idx < fsz) {
         const int i = (int)(idx / N), j = (int)(idx % N);
-        um[e] = u[idx];
-        if (i > 0 && j > 0) pv[e] = pml_op(z, i, j, N, V, a2, a1, sc, bk) - sg * um[e];
-        p[idx] = pv[e];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) um[e][c] = u[c * fsz + idx];
+        if (i > 0 && j > 0) {
+          c128 az[NC];
+          pml_op<NC>(z, i, j, N, coef, a2, a1, sc, bk, az);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) pv[e][c] = az[c] - sg * um[e][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p[c * fsz + idx] = pv[e][c];
       }
     }
   }
@@ -349,11 +399,14 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
 #pragma unroll
     for (int e = 0; e < AP_E; ++e) {
       const size_t idx = base + (size_t)e * 256;
-      const c128 a = (i == m) ? um[e] : (idx < fsz ? u[idx] : mk(0.0, 0.0));
-      pr += a.re * pv[e].re + a.im * pv[e].im;
-      pi += a.re * pv[e].im - a.im * pv[e].re;
-      qr += a.re * um[e].re + a.im * um[e].im;
-      qi += a.re * um[e].im - a.im * um[e].re;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const c128 a = (i == m) ? um[e][c] : (idx < fsz ? u[c * fsz + idx] : mk(0.0, 0.0));
+        pr += a.re * pv[e][c].re + a.im * pv[e][c].im;
+        pi += a.re * pv[e][c].im - a.im * pv[e][c].re;
+        qr += a.re * um[e][c].re + a.im * um[e][c].im;
+        qi += a.re * um[e][c].im - a.im * um[e][c].re;
+      }
     }
     pr = pml_wave_sum(pr);
     pi = pml_wave_sum(pi);
@@ -371,15 +424,16 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
 
 __global__ __launch_bounds__(256) void k_pml_copy(const c128* __restrict__ src, size_t sbs, PoleList isel,
                                                   c128* __restrict__ dst, size_t dbs, PoleList osel,
-                                                  double* __restrict__ part, size_t part_bs, int N) {
+                                                  double* __restrict__ part, size_t part_bs, int N, int ncomp) {
   __shared__ double red[4];
   const int z = blockIdx.z;
   src += (size_t)isel.k[z] * sbs;
   dst += (size_t)osel.k[z] * dbs;
-  const size_t fsz = (size_t)N * N;
+  const size_t fsz = (size_t)N * N, total = fsz * ncomp;
   double nrm = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
-    const int i = (int)(idx / N), j = (int)(idx % N);
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    const size_t e = idx % fsz;
+    const int i = (int)(e / N), j = (int)(e % N);
     const c128 v = (i > 0 && j > 0) ? src[idx] : mk(0.0, 0.0);
     dst[idx] = v;
     nrm += abs2(v);
@@ -392,10 +446,11 @@ __global__ __launch_bounds__(256) void k_pml_final(const c128* __restrict__ w, c
                                                    const c128* __restrict__ zbase, size_t zsp, size_t zsi,
                                                    const c128* __restrict__ xacc, size_t xsp,
                                                    const PoleState* __restrict__ st, int npoles, c128 phase,
-                                                   c128 rinf_phase, int N) {
-  const size_t fsz = (size_t)N * N;
-  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
-    const int i = (int)(idx / N), j = (int)(idx % N);
+                                                   c128 rinf_phase, int N, int ncomp) {
+  const size_t fsz = (size_t)N * N, total = fsz * ncomp;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    const size_t e = idx % fsz;
+    const int i = (int)(e / N), j = (int)(e % N);
     c128 v = mk(0.0, 0.0);
     if (i > 0 && j > 0) {
       c128 acc = mk(0.0, 0.0);
@@ -427,23 +482,23 @@ int flat_blocks(size_t n) {
 }  // namespace
 
 void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out,
-                     const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N,
+                     const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N, int ncomp,
                      hipStream_t s) {
   const PoleList l = make_list(list, n);
   // variant 1 takes 64 x 64 tiles while they give every CU two workgroups, else 32 x 32
-  const int big = n * (N / 64) * (N / 64) >= 512;
+  const int big = n * ncomp * (N / 64) * (N / 64) >= 512;
   const int bt = (variant == 2 || (variant == 1 && !big)) ? 32 : 64;
-  const dim3 grid(N / bt, N / bt, n);
+  const dim3 grid(N / bt, N / bt, n * ncomp);
 #define G_(L, E)                                                                                                   \
   do {                                                                                                             \
     if (variant == 0)                                                                                              \
-      hipLaunchKernelGGL((k_pml_gemm<L, E>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, N);     \
+      hipLaunchKernelGGL((k_pml_gemm<L, E>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, N, ncomp); \
     else if (bt == 32)                                                                                             \
       hipLaunchKernelGGL((k_pml_gemm_mfma<L, E, 32>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, \
-                         N);                                                                                       \
+                         N, ncomp);                                                                                \
     else                                                                                                           \
       hipLaunchKernelGGL((k_pml_gemm_mfma<L, E, 64>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out, lam, \
-                         N);                                                                                       \
+                         N, ncomp);                                                                                \
   } while (0)
   if (left) {
     if (epilogue == 1)
@@ -469,30 +524,39 @@ int pml_apply_parts(int N) {
 }
 
 void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, size_t psp, c128* const* uptr,
-                      const double* V, const c128* a2, const c128* a1, const StencilCoef& sc, const PoleState* st,
-                      const int* active, int nactive, double2* part, int N, hipStream_t s) {
+                      const double* coef, const c128* a2, const c128* a1, const StencilCoef& sc, const PoleState* st,
+                      const int* active, int nactive, double2* part, int N, int ncomp, hipStream_t s) {
   const int nparts = pml_apply_parts(N);
-  hipLaunchKernelGGL(k_pml_apply, dim3(nparts / 4, nactive), dim3(256), 0, s, zbase, zsp, zsi, pbase, psp, uptr, V,
-                     a2, a1, sc, st, active, part, nparts, N);
+  if (ncomp == 2)
+    hipLaunchKernelGGL(k_pml_apply<2>, dim3(nparts / 4, nactive), dim3(256), 0, s, zbase, zsp, zsi, pbase, psp,
+                       uptr, coef, a2, a1, sc, st, active, part, nparts, N);
+  else
+    hipLaunchKernelGGL(k_pml_apply<1>, dim3(nparts / 4, nactive), dim3(256), 0, s, zbase, zsp, zsi, pbase, psp,
+                       uptr, coef, a2, a1, sc, st, active, part, nparts, N);
 }
 
-void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* V,
+void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
                          const c128* a2, const c128* a1, const StencilCoef& sc, const c128* shifts, int n,
-                         double* part, size_t pbs, int nblk, int N, hipStream_t s) {
+                         double* part, size_t pbs, int nblk, int N, int ncomp, hipStream_t s) {
   ShiftList sh;
   for (int a = 0; a < HP_MAXPOLES; ++a) sh.b[a] = a < n ? shifts[a] : mk(0.0, 0.0);
-  hipLaunchKernelGGL(k_pml_residual, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, V, a2, a1, sc, sh,
-                     part, pbs, N);
+  if (ncomp == 2)
+    hipLaunchKernelGGL(k_pml_residual<2>, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, coef, a2, a1, sc,
+                       sh, part, pbs, N);
+  else
+    hipLaunchKernelGGL(k_pml_residual<1>, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, coef, a2, a1, sc,
+                       sh, part, pbs, N);
 }
 
 void launch_pml_copy(const c128* src, size_t sbs, const int* isel, c128* dst, size_t dbs, const int* osel, int n,
-                     double* part, size_t part_bs, int nblk, int N, hipStream_t s) {
+                     double* part, size_t part_bs, int nblk, int N, int ncomp, hipStream_t s) {
   hipLaunchKernelGGL(k_pml_copy, dim3(nblk, 1, n), dim3(256), 0, s, src, sbs, make_list(isel, n), dst, dbs,
-                     make_list(osel, n), part, part_bs, N);
+                     make_list(osel, n), part, part_bs, N, ncomp);
 }
 
 void launch_pml_final(const c128* w, c128* out, const c128* zbase, size_t zsp, size_t zsi, const c128* xacc,
-                      size_t xsp, const PoleState* st, int npoles, c128 phase, c128 rinf_phase, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_pml_final, dim3(flat_blocks((size_t)N * N)), dim3(256), 0, s, w, out, zbase, zsp, zsi, xacc,
-                     xsp, st, npoles, phase, rinf_phase, N);
+                      size_t xsp, const PoleState* st, int npoles, c128 phase, c128 rinf_phase, int N, int ncomp,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pml_final, dim3(flat_blocks((size_t)N * N * ncomp)), dim3(256), 0, s, w, out, zbase, zsp,
+                     zsi, xacc, xsp, st, npoles, phase, rinf_phase, N, ncomp);
 }

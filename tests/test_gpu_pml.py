@@ -240,8 +240,8 @@ def test_pml_failure_modes():
 
 
 def test_pml_refuses_other_plans():
-    """The layers are built for scalar FP64 plans on square grids: a vector plan, a mixed-precision
-    plan and a 64 x 128 plan refuse them, and stay usable."""
+    """The layers are built for FP64 plans on square grids: a mixed-precision plan and a 64 x 128
+    plan refuse them."""
     _cuda()
     from paper_2410_17446_amd import hp
     wl, g = _setup()
@@ -250,9 +250,85 @@ def test_pml_refuses_other_plans():
     common = dict(dx=0.25, dy=0.25, k0=K0, n0=1.0, dz=1.0, poles=f["poles"], residues=f["residues"],
                   r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"], edge_width=12, edge_eta=0.25, tol=1e-10,
                   restart=30, max_cycles=20)
-    for kw in (dict(nx=64, ny=64, ncomp=2, precision=0), dict(nx=64, ny=64, ncomp=1, precision=hp.HP_MIXED),
-               dict(nx=64, ny=128, ncomp=1, precision=0)):
+    for kw in (dict(nx=64, ny=64, ncomp=1, precision=hp.HP_MIXED), dict(nx=64, ny=128, ncomp=1, precision=0)):
         plan = hp.Plan(**common, **kw)
         with pytest.raises(hp.HPError):
             plan.set_pml(1.0, Q, Qi, lam)
         plan.close()
+
+
+# ---------------------------------------------------------------- vector fields (E_x, E_y)
+
+
+def _vector_case(N=64, W=12, sm=2.0, npoles=8):
+    """A vector plan with layers in a GRF medium (psi coupling in the interior) and the oracle's
+    matching grid and coefficients."""
+    from oracle import operator as op
+    from paper_2410_17446_amd import hp, inputs
+    wl = workload(N=N, ncomp=2, W=W, npoles=npoles, tol=1e-10)
+    n2 = inputs.grf_n2(N, 0.25, 0.02, 1.0, seed=5)
+    g = pml.PMLGrid(N=N, h=0.25, k0=K0, n0=1.0, c=wl["c"], d=wl["d"], W=W, sigma_max=sm)
+    co = op.coefficients(pml.vector_grid(g), n2, True)
+    f = wl["fit"]
+    plan = hp.Plan(nx=N, ny=N, dx=0.25, dy=0.25, k0=K0, n0=1.0, dz=1.0, ncomp=2, poles=f["poles"],
+                   residues=f["residues"], r_inf=f["r_inf"], d2=wl["c"], d1=wl["d"], edge_width=W, edge_eta=0.25,
+                   tol=1e-10, restart=30, max_cycles=20, precision=0)
+    plan.set_pml(sm, *tables.pml_eigen(N, 0.25, K0, 1.0, W, sm, wl["c"], wl["d"]))
+    plan.set_medium(to_gpu(n2))
+    u = _tilted_beam(N)
+    w = np.stack([u, 0.3j * np.roll(u, 3, axis=0)])
+    w[:, 0, :] = 0
+    w[:, :, 0] = 0
+    return wl, g, co, n2, plan, w
+
+
+@pytest.mark.parametrize("pole", [-1, 3])
+def test_vector_pml_operator_matches_oracle(pole):
+    torch = _cuda()
+    wl, g, co, n2, plan, _ = _vector_case()
+    x = np.random.default_rng(7).standard_normal((2, 64, 64)) + 1j * np.random.default_rng(8).standard_normal((2, 64, 64))
+    x[:, 0, :] = 0
+    x[:, :, 0] = 0
+    b = 0.0 if pole < 0 else wl["fit"]["poles"][pole]
+    ref = pml.apply_shifted_vector(g, co, x, b)
+    y = torch.zeros((2, 64, 64), dtype=torch.complex128, device="cuda")
+    plan.apply_operator(pole, to_gpu(x), y)
+    assert rel_l2(y.cpu().numpy(), ref) < 1e-13
+
+
+def test_vector_pml_preconditioner_matches_oracle():
+    torch = _cuda()
+    wl, g, co, n2, plan, _ = _vector_case()
+    x = np.random.default_rng(9).standard_normal((2, 64, 64)) + 1j * np.random.default_rng(10).standard_normal((2, 64, 64))
+    x[:, 0, :] = 0
+    x[:, :, 0] = 0
+    Q = tables.pml_eigen(64, 0.25, K0, 1.0, g.W, g.sigma_max, wl["c"], wl["d"])[0]
+    bound = 20 * 2.2e-16 * 63 * np.linalg.cond(Q) ** 2     # as for scalar fields
+    for pole in (0, 5):
+        b = wl["fit"]["poles"][pole]
+        ref = np.stack([pml.apply_minv(g, x[c], b) for c in range(2)])
+        y = torch.zeros((2, 64, 64), dtype=torch.complex128, device="cuda")
+        plan.apply_preconditioner(pole, to_gpu(x), y)
+        err = rel_l2(y.cpu().numpy(), ref)
+        assert err < max(bound, 1e-12), (pole, err, bound)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_vector_pml_step_replayed_iterations(variant):
+    """One vector step (coupled E_x, E_y in a GRF medium, PML layers) with the oracle's per-pole
+    iteration counts replayed."""
+    torch = _cuda()
+    wl, g, co, n2, plan, w = _vector_case()
+    f = wl["fit"]
+    ref, res = pml.step_vector(g, co, w, f["poles"], f["residues"], f["r_inf"], 1.0, 1e-10)
+    counts = [r.iters for r in res]
+    assert all(r.cycles == 1 for r in res)
+    plan.set_launch(variant)
+    plan.set_fixed_iters(counts)
+    out = plan.step(to_gpu(w))
+    assert rel_l2(out.cpu().numpy(), ref) < 1e-9
+    assert plan.stats()[0] == counts
+    plan.set_fixed_iters(None)
+    out = plan.step(to_gpu(w))
+    it, rr = plan.stats()
+    assert max(rr) <= 1e-10 and rel_l2(out.cpu().numpy(), ref) < 1e-8
