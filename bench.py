@@ -607,7 +607,8 @@ def run_pml(args):
         roof = {"bound": "alu", "kernel": "pml_gemm (the four dense stages of a round)", "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFS,
                 "traffic": None, "algorithmic_flops_per_launch": amount / max(n_l, 1),
-                "flops_convention": "8 (N-1)^3 per complex product, four products per pole that did the round",
+                "flops_convention": "8 (N-1)^3 per complex product actually needed: four per pole that did the "
+                                    "round, and in the step's first round two shared by all poles plus two per pole",
                 "peak_is": "FP64 vector ALU (256 CUs x 2.4 GHz x 128 FP64 flops/clock; the FP64 matrix "
                            "cores have the same rate)"}
     else:

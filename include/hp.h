@@ -294,7 +294,9 @@ int hp_fit_exp_sqrt(double K, int degree, int lawson_steps, void* stream, hp_c12
  * sigma_max = 0 with Q, Qinv, lam all NULL removes the layers.  In the
  * kernel timing the class HP_K_PML holds the four dense stages of every
  * round, and its byte figure counts floating-point operations instead
- * (32 (N-1)^3 per pole and round). */
+ * (8 (N-1)^3 ncomp per complex product: four per pole and round, except in a
+ * round where every pole starts from the step's shared first basis vector,
+ * whose first two products are pole-independent and run once). */
 int hp_set_pml(hp_plan plan, double sigma_max, const void* Q, const void* Qinv, const void* lam);
 
 /* x_k of the last step, guess step or solve for pole k (Sec. 2 eq. W_k_def):

@@ -137,6 +137,7 @@ struct hp_plan_s {
   char* pml_mem = nullptr;
   c128 *pml_q = nullptr, *pml_qi = nullptr, *pml_lam = nullptr, *pml_a2 = nullptr, *pml_a1 = nullptr;
   c128* pml_s = nullptr;
+  c128* pml_shared = nullptr;  // two fields: the first round's pole-independent products
   double2* pml_part = nullptr;
   std::string scratch_err;
   std::string err;
@@ -668,6 +669,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     std::vector<int> ms;     // per pole: its Arnoldi index in the round
     std::vector<char> sh;    // per pole: its first basis vector is the shared S_x w
     long pslot[3];           // timed-launch slots of the column pass, row pass and update
+    bool shared;             // absorbing layers: the round shared its first two dense products
   };
   // Algorithmic bytes of a round's column pass, row pass and update over the
   // poles that did the step (the others skipped themselves on the device), each
@@ -691,8 +693,10 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       }
     }
     const double dup = shared > 0 ? shared - 1.0 : 0.0, dup0 = shared_m0 > 0 ? shared_m0 - 1.0 : 0.0;
-    // absorbing layers: the dense stages count floating-point operations
-    prof_settle(p, p->pml ? HP_K_PML : HP_K_COL, f.pslot[0], p->pml ? nw * pml_flops(p) : U1 * es * (col - dup0));
+    // absorbing layers: the dense stages count floating-point operations (a shared round:
+    // two products once, two per pole)
+    const double pf = f.shared ? (nw ? (2.0 + 2.0 * nw) / 4.0 : 0.0) : (double)nw;
+    prof_settle(p, p->pml ? HP_K_PML : HP_K_COL, f.pslot[0], p->pml ? pf * pml_flops(p) : U1 * es * (col - dup0));
     prof_settle(p, HP_K_ROW_APPLY, f.pslot[1], nw ? U1 * es * (row - dup) + (U1 / d.ncomp) * 8.0 * planes : 0.0);
     prof_settle(p, HP_K_UPDATE, f.pslot[2], U1 * es * (upd - dup));
   };
@@ -732,7 +736,7 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
     const int na = (int)poles.size();
     int* ad = p->active_d + slot * HP_MAXPOLES;
     int maxm = 0;
-    Flight fl{poles, slot, next_iter, 0, std::vector<int>(na), std::vector<char>(na), {-1, -1, -1}};
+    Flight fl{poles, slot, next_iter, 0, std::vector<int>(na), std::vector<char>(na), {-1, -1, -1}, false};
     for (int a = 0; a < na; ++a) {
       const int mk_ = (int)std::min<long>(next_iter - since[poles[a]], M - 1);
       maxm = std::max(maxm, mk_);
@@ -745,10 +749,33 @@ int run_poles(hp_plan p, const c128* w, const std::vector<int>& subset, bool* no
       c128* Zc = reinterpret_cast<c128*>(p->Z);
       c128* Pc = reinterpret_cast<c128*>(p->P);
       c128* const* uc = reinterpret_cast<c128* const*>(p->uptr);
+      // a round in which every pole starts from the shared first basis vector shares
+      // the first two dense products (matrix-core forms)
+      bool shared = p->geo.col_variant != 0;
+      for (int a = 0; a < na && shared; ++a) shared = fl.sh[a] && fl.ms[a] == 0;
+      fl.shared = shared;
       {
         Prof pr(p, HP_K_PML, -1.0, &fl.pslot[0]);
-        pml_prec(p, p->st, poles.data(), na, ad, PmlRef{uc, nullptr, 0, 0}, PmlRef{nullptr, Zc, zsp, zsi}, Pc,
-                 p->pml_s);
+        if (shared) {
+          const int zero = 0, N = d.nx, nc = d.ncomp;
+          c128* T1 = p->pml_shared;
+          c128* T2 = p->pml_shared + fn;
+          launch_pml_shared_setup(p->st_scratch, reinterpret_cast<c128**>(p->uptr_scratch),
+                                  reinterpret_cast<const c128*>(bR), p->stream);
+          launch_pml_gemm(p->geo.col_variant, true, 0, p->pml_qi,
+                          PmlRef{reinterpret_cast<c128* const*>(p->uptr_scratch), nullptr, 0, 0},
+                          PmlRef{nullptr, T1, 0, 0}, p->st_scratch, &zero, 1, nullptr, p->pml_lam, N, nc, p->stream);
+          launch_pml_gemm(p->geo.col_variant, false, 0, p->pml_qi, PmlRef{nullptr, T1, 0, 0},
+                          PmlRef{nullptr, T2, 0, 0}, p->st_scratch, &zero, 1, nullptr, p->pml_lam, N, nc, p->stream);
+          launch_pml_gemm_divided(p->pml_q, PmlRef{nullptr, T2, 0, 0}, PmlRef{nullptr, Pc, fn, 0}, p->st,
+                                  poles.data(), na, ad, p->pml_lam, N, nc, p->stream);
+          launch_pml_gemm(p->geo.col_variant, false, 2, p->pml_q, PmlRef{nullptr, Pc, fn, 0},
+                          PmlRef{nullptr, Zc, zsp, zsi}, p->st, poles.data(), na, nullptr, p->pml_lam, N, nc,
+                          p->stream);
+        } else {
+          pml_prec(p, p->st, poles.data(), na, ad, PmlRef{uc, nullptr, 0, 0}, PmlRef{nullptr, Zc, zsp, zsi}, Pc,
+                   p->pml_s);
+        }
       }
       {
         Prof pr(p, HP_K_ROW_APPLY, -1.0, &fl.pslot[1]);
@@ -1458,7 +1485,7 @@ int hp_set_form(hp_plan p, int form, int substeps) {
 static void free_pml(hp_plan p) {
   if (p->pml_mem) (void)hipFree(p->pml_mem);
   p->pml_mem = nullptr;
-  p->pml_q = p->pml_qi = p->pml_lam = p->pml_a2 = p->pml_a1 = p->pml_s = nullptr;
+  p->pml_q = p->pml_qi = p->pml_lam = p->pml_a2 = p->pml_a1 = p->pml_s = p->pml_shared = nullptr;
   p->pml_part = nullptr;
   p->pml = false;
   p->pml_sigma = 0.0;
@@ -1567,7 +1594,8 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
   const size_t NN = (size_t)N * N, fn = p->fieldn, K = (size_t)d.npoles;
   const size_t nparts = (size_t)pml_apply_parts(N);
   if (!p->pml_mem) {
-    const size_t bytes = (2 * NN + 3 * (size_t)N + K * fn) * sizeof(c128) + K * (HP_MAXM + 1) * 2 * nparts * sizeof(double2);
+    const size_t bytes = (2 * NN + 3 * (size_t)N + (K + 2) * fn) * sizeof(c128) +
+                         K * (HP_MAXM + 1) * 2 * nparts * sizeof(double2);
     hipError_t e = hipMalloc(&p->pml_mem, bytes);
     if (e != hipSuccess) {
       p->pml_mem = nullptr;
@@ -1580,7 +1608,8 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
     p->pml_a2 = p->pml_lam + N;
     p->pml_a1 = p->pml_a2 + N;
     p->pml_s = p->pml_a1 + N;
-    p->pml_part = reinterpret_cast<double2*>(p->pml_s + K * fn);
+    p->pml_shared = p->pml_s + K * fn;
+    p->pml_part = reinterpret_cast<double2*>(p->pml_shared + 2 * fn);
   }
   // padded to N x N: row and column 0 zero
   std::vector<c128> pad(NN, mk(0.0, 0.0));
@@ -1599,7 +1628,7 @@ int hp_set_pml(hp_plan p, double sigma_max, const void* Q, const void* Qinv, con
   HPCHK(hipMemcpy(p->pml_a2, a2.data(), N * sizeof(c128), hipMemcpyHostToDevice));
   HPCHK(hipMemcpy(p->pml_a1, a1.data(), N * sizeof(c128), hipMemcpyHostToDevice));
   // the medium-pass slots and the dense stages' scratch start from zero (rows 0 and columns 0 stay so)
-  HPCHK(hipMemset(p->pml_s, 0, K * fn * sizeof(c128)));
+  HPCHK(hipMemset(p->pml_s, 0, (K + 2) * fn * sizeof(c128)));
   p->pml = true;
   p->pml_sigma = sigma_max;
   p->prev_valid = false;

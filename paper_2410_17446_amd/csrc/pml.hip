@@ -130,7 +130,7 @@ __global__ __launch_bounds__(GWG) void k_pml_gemm(const c128* __restrict__ mat, 
 // at most 128 registers per lane (accumulators included), four waves per SIMD.
 typedef double pml_d4 __attribute__((ext_vector_type(4)));
 
-template <bool LEFT, int EPI, int BT>
+template <bool LEFT, int EPI, int BT, bool DIVB = false>
 __global__ __launch_bounds__(GWG, 4) void k_pml_gemm_mfma(const c128* __restrict__ mat, PmlRef in, PmlRef out,
                                                        const PoleState* __restrict__ st, PoleList list,
                                                        int* __restrict__ active_out, const c128* __restrict__ lam,
@@ -154,15 +154,20 @@ __global__ __launch_bounds__(GWG, 4) void k_pml_gemm_mfma(const c128* __restrict
   __shared__ c128 As[GK][BT + 1];
   __shared__ c128 Bs[GK][BT + 1];
   c128 ra[LPT], rb[LPT];
+  const c128 bk0 = st[k].bk;
   auto fetch = [&](int j0) {
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + GWG * q;
       ra[q] = Ag[(size_t)(r0 + e / GK) * N + j0 + e % GK];
-      if (LEFT)
-        rb[q] = Bg[(size_t)(j0 + e / BT) * N + c0 + e % BT];
-      else
+      if (LEFT) {
+        const int jr = j0 + e / BT, jc = c0 + e % BT;
+        rb[q] = Bg[(size_t)jr * N + jc];
+        // the divide of the pole's middle stage, applied to a product shared by all poles
+        if (DIVB) rb[q] = (jr == 0 || jc == 0) ? mk(0.0, 0.0) : cdiv(rb[q], lam[jr] + lam[jc] - bk0);
+      } else {
         rb[q] = Bg[(size_t)(c0 + e / GK) * N + j0 + e % GK];
+      }
     }
   };
   pml_d4 cr[MB][MB], ci[MB][MB];
@@ -480,6 +485,33 @@ int flat_blocks(size_t n) {
 }
 
 }  // namespace
+
+__global__ void k_pml_shared_setup(PoleState* st, c128** tbl, const c128* u0) {
+  if (threadIdx.x != 0) return;
+  st->flag = 0;
+  st->m = 0;
+  st->bk = mk(0.0, 0.0);
+  st->sigma[0] = 1.0;
+  tbl[0] = const_cast<c128*>(u0);
+}
+
+void launch_pml_shared_setup(PoleState* st, c128** tbl, const c128* u0, hipStream_t s) {
+  hipLaunchKernelGGL(k_pml_shared_setup, dim3(1), dim3(64), 0, s, st, tbl, u0);
+}
+
+void launch_pml_gemm_divided(const c128* mat, PmlRef in, PmlRef out, const PoleState* st, const int* list, int n,
+                             int* active_out, const c128* lam, int N, int ncomp, hipStream_t s) {
+  const PoleList l = make_list(list, n);
+  const int big = n * ncomp * (N / 64) * (N / 64) >= 512;
+  const int bt = big ? 64 : 32;
+  const dim3 grid(N / bt, N / bt, n * ncomp);
+  if (bt == 64)
+    hipLaunchKernelGGL((k_pml_gemm_mfma<true, 0, 64, true>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out,
+                       lam, N, ncomp);
+  else
+    hipLaunchKernelGGL((k_pml_gemm_mfma<true, 0, 32, true>), grid, dim3(GWG), 0, s, mat, in, out, st, l, active_out,
+                       lam, N, ncomp);
+}
 
 void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlRef in, PmlRef out,
                      const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N, int ncomp,

@@ -44,6 +44,16 @@ void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlR
                      const PoleState* st, const int* list, int n, int* active_out, const c128* lam, int N, int ncomp,
                      hipStream_t s);
 
+// A round whose poles all start from the step's shared first basis vector u_0
+// shares the first two products: T = Q^-1 u_0 Q^-T once (one-entry pole list
+// with the state k_pml_shared_setup writes: m = 0, b = 0, sigma_0 = 1, tbl[0] =
+// u0), then per pole Q [T / (lam_p + lam_q - b_k)] with the divide applied as
+// the operand is loaded (launch_pml_gemm_divided, matrix cores; tiles as
+// variant 1), then the last stage as usual.
+void launch_pml_shared_setup(PoleState* st, c128** tbl, const c128* u0, hipStream_t s);
+void launch_pml_gemm_divided(const c128* mat, PmlRef in, PmlRef out, const PoleState* st, const int* list, int n,
+                             int* active_out, const c128* lam, int N, int ncomp, hipStream_t s);
+
 // p = (Zbar~ - b_k I) z_m - sigma_m u_m into P[k] (so that A_k z_m = ~v_m + p
 // for the z_m as stored) and the partial inner products <u_i, p>, <u_i, u_m>,
 // i = 0..m, in the layout the dot reduction reads (pml_apply_parts per product).
