@@ -24,8 +24,8 @@ sizes run concurrently), learned (a U-Net trained on the GPU from the
 propagator's own solves supplies GMRES starting points; timed against the plain
 method and the previous-step start on scalar1024), unet (training steps of that
 U-Net at its training shape), copy (the HBM reference for the counters) and
-pml512 (absorbing layers: 512^2 with PML layers of 64 cells, the eigen-route
-Sylvester preconditioner's dense products), fit (the rational fit on the device
+pml512 and pml512v (absorbing layers, scalar and vector: 512^2 with PML layers
+of 64 cells, the eigen-route Sylvester preconditioner's dense products), fit (the rational fit on the device
 against the host's), sqrt1024 (the scalar1024 workload
 through the pseudo-differential form: 25
 Cauchy-integral terms of sqrt(1+z), alpha = 1, eight RK4 substeps of lambda/8
@@ -577,24 +577,27 @@ FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector (and FP64 matrix) peak
 PML_SIGMA = 10.0
 
 
-def run_pml(args):
-    """Absorbing layers (Sec. 4.1): the scalar workload of the sine-product runs of Sec. 5 on 512^2
-    cells of lambda/4 (128 lambda) with PML layers of 64 cells (16 lambda) on every side, sigma_max
-    = 10, a Gaussian beam (1/e radius 8 lambda) tilted 20 degrees off axis and 16 lambda off centre
-    toward the layer, sine-product medium n = 1 + 0.02 sin(2 pi x) sin(2 pi y), 16 poles, dz =
-    lambda, tol 1e-8, FP64.  The preconditioner is the eigen route of the stretched Sylvester
-    equation: four dense complex products per pole and Arnoldi step."""
+def run_pml(args, ncomp=1):
+    """Absorbing layers (Sec. 4.1): the workload of the sine-product runs of Sec. 5 on 512^2 cells of
+    lambda/4 (128 lambda) with PML layers of 64 cells (16 lambda) on every side, sigma_max = 10, a
+    Gaussian beam (1/e radius 8 lambda; x-polarised for vector fields) tilted 20 degrees off axis and
+    16 lambda off centre toward the layer, sine-product medium n = 1 + 0.02 sin(2 pi x) sin(2 pi y),
+    16 poles, dz = lambda, tol 1e-8, FP64; scalar (pml512) or vector (pml512v: coupled E_x, E_y).
+    The preconditioner is the eigen route of the stretched Sylvester equation: four dense complex
+    products per pole, component and Arnoldi step."""
     import numpy as np
     import torch
 
     from paper_2410_17446_amd import hp, inputs, tables
     N, W = 512, 64
-    cfg = dict(N=N, dx=0.25, ncomp=1, W=W, eta_max=0.25, dz=1.0, npoles=16, tol=1e-8, restart=30,
+    cfg = dict(N=N, dx=0.25, ncomp=ncomp, W=W, eta_max=0.25, dz=1.0, npoles=16, tol=1e-8, restart=30,
                medium=("sine", 0.02, 1.0), w0=8.0)
     tab = tables.plan_tables(inputs.K0 * cfg["dz"], cfg["npoles"])
     Q, Qi, lam = tables.pml_eigen(N, cfg["dx"], inputs.K0, 1.0, W, PML_SIGMA, tab[3], tab[4])
     cond = float(np.linalg.cond(Q))
     w = inputs.tilted_beam(N, cfg["dx"], cfg["w0"], np.sin(np.radians(20.0)), x0=16.0)
+    if ncomp == 2:
+        w = np.concatenate([w, np.zeros_like(w)])
     w0 = torch.from_numpy(w).cuda()
     n2 = torch.from_numpy(inputs.medium_n2(cfg)).cuda()
     r = run_mode(hp, torch, cfg, tab, hp.HP_FP64, w0, n2, args.warmup, args.steps, event_period=args.event_period,
@@ -620,11 +623,12 @@ def run_pml(args):
     f_in, f_out = w0.cpu().numpy(), r["field"].cpu().numpy()
     gemm_ms = brk["pml_gemm"][1]
     line = {
-        "metric": f"propagation steps/s ({N}^2, {cfg['npoles']} poles, PML layers of {W} cells)",
+        "metric": f"propagation steps/s ({N}^2{' vector' if ncomp == 2 else ''}, {cfg['npoles']} poles, "
+                  f"PML layers of {W} cells)",
         "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * r["seconds"] / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c128", "data": "synthetic",
-        "config": {"workload": "pml512", "grid": N, "pml_cells": W, "sigma_max": PML_SIGMA, "poles": cfg["npoles"],
+        "config": {"workload": "pml512v" if ncomp == 2 else "pml512", "grid": N, "pml_cells": W, "sigma_max": PML_SIGMA, "poles": cfg["npoles"],
                    "tol": cfg["tol"], "mode": "fp64", "beam": "1/e radius 8 lambda, 20 degrees, 16 lambda off axis",
                    "dense_stage_variant": r["variant"]},
         "last_step_iters": r["iters"], "last_step_true_relres_max": max(r["relres"]),
@@ -636,22 +640,28 @@ def run_pml(args):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_pml(cfg, tab, w, inputs.medium_n2(cfg))
+    if ncomp == 2:
+        line["power_in_E_y"] = float(np.sum(np.abs(f_out[1]) ** 2) / np.sum(np.abs(f_out) ** 2))
     print(json.dumps(line))
     return 0
 
 
 def cpu_baseline_pml(cfg, tab, w, n2):
     """The oracle's PML solve (Bartels-Stewart preconditioner) of one pole of step 1, scaled to steps/s."""
+    from oracle import operator as op
     from oracle import pml
     from paper_2410_17446_amd import inputs
     poles = tab[0]
     g = pml.PMLGrid(N=cfg["N"], h=cfg["dx"], k0=inputs.K0, n0=1.0, c=tab[3], d=tab[4], W=cfg["W"],
                     sigma_max=PML_SIGMA)
-    V = pml.medium(g, n2)
     threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
     j = len(poles) // 2
     t0 = time.perf_counter()
-    r = pml.solve_pole(g, V, w[0], poles[j], cfg["tol"], cfg["restart"])
+    if cfg["ncomp"] == 2:
+        co = op.coefficients(pml.vector_grid(g), n2, True)
+        r = pml.solve_pole_vector(g, co, w, poles[j], cfg["tol"], cfg["restart"])
+    else:
+        r = pml.solve_pole(g, pml.medium(g, n2), w[0], poles[j], cfg["tol"], cfg["restart"])
     dt = time.perf_counter() - t0
     return dict(value=1.0 / (dt * cfg["npoles"]), unit="steps/s", cores=threads, kind="oracle",
                 sample=f"GMRES solve of pole {j} (of {cfg['npoles']}) in step 1 of the {cfg['N']}^2 PML workload "
@@ -767,6 +777,8 @@ def main():
         return run_sineprod(args)
     if args.config == "pml512":
         return run_pml(args)
+    if args.config == "pml512v":
+        return run_pml(args, ncomp=2)
     if args.config == "fit":
         return run_fit(args)
     import numpy as np
