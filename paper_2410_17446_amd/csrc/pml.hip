@@ -296,14 +296,9 @@ __device__ __forceinline__ PmlPoint pml_point(const c128* __restrict__ x, int i,
 // coupling of eq. Z_bar_eq (coefficient planes 1..5: s psi_x, s psi_y, s psi_xx,
 // s psi_yy, s psi_xy, zero in the layers).
 template <int NC>
-__device__ __forceinline__ void pml_op(const c128* __restrict__ x, int i, int j, int N,
-                                       const double* __restrict__ coef, const c128* __restrict__ a2,
-                                       const c128* __restrict__ a1, const StencilCoef& sc, c128 b, c128* out) {
-  const size_t fsz = (size_t)N * N, idx = (size_t)i * N + j;
+__device__ __forceinline__ void pml_combine(const PmlPoint* pt, const double* __restrict__ coef, size_t idx,
+                                            size_t fsz, c128 b, c128* out) {
   const double V = coef[idx];
-  PmlPoint pt[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) pt[c] = pml_point(x + c * fsz, i, j, N, a2, a1, sc);
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] = pt[c].lap + (V * pt[c].ctr - b * pt[c].ctr);
   if constexpr (NC == 2) {
@@ -312,6 +307,17 @@ __device__ __forceinline__ void pml_op(const c128* __restrict__ x, int i, int j,
     out[0] = out[0] + pxx * pt[0].ctr + px * pt[0].dx + pxy * pt[1].ctr + py * pt[1].dx;
     out[1] = out[1] + pxy * pt[0].ctr + px * pt[0].dy + pyy * pt[1].ctr + py * pt[1].dy;
   }
+}
+
+template <int NC>
+__device__ __forceinline__ void pml_op(const c128* __restrict__ x, int i, int j, int N,
+                                       const double* __restrict__ coef, const c128* __restrict__ a2,
+                                       const c128* __restrict__ a1, const StencilCoef& sc, c128 b, c128* out) {
+  const size_t fsz = (size_t)N * N, idx = (size_t)i * N + j;
+  PmlPoint pt[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) pt[c] = pml_point(x + c * fsz, i, j, N, a2, a1, sc);
+  pml_combine<NC>(pt, coef, idx, fsz, b, out);
 }
 
 template <int NC>
@@ -351,7 +357,12 @@ __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x
 // operator are far from unitary), so the Arnoldi relation of the stored Z is
 // exact up to the rounding of p itself.
 
-constexpr int AP_E = 4;  // elements per thread
+// The pass stages a 64 x 16 tile of every component of z with a 6-node halo
+// (odd reflection applied while staging) in LDS, so each z value is read from
+// memory about 1.6 times instead of once per stencil point; each thread then
+// takes four points of a tile column.  The inner products are summed per wave.
+constexpr int AP_X = 64, AP_Y = 16, AP_H = 6;
+constexpr int AP_LX = AP_X + 2 * AP_H, AP_LY = AP_Y + 2 * AP_H;
 
 template <int NC>
 __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbase, size_t zsp, size_t zsi,
@@ -360,6 +371,7 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
                                                    const c128* __restrict__ a1, StencilCoef sc,
                                                    const PoleState* __restrict__ st, const int* __restrict__ active,
                                                    double2* __restrict__ part, int nparts, int N) {
+  __shared__ c128 tile[NC][AP_LY * AP_LX];
   const int k = active[blockIdx.y];
   if (st[k].flag) return;
   const int m = st[k].m;
@@ -369,48 +381,70 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
   const c128* z = zbase + (size_t)k * zsp + (size_t)m * zsi;
   c128* p = pbase + (size_t)k * psp;
   const c128* const* up = uptr + (size_t)k * (HP_MAXM + 1);
-  const size_t base = (size_t)blockIdx.x * 256 * AP_E + threadIdx.x;
-  c128 pv[AP_E][NC], um[AP_E][NC];
+  const int ntx = N / AP_X;
+  const int x0 = (blockIdx.x % ntx) * AP_X, y0 = (blockIdx.x / ntx) * AP_Y;
+  const int tid = threadIdx.x, tx = tid & 63, tq = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    for (int e = tid; e < AP_LY * AP_LX; e += 256)
+      tile[c][e] = pml_ld(z + c * fsz, y0 + e / AP_LX - AP_H, x0 + e % AP_LX - AP_H, N);
+  __syncthreads();
+  c128 pv[4][NC], um[4][NC];
   {
     const c128* u = up[m];
 #pragma unroll
-    for (int e = 0; e < AP_E; ++e) {
-      const size_t idx = base + (size_t)e * 256;
+    for (int q = 0; q < 4; ++q) {
+      const int ty = tq + 4 * q, i = y0 + ty, j = x0 + tx;
+      const size_t idx = (size_t)i * N + j;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        pv[e][c] = mk(0.0, 0.0);
-        um[e][c] = mk(0.0, 0.0);
+        um[q][c] = u[c * fsz + idx];
+        pv[q][c] = mk(0.0, 0.0);
       }
-      if (idx < fsz) {
-        const int i = (int)(idx / N), j = (int)(idx % N);
+      if (i > 0 && j > 0) {
+        const int lc = (ty + AP_H) * AP_LX + tx + AP_H;
+        PmlPoint pt[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) um[e][c] = u[c * fsz + idx];
-        if (i > 0 && j > 0) {
-          c128 az[NC];
-          pml_op<NC>(z, i, j, N, coef, a2, a1, sc, bk, az);
+        for (int c = 0; c < NC; ++c) {
+          const c128* t = tile[c];
+          pt[c].ctr = t[lc];
+          c128 sxx = sc.c2x[0] * pt[c].ctr, syy = sc.c2x[0] * pt[c].ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) pv[e][c] = az[c] - sg * um[e][c];
+          for (int mm = 1; mm <= 6; ++mm) {
+            const c128 xp = t[lc + mm], xm = t[lc - mm], yp = t[lc + mm * AP_LX], ym = t[lc - mm * AP_LX];
+            sxx = sxx + sc.c2x[mm] * (xp + xm);
+            sx1 = sx1 + sc.d1x[mm - 1] * (xp - xm);
+            syy = syy + sc.c2x[mm] * (yp + ym);
+            sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
+          }
+          pt[c].lap = (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1);
+          pt[c].dx = sx1;
+          pt[c].dy = sy1;
         }
+        c128 az[NC];
+        pml_combine<NC>(pt, coef, idx, fsz, bk, az);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) p[c * fsz + idx] = pv[e][c];
+        for (int c = 0; c < NC; ++c) pv[q][c] = az[c] - sg * um[q][c];
       }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) p[c * fsz + idx] = pv[q][c];
     }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int slot = blockIdx.x * 4 + wave;
   for (int i = 0; i <= m; ++i) {
     const c128* u = up[i];
     double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
 #pragma unroll
-    for (int e = 0; e < AP_E; ++e) {
-      const size_t idx = base + (size_t)e * 256;
+    for (int q = 0; q < 4; ++q) {
+      const size_t idx = (size_t)(y0 + tq + 4 * q) * N + x0 + tx;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const c128 a = (i == m) ? um[e][c] : (idx < fsz ? u[c * fsz + idx] : mk(0.0, 0.0));
-        pr += a.re * pv[e][c].re + a.im * pv[e][c].im;
-        pi += a.re * pv[e][c].im - a.im * pv[e][c].re;
-        qr += a.re * um[e][c].re + a.im * um[e][c].im;
-        qi += a.re * um[e][c].im - a.im * um[e][c].re;
+        const c128 a = (i == m) ? um[q][c] : u[c * fsz + idx];
+        pr += a.re * pv[q][c].re + a.im * pv[q][c].im;
+        pi += a.re * pv[q][c].im - a.im * pv[q][c].re;
+        qr += a.re * um[q][c].re + a.im * um[q][c].im;
+        qi += a.re * um[q][c].im - a.im * um[q][c].re;
       }
     }
     pr = pml_wave_sum(pr);
@@ -550,10 +584,7 @@ void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlR
 #undef G_
 }
 
-int pml_apply_parts(int N) {
-  const size_t fsz = (size_t)N * N;
-  return (int)((fsz + 256 * AP_E - 1) / (256 * AP_E)) * 4;
-}
+int pml_apply_parts(int N) { return (N / AP_X) * (N / AP_Y) * 4; }
 
 void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, size_t psp, c128* const* uptr,
                       const double* coef, const c128* a2, const c128* a1, const StencilCoef& sc, const PoleState* st,
