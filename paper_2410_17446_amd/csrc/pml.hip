@@ -270,27 +270,6 @@ __device__ __forceinline__ c128 pml_ld(const c128* __restrict__ x, int i, int j,
 struct PmlPoint {
   c128 lap, dx, dy, ctr;
 };
-__device__ __forceinline__ PmlPoint pml_point(const c128* __restrict__ x, int i, int j, int N,
-                                              const c128* __restrict__ a2, const c128* __restrict__ a1,
-                                              const StencilCoef& sc) {
-  PmlPoint r;
-  r.ctr = x[(size_t)i * N + j];
-  c128 sxx = sc.c2x[0] * r.ctr, syy = sc.c2x[0] * r.ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
-#pragma unroll
-  for (int mm = 1; mm <= 6; ++mm) {
-    const c128 xp = pml_ld(x, i, j + mm, N), xm = pml_ld(x, i, j - mm, N);
-    const c128 yp = pml_ld(x, i + mm, j, N), ym = pml_ld(x, i - mm, j, N);
-    sxx = sxx + sc.c2x[mm] * (xp + xm);
-    sx1 = sx1 + sc.d1x[mm - 1] * (xp - xm);
-    syy = syy + sc.c2x[mm] * (yp + ym);
-    sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
-  }
-  r.lap = (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1);
-  r.dx = sx1;
-  r.dy = sy1;
-  return r;
-}
-
 // (Zbar~ - b I) x at interior node (i, j) for the NC components of x (planes fsz
 // apart): the stretched Laplacian plus (V - b) x, and for vector fields the psi
 // coupling of eq. Z_bar_eq (coefficient planes 1..5: s psi_x, s psi_y, s psi_xx,
@@ -309,34 +288,67 @@ __device__ __forceinline__ void pml_combine(const PmlPoint* pt, const double* __
   }
 }
 
-template <int NC>
-__device__ __forceinline__ void pml_op(const c128* __restrict__ x, int i, int j, int N,
-                                       const double* __restrict__ coef, const c128* __restrict__ a2,
-                                       const c128* __restrict__ a1, const StencilCoef& sc, c128 b, c128* out) {
-  const size_t fsz = (size_t)N * N, idx = (size_t)i * N + j;
-  PmlPoint pt[NC];
+// The tile layout of the operator pass below (64 x 16 points, 6-node halo).
+constexpr int AP_X = 64, AP_Y = 16, AP_H = 6;
+constexpr int AP_LX = AP_X + 2 * AP_H, AP_LY = AP_Y + 2 * AP_H;
+
+// Stencil sums of one component at tile point lc (the LDS tile holds the
+// component with its halo; node (i, j) of the field).
+__device__ __forceinline__ PmlPoint pml_point_tile(const c128* t, int lc, int i, int j, const c128* __restrict__ a2,
+                                                   const c128* __restrict__ a1, const StencilCoef& sc) {
+  PmlPoint r;
+  r.ctr = t[lc];
+  c128 sxx = sc.c2x[0] * r.ctr, syy = sc.c2x[0] * r.ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
 #pragma unroll
-  for (int c = 0; c < NC; ++c) pt[c] = pml_point(x + c * fsz, i, j, N, a2, a1, sc);
-  pml_combine<NC>(pt, coef, idx, fsz, b, out);
+  for (int mm = 1; mm <= 6; ++mm) {
+    const c128 xp = t[lc + mm], xm = t[lc - mm], yp = t[lc + mm * AP_LX], ym = t[lc - mm * AP_LX];
+    sxx = sxx + sc.c2x[mm] * (xp + xm);
+    sx1 = sx1 + sc.d1x[mm - 1] * (xp - xm);
+    syy = syy + sc.c2x[mm] * (yp + ym);
+    sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
+  }
+  r.lap = (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1);
+  r.dx = sx1;
+  r.dy = sy1;
+  return r;
 }
 
+// Field z (blockIdx.z) of a batch: y = rhs - (Zbar~ - b_z I) x (y = (Zbar~ - b I) x without rhs)
+// on one 64 x 16 tile per workgroup (blockIdx.x), partial |y|^2 per workgroup.
 template <int NC>
 __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x, size_t xbs,
                                                       const c128* __restrict__ rhs, c128* __restrict__ y, size_t ybs,
                                                       const double* __restrict__ coef, const c128* __restrict__ a2,
                                                       const c128* __restrict__ a1, StencilCoef sc, ShiftList sh,
                                                       double* __restrict__ part, size_t pbs, int N) {
+  __shared__ c128 tile[NC][AP_LY * AP_LX];
   __shared__ double red[4];
   const int z = blockIdx.z;
   x += (size_t)z * xbs;
   y += (size_t)z * ybs;
   const c128 b = sh.b[z];
   const size_t fsz = (size_t)N * N;
+  const int ntx = N / AP_X;
+  const int x0 = (blockIdx.x % ntx) * AP_X, y0 = (blockIdx.x / ntx) * AP_Y;
+  const int tid = threadIdx.x, tx = tid & 63, tq = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    for (int e = tid; e < AP_LY * AP_LX; e += 256)
+      tile[c][e] = pml_ld(x + c * fsz, y0 + e / AP_LX - AP_H, x0 + e % AP_LX - AP_H, N);
+  __syncthreads();
   double nrm = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < fsz; idx += (size_t)gridDim.x * 256) {
-    const int i = (int)(idx / N), j = (int)(idx % N);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ty = tq + 4 * q, i = y0 + ty, j = x0 + tx;
+    const size_t idx = (size_t)i * N + j;
     c128 ax[NC];
-    if (i > 0 && j > 0) pml_op<NC>(x, i, j, N, coef, a2, a1, sc, b, ax);
+    if (i > 0 && j > 0) {
+      const int lc = (ty + AP_H) * AP_LX + tx + AP_H;
+      PmlPoint pt[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pt[c] = pml_point_tile(tile[c], lc, i, j, a2, a1, sc);
+      pml_combine<NC>(pt, coef, idx, fsz, b, ax);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       c128 v = mk(0.0, 0.0);
@@ -361,9 +373,6 @@ __global__ __launch_bounds__(256) void k_pml_residual(const c128* __restrict__ x
 // (odd reflection applied while staging) in LDS, so each z value is read from
 // memory about 1.6 times instead of once per stencil point; each thread then
 // takes four points of a tile column.  The inner products are summed per wave.
-constexpr int AP_X = 64, AP_Y = 16, AP_H = 6;
-constexpr int AP_LX = AP_X + 2 * AP_H, AP_LY = AP_Y + 2 * AP_H;
-
 template <int NC>
 __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbase, size_t zsp, size_t zsi,
                                                    c128* __restrict__ pbase, size_t psp, c128* const* __restrict__ uptr,
@@ -405,22 +414,7 @@ __global__ __launch_bounds__(256) void k_pml_apply(const c128* __restrict__ zbas
         const int lc = (ty + AP_H) * AP_LX + tx + AP_H;
         PmlPoint pt[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const c128* t = tile[c];
-          pt[c].ctr = t[lc];
-          c128 sxx = sc.c2x[0] * pt[c].ctr, syy = sc.c2x[0] * pt[c].ctr, sx1 = mk(0.0, 0.0), sy1 = mk(0.0, 0.0);
-#pragma unroll
-          for (int mm = 1; mm <= 6; ++mm) {
-            const c128 xp = t[lc + mm], xm = t[lc - mm], yp = t[lc + mm * AP_LX], ym = t[lc - mm * AP_LX];
-            sxx = sxx + sc.c2x[mm] * (xp + xm);
-            sx1 = sx1 + sc.d1x[mm - 1] * (xp - xm);
-            syy = syy + sc.c2x[mm] * (yp + ym);
-            sy1 = sy1 + sc.d1x[mm - 1] * (yp - ym);
-          }
-          pt[c].lap = (a2[j] * sxx - a1[j] * sx1) + (a2[i] * syy - a1[i] * sy1);
-          pt[c].dx = sx1;
-          pt[c].dy = sy1;
-        }
+        for (int c = 0; c < NC; ++c) pt[c] = pml_point_tile(tile[c], lc, i, j, a2, a1, sc);
         c128 az[NC];
         pml_combine<NC>(pt, coef, idx, fsz, bk, az);
 #pragma unroll
@@ -584,7 +578,9 @@ void launch_pml_gemm(int variant, bool left, int epilogue, const c128* mat, PmlR
 #undef G_
 }
 
-int pml_apply_parts(int N) { return (N / AP_X) * (N / AP_Y) * 4; }
+int pml_tiles(int N) { return (N / AP_X) * (N / AP_Y); }
+
+int pml_apply_parts(int N) { return pml_tiles(N) * 4; }
 
 void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, size_t psp, c128* const* uptr,
                       const double* coef, const c128* a2, const c128* a1, const StencilCoef& sc, const PoleState* st,
@@ -603,6 +599,7 @@ void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, si
                          double* part, size_t pbs, int nblk, int N, int ncomp, hipStream_t s) {
   ShiftList sh;
   for (int a = 0; a < HP_MAXPOLES; ++a) sh.b[a] = a < n ? shifts[a] : mk(0.0, 0.0);
+  if (nblk != pml_tiles(N)) return;  // the caller's partial sums must match the tiles
   if (ncomp == 2)
     hipLaunchKernelGGL(k_pml_residual<2>, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, coef, a2, a1, sc,
                        sh, part, pbs, N);
