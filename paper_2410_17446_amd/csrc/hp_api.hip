@@ -515,8 +515,9 @@ int check_poles(hp_plan p, const std::vector<int>& chk, const c128* w, int beta_
       for (int a = 0; a < n; ++a)
         HPCHK(hipMemcpyAsync(p->guess_x + (size_t)a * fn, p->X + (size_t)chk[a] * fn, fn * sizeof(c128),
                              hipMemcpyDeviceToDevice, p->stream));
-      launch_pml_residual(p->guess_x, fn, w, p->guess_r, fn, p->coef, p->pml_a2, p->pml_a1, p->sc, shifts.data(), n,
-                          p->guess_part, p->nopblk, p->nopblk, p->d.nx, p->d.ncomp, p->stream);
+      if (!launch_pml_residual(p->guess_x, fn, w, p->guess_r, fn, p->coef, p->pml_a2, p->pml_a1, p->sc,
+                               shifts.data(), n, p->guess_part, p->nopblk, p->nopblk, p->d.nx, p->d.ncomp, p->stream))
+        return fail(p, HP_EINVAL, "absorbing-layer residual: the grid does not tile by 64 x 16");
     } else {
       launch_row_inv_batch<double>(p->X, fn, chk.data(), n, p->guess_x, fn, p->tw64_x, p->geo, tile_width<T>(),
                                    p->stream);
@@ -1741,10 +1742,12 @@ int hp_apply_operator(hp_plan p, int pole, const void* x, void* y) {
   if (pole >= p->d.npoles) return fail(p, HP_EINVAL, "pole out of range");
   if (!p->medium_set) return fail(p, HP_ESTATE, "no medium set");
   const c128 b = pole < 0 ? mk(0.0, 0.0) : mk(p->poles[pole].re, p->poles[pole].im);
-  if (p->pml)
-    launch_pml_residual(reinterpret_cast<const c128*>(x), 0, nullptr, reinterpret_cast<c128*>(y), 0, p->coef,
-                        p->pml_a2, p->pml_a1, p->sc, &b, 1, nullptr, 0, p->nopblk, p->d.nx, p->d.ncomp, p->stream);
-  else
+  if (p->pml) {
+    if (!launch_pml_residual(reinterpret_cast<const c128*>(x), 0, nullptr, reinterpret_cast<c128*>(y), 0, p->coef,
+                             p->pml_a2, p->pml_a1, p->sc, &b, 1, nullptr, 0, p->nopblk, p->d.nx, p->d.ncomp,
+                             p->stream))
+      return fail(p, HP_EINVAL, "absorbing-layer operator: the grid does not tile by 64 x 16");
+  } else
     launch_apply_op(reinterpret_cast<const c128*>(x), nullptr, reinterpret_cast<c128*>(y), p->coef, b, p->sc, p->geo,
                     nullptr, p->stream);
   HPCHK(hipGetLastError());

@@ -594,18 +594,19 @@ void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, si
                        uptr, coef, a2, a1, sc, st, active, part, nparts, N);
 }
 
-void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
+bool launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
                          const c128* a2, const c128* a1, const StencilCoef& sc, const c128* shifts, int n,
                          double* part, size_t pbs, int nblk, int N, int ncomp, hipStream_t s) {
   ShiftList sh;
   for (int a = 0; a < HP_MAXPOLES; ++a) sh.b[a] = a < n ? shifts[a] : mk(0.0, 0.0);
-  if (nblk != pml_tiles(N)) return;  // the caller's partial sums must match the tiles
+  if (nblk != pml_tiles(N) || N % AP_X) return false;  // the caller's partial sums must match the tiles
   if (ncomp == 2)
     hipLaunchKernelGGL(k_pml_residual<2>, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, coef, a2, a1, sc,
                        sh, part, pbs, N);
   else
     hipLaunchKernelGGL(k_pml_residual<1>, dim3(nblk, 1, n), dim3(256), 0, s, x, xbs, rhs, y, ybs, coef, a2, a1, sc,
                        sh, part, pbs, N);
+  return true;
 }
 
 void launch_pml_copy(const c128* src, size_t sbs, const int* isel, c128* dst, size_t dbs, const int* osel, int n,

@@ -66,9 +66,9 @@ void launch_pml_apply(const c128* zbase, size_t zsp, size_t zsi, c128* pbase, si
 // y = rhs - (Zbar~ - b I) x (rhs NULL: y = (Zbar~ - b I) x) with the stretched
 // stencils, for n fields (field z at x + z xbs, y + z ybs, shift shifts[z], host
 // array); partial |y|^2 of each of the nblk = pml_tiles(N) 64 x 16 tiles per
-// field at part + z pbs (nothing is launched for another nblk).
+// field at part + z pbs; false (nothing launched) for another nblk.
 int pml_tiles(int N);
-void launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
+bool launch_pml_residual(const c128* x, size_t xbs, const c128* rhs, c128* y, size_t ybs, const double* coef,
                          const c128* a2, const c128* a1, const StencilCoef& sc, const c128* shifts, int n,
                          double* part, size_t pbs, int nblk, int N, int ncomp, hipStream_t s);
 
