@@ -363,6 +363,31 @@ __device__ __forceinline__ void load_pre_row(cx<C>* buf, const cx<T>* __restrict
   }
 }
 
+// The same value, which the compiler must take as new: the LDS addresses of a
+// transform derive from the thread index alone, and without this the
+// compiler keeps those of every transform in a kernel live from the first to
+// the last (registers the vector row pass cannot spare).
+__device__ __forceinline__ int fresh(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// D1x at point j of a row held (unscaled) in the transform buffer b: the
+// 13-point first-difference stencil, with the odd reflection about points 0
+// and N taken only where the caller says the stencil may reach them.
+template <typename C, int N, bool INTERIOR>
+__device__ __forceinline__ cx<C> row_d1x(const cx<C>* b, int j, const StencilCoef& sc) {
+  cx<C> acc = czero<C>();
+#pragma unroll
+  for (int mm = 1; mm <= 6; ++mm) {
+    if constexpr (INTERIOR)
+      acc = acc + (C)sc.d1x[mm - 1] * (b[pidx<C>(j + mm)] - b[pidx<C>(j - mm)]);
+    else
+      acc = acc + (C)sc.d1x[mm - 1] * (odd_at(b, N, j + mm) - odd_at(b, N, j - mm));
+  }
+  return acc;
+}
+
 template <int N, int NC>
 struct ApplyCfg {
   static constexpr int NT = N / 8;
@@ -372,17 +397,19 @@ struct ApplyCfg {
   static constexpr int WG = GROUPS * NT;
   static constexpr int WAVES = (WG + 63) / 64;
   static constexpr int SCR = ScanScratch<NT>::SIZE;
+  static_assert(NT >= 8, "the stencil's interior points assume at least 8 threads per row");
 };
 
-// Waves per SIMD the register allocation must allow, the most that compile
-// without spilling: scalar fields four (128 VGPRs; 12 bytes spill at n = 128)
-// for 2^k up to 1024, else three (complex128 at 2048: two); vector fields: two
-// complex128, three complex64, and four at 2048, where a workgroup is 512 threads
-// and only four waves per SIMD fit two of them per CU (a 48-byte spill).
+// Waves per SIMD the register allocation must allow: scalar fields four (128
+// VGPRs; 12 bytes spill at n = 128) for 2^k up to 1024, else three (complex128
+// at 2048: two); vector fields four, which lets two 512-thread workgroups share
+// a CU at 2048 (their LDS, one buffer per component, fits twice).  Complex128
+// vector rows then spill about 45 registers: measured, that costs less than
+// the second workgroup gains (2048^2, FP64: 6.4 against 7.7 ms per launch).
 template <typename C, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
-  static constexpr int V = NC == 2 ? (sizeof(C) == 4 ? (N >= 2048 ? 4 : 3) : 2)
+  static constexpr int V = NC == 2 ? 4
                                    : ((N <= 1024 && POW2) ? 4 : (sizeof(C) == 4 || N < 2048 ? 3 : 2));
 };
 
@@ -390,19 +417,27 @@ template <typename T, typename C, int N, int NC>
 __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) void k_row_apply(
     const cx<T>* __restrict__ zbase, size_t zsp, size_t zsi, const cx<T>* __restrict__ dzbase, size_t dzsp,
     cx<T>* __restrict__ pbase, size_t psp, const cx<T>* const* __restrict__ uptr, const C* __restrict__ coef,
-    const PoleState* __restrict__ st, const int* __restrict__ active, double2* __restrict__ part, int nparts,
-    const cx<C>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
+    const PoleState* __restrict__ st, const int* __restrict__ active, int nactive, int nrb, double2* __restrict__ part,
+    int nparts, const cx<C>* __restrict__ tw, int ny, size_t fsz, StencilCoef sc) {
   using AC = ApplyCfg<N, NC>;
   constexpr int NT = AC::NT, GROUPS = AC::GROUPS, ROWS = AC::ROWS, TW = Tile<T>::W;
   constexpr int PT = N / NT;  // values per thread per row
   constexpr int PL = plen<C>(N);
-  __shared__ cx<C> lds[GROUPS * PL * NC];
+  __shared__ cx<C> lds[GROUPS * PL];
   __shared__ cx<C> scr[GROUPS * AC::SCR];
   const int g = threadIdx.x / NT, t = threadIdx.x % NT;
   const int comp = g % NC;
-  const int row = 1 + blockIdx.x * ROWS + g / NC;
+  // XCD-aware order (workgroups go round-robin to the eight XCDs): the
+  // workgroups of one XCD take its row blocks in turn with every pole's
+  // workgroup for a block next to the others, so the block's medium
+  // coefficients (and, in a first cycle, the shared basis vector) come from
+  // that XCD's L2 for all but the first pole
+  const int xcd = blockIdx.x % 8, q = blockIdx.x / 8;
+  const int rb = (q / nactive) * 8 + xcd;
+  if (rb >= nrb) return;
+  const int row = 1 + rb * ROWS + g / NC;
   const bool valid = row < ny;
-  const int k = active[blockIdx.y];
+  const int k = active[q % nactive];
   if (st[k].flag) return;
   const int m = st[k].m;
   cx<C>* buf = lds + g * PL;
@@ -439,20 +474,35 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
       return (valid ? coef[ci0 + p] : (C)0) * (scale * X);
     });
   } else {
-    // both loads fused with their transforms' pre-processing, as for scalar fields
-    const size_t rbase = cbase + tix<TW>(valid ? row : 0, 0, ny);
-    load_pre_row<T, C, N, NT, TW>(buf, z, toff, rbase, ny, valid, t, at, tw + N);
-    __syncthreads();
-    dst1_core<C, N>(buf, tw, sg, t);
     // eq. Z_bar_eq, medium part (coefficient planes carry s = 1/(k0 n0)^2):
     //   (P w)_1 = psi_xx w1 + psi_x D1x w1 + psi_xy w2 + psi_y D1x w2 + V w1
     //   (P w)_2 = psi_xy w1 + psi_x D1y w1 + psi_yy w2 + psi_y D1y w2 + V w2
-    // Component 0 needs w2 and D1x w2 from its partner, component 1 needs w1
-    // and D1y w1; each group reads the partner's transform buffer directly, so
-    // only P z stays in registers.  D1x w2 goes through the exchange buffer.
-    cx<C>* xb = lds + (GROUPS + g) * PL;
+    // A workgroup holds one transform buffer per component (two workgroups fit
+    // a CU) and no partial product stays in registers across a transform: the
+    // D1y rows (the column pass's second output) are transformed first, and
+    // the D1y part of (P w)_2 waits in the component's own output row of p (in
+    // the storage precision), which the final store overwrites.  Each group reads its partner's buffer
+    // directly; component 0 takes both x-derivatives itself.  Both loads are
+    // fused with their transforms' pre-processing, as for scalar fields.
+    const size_t rbase = cbase + tix<TW>(valid ? row : 0, 0, ny);
     const cx<C>* ob = lds + (g ^ 1) * PL;
-    const cx<C>* oxb = lds + (GROUPS + (g ^ 1)) * PL;
+    cx<T>* pk = pbase + k * psp;
+    load_pre_row<T, C, N, NT, TW>(buf, dzbase + k * dzsp, toff, rbase, ny, valid, t, at, tw + N);
+    __syncthreads();
+    dst1_core<C, N>(buf, tw, sg, fresh(t));
+    if (comp == 1 && valid) {
+#pragma unroll
+      for (int s = 0; s < PT; ++s) {
+        const int j = t + s * NT;
+        if (j == 0) continue;
+        const size_t ci = ci0 + j;
+        pk[toff.at(s)] = cvt<T>(coef[2 * fsz + ci] * (scale * buf[at(s)]) + coef[fsz + ci] * (scale * ob[at(s)]));
+      }
+    }
+    __syncthreads();
+    load_pre_row<T, C, N, NT, TW>(buf, z, toff, rbase, ny, valid, t, at, tw + N);
+    __syncthreads();
+    dst1_core<C, N>(buf, tw, sg, fresh(t));
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
@@ -460,39 +510,19 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
       if (!valid || j == 0) continue;
       const size_t ci = ci0 + j;
       const cx<C> zc = scale * buf[at(s)], zo = scale * ob[at(s)];
-      cx<C> acc = czero<C>();
-#pragma unroll
-      for (int mm = 1; mm <= 6; ++mm) acc = acc + (C)sc.d1x[mm - 1] * (odd_at(buf, N, j + mm) - odd_at(buf, N, j - mm));
-      const cx<C> dx = scale * acc;
       const C v = coef[ci], pxy = coef[5 * fsz + ci];
       if (comp == 0) {
-        pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * dx + pxy * zo;
+        // the thread's middle points never reach the reflections at 0 and N
+        const bool inner = s > 0 && s < PT - 1;
+        const cx<C> dxc = inner ? row_d1x<C, N, true>(buf, j, sc) : row_d1x<C, N, false>(buf, j, sc);
+        const cx<C> dxo = inner ? row_d1x<C, N, true>(ob, j, sc) : row_d1x<C, N, false>(ob, j, sc);
+        pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * (scale * dxc) + pxy * zo +
+                coef[2 * fsz + ci] * (scale * dxo);
       } else {
-        pz[s] = (coef[4 * fsz + ci] + v) * zc + pxy * zo;
-        xb[at(s)] = dx;
+        pz[s] = (coef[4 * fsz + ci] + v) * zc + pxy * zo + cvt<C>(pk[toff.at(s)]);
       }
-    }
-    __syncthreads();
-    if (comp == 0 && valid) {
-#pragma unroll
-      for (int s = 0; s < PT; ++s) {
-        const int j = t + s * NT;
-        if (j > 0) pz[s] = pz[s] + coef[2 * fsz + ci0 + j] * oxb[at(s)];
-      }
-    }
-    // D1y of both components (the column pass's second output), row-transformed
-    const cx<T>* dz = dzbase + k * dzsp;
-    load_pre_row<T, C, N, NT, TW>(buf, dz, toff, rbase, ny, valid, t, at, tw + N);
-    __syncthreads();
-    dst1_core<C, N>(buf, tw, sg, t);
-    if (comp == 1 && valid) {
-#pragma unroll
-      for (int s = 0; s < PT; ++s) {
-        const int j = t + s * NT;
-        if (j == 0) continue;
-        const size_t ci = ci0 + j;
-        pz[s] = pz[s] + coef[2 * fsz + ci] * scale * buf[at(s)] + coef[fsz + ci] * scale * ob[at(s)];
-      }
+      // one point at a time: hoisting every point's loads would spill
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
@@ -505,14 +535,20 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     }
     __syncthreads();
   }
-  dst1<C, N>(buf, tw, sg, t);
-  cx<T> pv[PT];  // p as stored: the inner products use exactly what the update reads
+  dst1<C, N>(buf, tw, sg, NC == 1 ? t : fresh(t));
+  // p as stored: the inner products use exactly what the update reads (vector
+  // fields re-read it from LDS in each product, to keep fewer values live)
+  auto pval = [&](int s) {
+    const int j = t + s * NT;
+    return (j == 0 || !valid) ? czero<T>() : cvt<T>(scale * buf[at(s)]);
+  };
+  cx<T> pv[NC == 1 ? PT : 1];
   cx<T>* p = pbase + k * psp;
 #pragma unroll
   for (int s = 0; s < PT; ++s) {
-    const int j = t + s * NT;
-    pv[s] = (j == 0 || !valid) ? czero<T>() : cvt<T>(scale * buf[at(s)]);
-    if (valid) p[toff.at(s)] = pv[s];
+    const cx<T> ps = pval(s);
+    if constexpr (NC == 1) pv[s] = ps;
+    if (valid) p[toff.at(s)] = ps;
   }
   // <u_i, p> and <u_i, u_m>, i = 0..m: the new direction's projections and
   // the reorthogonalisation of the provisional u_m, from the same reads of the
@@ -524,7 +560,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     for (int s = 0; s < PT; ++s) um[s] = valid ? u[toff.at(s)] : czero<T>();
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int slot = blockIdx.x * AC::WAVES + wave;
+  const int slot = rb * AC::WAVES + wave;
   for (int i = 0; i <= m; ++i) {
     const cx<T>* u = uptr[k * (HP_MAXM + 1) + i];
     double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
@@ -532,7 +568,7 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
 #pragma unroll
       for (int s = 0; s < PT; ++s) {
         const cx<double> a = cvt<double>(i == m ? um[s] : u[toff.at(s)]);
-        const cx<double> bp = cvt<double>(pv[s]);
+        const cx<double> bp = cvt<double>(NC == 1 ? pv[s] : pval(s));
         const cx<double> bq = cvt<double>(um[s]);
         pr += a.re * bp.re + a.im * bp.im;
         pi += a.re * bp.im - a.im * bp.re;
@@ -1410,14 +1446,15 @@ void launch_row_apply(const cx<T>* zbase, size_t zsp, size_t zsi, const cx<T>* d
                       const StencilCoef& sc, hipStream_t s) {
   const int nblk = row_apply_blocks<T>(g);
   const int nparts = row_apply_parts<T>(g);
-  dim3 grid(nblk, nactive);
+  // one workgroup per (row block, pole), row blocks padded to a multiple of 8
+  dim3 grid((unsigned)((nblk + 7) / 8 * 8) * (unsigned)nactive);
 #define L_(NN)                                                                                                  \
   if (g.ncomp == 1)                                                                                             \
     hipLaunchKernelGGL((k_row_apply<T, C, NN, 1>), grid, dim3(ApplyCfg<NN, 1>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
-                       dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);            \
+                       dzsp, pbase, psp, uptr, coef, st, active, nactive, nblk, part, nparts, tw, g.ny, g.fsz, sc);  \
   else                                                                                                          \
     hipLaunchKernelGGL((k_row_apply<T, C, NN, 2>), grid, dim3(ApplyCfg<NN, 2>::WG), 0, s, zbase, zsp, zsi, dzbase,  \
-                       dzsp, pbase, psp, uptr, coef, st, active, part, nparts, tw, g.ny, g.fsz, sc);
+                       dzsp, pbase, psp, uptr, coef, st, active, nactive, nblk, part, nparts, tw, g.ny, g.fsz, sc);
   HP_DISPATCH_N(g.nx, L_)
 #undef L_
 }
