@@ -403,9 +403,7 @@ struct ApplyCfg {
 // Waves per SIMD the register allocation must allow: scalar fields four (128
 // VGPRs; 12 bytes spill at n = 128) for 2^k up to 1024, else three (complex128
 // at 2048: two); vector fields four, which lets two 512-thread workgroups share
-// a CU at 2048 (their LDS, one buffer per component, fits twice).  Complex128
-// vector rows then spill about 45 registers: measured, that costs less than
-// the second workgroup gains (2048^2, FP64: 6.4 against 7.7 ms per launch).
+// a CU at 2048 (their LDS, one buffer per component, fits twice).
 template <typename C, int N, int NC>
 struct ApplyWaves {
   static constexpr bool POW2 = (N & (N - 1)) == 0;
@@ -481,9 +479,10 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     // a CU) and no partial product stays in registers across a transform: the
     // D1y rows (the column pass's second output) are transformed first, and
     // the D1y part of (P w)_2 waits in the component's own output row of p (in
-    // the storage precision), which the final store overwrites.  Each group reads its partner's buffer
-    // directly; component 0 takes both x-derivatives itself.  Both loads are
-    // fused with their transforms' pre-processing, as for scalar fields.
+    // the storage precision), which the final store overwrites.  Each group
+    // reads its partner's buffer directly, and each takes one x-derivative
+    // stencil.  Both loads are fused with their transforms' pre-processing, as
+    // for scalar fields.
     const size_t rbase = cbase + tix<TW>(valid ? row : 0, 0, ny);
     const cx<C>* ob = lds + (g ^ 1) * PL;
     cx<T>* pk = pbase + k * psp;
@@ -503,6 +502,23 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
     load_pre_row<T, C, N, NT, TW>(buf, z, toff, rbase, ny, valid, t, at, tw + N);
     __syncthreads();
     dst1_core<C, N>(buf, tw, sg, fresh(t));
+    // component 1 takes psi_y D1x w2 of component 0's product from its own
+    // buffer and leaves it (storage precision) in component 0's output row of
+    // p, where component 0 picks it up after the barrier
+    cx<T>* pk0 = pk - cbase;  // component 0's rows of p
+    if (comp == 1 && valid) {
+#pragma unroll
+      for (int s = 0; s < PT; ++s) {
+        const int j = t + s * NT;
+        if (j == 0) continue;
+        // the thread's middle points never reach the reflections at 0 and N
+        const bool inner = s > 0 && s < PT - 1;
+        const cx<C> dx = inner ? row_d1x<C, N, true>(buf, j, sc) : row_d1x<C, N, false>(buf, j, sc);
+        pk0[toff.at(s)] = cvt<T>(coef[2 * fsz + ci0 + j] * (scale * dx));
+        // one point at a time: hoisting every point's loads would spill
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
 #pragma unroll
     for (int s = 0; s < PT; ++s) {
       const int j = t + s * NT;
@@ -512,19 +528,20 @@ __global__ __launch_bounds__((ApplyCfg<N, NC>::WG), (ApplyWaves<C, N, NC>::V)) v
       const cx<C> zc = scale * buf[at(s)], zo = scale * ob[at(s)];
       const C v = coef[ci], pxy = coef[5 * fsz + ci];
       if (comp == 0) {
-        // the thread's middle points never reach the reflections at 0 and N
         const bool inner = s > 0 && s < PT - 1;
-        const cx<C> dxc = inner ? row_d1x<C, N, true>(buf, j, sc) : row_d1x<C, N, false>(buf, j, sc);
-        const cx<C> dxo = inner ? row_d1x<C, N, true>(ob, j, sc) : row_d1x<C, N, false>(ob, j, sc);
-        pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * (scale * dxc) + pxy * zo +
-                coef[2 * fsz + ci] * (scale * dxo);
+        const cx<C> dx = inner ? row_d1x<C, N, true>(buf, j, sc) : row_d1x<C, N, false>(buf, j, sc);
+        pz[s] = (coef[3 * fsz + ci] + v) * zc + coef[fsz + ci] * (scale * dx) + pxy * zo;
       } else {
         pz[s] = (coef[4 * fsz + ci] + v) * zc + pxy * zo + cvt<C>(pk[toff.at(s)]);
       }
-      // one point at a time: hoisting every point's loads would spill
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
+    if (comp == 0 && valid) {
+#pragma unroll
+      for (int s = 0; s < PT; ++s)
+        if (t + s * NT > 0) pz[s] = pz[s] + cvt<C>(pk0[toff.at(s)]);
+    }
   }
   // forward transform of P z (already in buf for scalar fields)
   if constexpr (NC == 2) {
