@@ -196,6 +196,41 @@ def test_non_square_grid():
     assert max(rr) <= 1e-10
 
 
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_non_square_grid_commutes_with_transposition(ncomp):
+    """A non-square grid against its transpose: with dx = dy and the same stencils on both axes the
+    operator of eq. Z_bar_eq is unchanged by x <-> y (vector fields: with E_x <-> E_y), so stepping
+    the transposed field and medium must give the transposed step.  The two plans route every row
+    through the other's column pass and back (different row blocks, tiles and ragged ends), so an
+    index slip in either pass breaks the symmetry; iterations are replayed so both take the same
+    Krylov spaces."""
+    torch = _cuda()
+    wl = workload(N=64, ny=128, W=8, ncomp=ncomp, tol=1e-9, restart=60)
+    if ncomp == 2:
+        wl["w"][1] = 0.4j * np.roll(wl["w"][0], 3, axis=1)
+        wl["w"][1][:, 0] = 0
+        wl["w"][1][0, :] = 0
+    a = gpu_plan(wl)
+    a.step(to_gpu(wl["w"]), to_gpu(wl["n2"]))
+    counts, _ = a.stats()
+    # one cycle of the same length on both sides (the symmetry holds for any length; the solves'
+    # own lengths, capped at the restart length, keep it a converged step)
+    counts = [min(c, 60) for c in counts]
+    a.set_fixed_iters(counts)
+    out_a = a.step(to_gpu(wl["w"]), to_gpu(wl["n2"])).cpu().numpy()
+    wt = dict(wl, nx=128, ny=64, n2=np.ascontiguousarray(wl["n2"].T),
+              w=np.ascontiguousarray(np.transpose(wl["w"], (0, 2, 1))[::-1] if ncomp == 2
+                                     else np.transpose(wl["w"], (0, 2, 1))))
+    b = gpu_plan(wt)
+    b.set_fixed_iters(counts)
+    out_b = b.step(to_gpu(wt["w"]), to_gpu(wt["n2"])).cpu().numpy()
+    back = np.transpose(out_b, (0, 2, 1))
+    if ncomp == 2:
+        back = back[::-1]
+    assert out_a.shape == (ncomp, 128, 64) and back.shape == out_a.shape
+    assert rel_l2(back, out_a) < 1e-11
+
+
 def test_batch_equals_single_plans():
     """Concurrent batch (uneven sizes, pole counts, media) gives the same fields as one plan at a time."""
     torch = _cuda()
