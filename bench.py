@@ -86,7 +86,9 @@ def parse():
     ap.add_argument("--train-n", type=int, default=256, help="training grid (learned workload)")
     ap.add_argument("--learned-workload", default="scalar1024", choices=["scalar1024", "vector2048"],
                     help="workload the learned guesses are timed on")
-    ap.add_argument("--learned-chunk", type=int, default=8, help="poles per U-Net forward pass (learned)")
+    ap.add_argument("--learned-chunk", type=int, default=None,
+                    help="poles per U-Net forward pass (learned; default 8, and 4 for vector2048, whose 206 GB "
+                         "workspace leaves room for the activations of 4)")
     ap.add_argument("--train-draws", type=int, default=48, help="(medium, beam) draws for training")
     ap.add_argument("--train-seconds", type=float, default=90.0, help="training time budget")
     ap.add_argument("--event-period", type=int, default=EVENT_PERIOD,
@@ -213,6 +215,8 @@ def run_learned(args):
     from paper_2410_17446_amd.unet import HP_UNET_BF16, HP_UNET_F32, UNet
     cfg = dict(inputs.CONFIGS[args.learned_workload])
     nc = cfg["ncomp"]
+    if args.learned_chunk is None:
+        args.learned_chunk = 4 if args.learned_workload == "vector2048" else 8
     cin, cout = 4 * nc + 3, 2 * nc
     poles, residues, r_inf, d2, d1 = tables.plan_tables(inputs.K0 * cfg["dz"], cfg["npoles"])
     fit = dict(poles=poles, residues=residues, r_inf=r_inf)
