@@ -454,6 +454,18 @@ def hp_k0():
     return inputs.K0
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, npoles_sample, sqrt_form=False, one_core_poles=2):
     """Oracle on a bounded sample: `npoles_sample` pole solves of step 1 (of its first RK stage for the
     pseudo-differential form), scaled to steps/s."""
@@ -489,7 +501,7 @@ def cpu_baseline(cfg, npoles_sample, sqrt_form=False, one_core_poles=2):
     step_s = dt * cfg["npoles"] * solves_per_pole / k
     where = "the first RK stage of step 1" if sqrt_form else "step 1"
     scale = f"{cfg['npoles']} x {solves_per_pole}/{k}" if sqrt_form else f"{cfg['npoles']}/{k}"
-    out = dict(value=1.0 / step_s, unit="steps/s", cores=threads, kind="oracle",
+    out = dict(value=1.0 / step_s, unit="steps/s", cores=threads, kind="oracle", cpu=cpu_model(),
                sample=f"GMRES solves of poles {picks} (of {cfg['npoles']}) in {where} of the {cfg['N']}^2 "
                       f"workload ({dt:.1f} s, iterations {iters}); per-step time = sample time x "
                       f"{scale}; scipy.fft uses {threads} threads, the rest of numpy one")
@@ -667,7 +679,7 @@ def cpu_baseline_pml(cfg, tab, w, n2):
     else:
         r = pml.solve_pole(g, pml.medium(g, n2), w[0], poles[j], cfg["tol"], cfg["restart"])
     dt = time.perf_counter() - t0
-    return dict(value=1.0 / (dt * cfg["npoles"]), unit="steps/s", cores=threads, kind="oracle",
+    return dict(value=1.0 / (dt * cfg["npoles"]), unit="steps/s", cores=threads, kind="oracle", cpu=cpu_model(),
                 sample=f"GMRES solve of pole {j} (of {cfg['npoles']}) in step 1 of the {cfg['N']}^2 PML workload "
                        f"({dt:.1f} s, {r.iters} iterations); per-step time = sample time x {cfg['npoles']}; "
                        f"numpy/scipy BLAS and LAPACK threads as the box sets them")
